@@ -1,0 +1,243 @@
+/*
+ * mcheis.h -- C ABI of the MI355X Metropolis library for the classical
+ * anisotropic Heisenberg model.
+ *
+ * Model (Charilaou, arXiv:2106.11286, Eq. (1)):
+ *     H = -J sum_<ij> S_i . S_j  -  K sum_i (S_i . e)^2
+ * with unit three-component spins, nearest-neighbour bonds counted once, and a
+ * uniaxial easy axis e.  Dynamics: single-spin Metropolis (the paper's Monte
+ * Carlo paragraph): propose a new orientation uniformly on the sphere, accept
+ * if dH <= 0 or if P <= exp(-dH/T) for a uniform P in (0,1).  Magnetisation:
+ * Eq. (2), M = sum_i S_i / (N |S|), here with |S| = 1.
+ *
+ * Sites are updated by sublattice colour: every site of one colour in one
+ * parallel pass (no bond joins two sites of one colour), colours 0..C-1 in
+ * order; one sweep = C passes = one attempted move per occupied site.
+ * C = 2 for simple cubic (sc) and body-centred cubic (bcc), 4 for
+ * face-centred cubic (fcc).
+ *
+ * Random numbers: Philox4x32-10 with key (seed lo32, seed hi32) and counter
+ * (s, replica_id, t, tag), where s is the canonical site index
+ * s = ((z*Ly + y)*Lx + x)*n_basis + b, t the replica's sweep counter, tag 0 for
+ * moves and 1 for the random initial state.  Word 0 gives z = 2u-1, word 1 the
+ * azimuth 2 pi u, word 2 the acceptance number P, with u = (k + 1/2) 2^-23 from
+ * the top 23 bits.  Results therefore depend only on (seed, replica_id, t, s),
+ * never on tiling, batching or thread order.
+ *
+ * Conventions for every function:
+ *  - the return value is an mc_status; nothing throws, aborts or exits;
+ *  - on error a thread-local message is available from mc_last_error();
+ *  - device pointers are HIP device memory on the current device, owned by
+ *    the caller, and must outlive the handle; the library never frees them;
+ *  - a handle is not thread-safe; calls on one handle must not overlap.
+ */
+#ifndef MCHEIS_H
+#define MCHEIS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MC_OK = 0,
+    MC_E_ARG = -1,         /* invalid argument value or NULL out-pointer          */
+    MC_E_UNSUPPORTED = -2, /* valid model the library cannot colour / lay out     */
+    MC_E_BUFFER = -3,      /* NULL, too small, misaligned or host buffer           */
+    MC_E_DEVICE = -4,      /* no device, or a HIP error (message has the reason)   */
+    MC_E_STATE = -5        /* call not valid in the handle's current state         */
+} mc_status;
+
+typedef enum { MC_SC = 0, MC_BCC = 1, MC_FCC = 2 } mc_lattice_kind;
+typedef enum { MC_F32 = 0, MC_F64 = 1 } mc_precision;
+typedef enum { MC_INIT_RANDOM = 0, MC_INIT_ALIGNED = 1, MC_INIT_USER = 2 } mc_init_mode;
+
+/* mc_sweep flags */
+#define MC_MEASURE 1u /* reduce observables on every sweep of this call */
+
+/* One replica: lattice geometry and model parameters (Eq. (1)).
+ *  kind          sc / bcc / fcc conventional cubic cells.
+ *  Lx, Ly, Lz    cells per axis (>= 1).  sc needs Lx even (colour packing) and
+ *                an even length on every periodic axis (2-colouring).
+ *  periodic_mask bit0 x, bit1 y, bit2 z: periodic axes; open faces drop bonds.
+ *  sphere_radius <= 0: every site of the box is occupied.  > 0: a site at
+ *                position r (cells) is occupied iff |r - (Lx,Ly,Lz)/2| <= R.
+ *                Unoccupied sites hold S = 0, are never updated and have no
+ *                bonds.
+ *  J, K          exchange and anisotropy (units of energy, k_B = 1).
+ *  e             easy axis, normalised by the library (must be nonzero).
+ *  T             temperature: 0 = greedy (accept iff dH <= 0), +inf = every
+ *                move accepted; must not be negative or NaN.
+ *  replica_id    counter word 1 of the random stream. */
+typedef struct {
+    int32_t kind;
+    int32_t Lx, Ly, Lz;
+    uint32_t periodic_mask;
+    uint32_t replica_id;
+    double sphere_radius;
+    double J, K, e[3];
+    double T;
+} mc_replica_desc;
+
+/* Spin storage of one replica: three device planes (x, y, z components), each
+ * of capacity_sites elements of the precision's type (float or double).
+ * Layout (colour-major, unoccupied sites hold 0):
+ *  sc:      colour c = (x+y+z) & 1,
+ *           idx = c*(N/2) + ((z*Ly + y)*Lx + x) / 2,  N = Lx*Ly*Lz;
+ *  bcc/fcc: colour = basis site b,
+ *           idx = b*(Lx*Ly*Lz) + (z*Ly + y)*Lx + x.
+ * Alignment: each plane 16-byte aligned. */
+typedef struct {
+    void *sx, *sy, *sz;
+    uint64_t capacity_sites;
+} mc_spin_buffers;
+
+/* Observables of one replica after one sweep (FP64 accumulation).
+ *  sweep       sweeps completed by the replica when measured;
+ *  n_sites     occupied sites N;  n_accepted  accepted moves in that sweep;
+ *  M           magnetisation per spin, Eq. (2);  absM = |M|;
+ *  E_exch      -J sum_bonds S_i.S_j;  E_anis  -K sum_i (S_i.e)^2;
+ *  E           E_exch + E_anis (extensive, units of J). */
+typedef struct {
+    uint64_t sweep, n_sites, n_accepted;
+    double M[3];
+    double absM;
+    double E, E_exch, E_anis;
+} mc_obs;
+
+/* Temperature schedule for mc_run_schedule.  For each of n_T steps: set the
+ * temperatures T[step*n_reps + r], run n_equil unmeasured sweeps, then n_meas
+ * sweeps, recording every measure_every-th of them (measure_every >= 1).  The
+ * state is carried from one step to the next. */
+typedef struct {
+    int32_t n_T;
+    const double *T; /* host array [n_T][n_reps] */
+    uint32_t n_equil, n_meas, measure_every;
+} mc_schedule;
+
+/* Summary statistics of one replica's series (equilibrium averages over the
+ * measured sweeps, per spin; errors by Flyvbjerg-Petersen blocking). */
+typedef struct {
+    uint64_t n;
+    double abs_m, abs_m_err, m2, m2_err, m4, m4_err, e, e_err;
+    double U4;  /* Binder cumulant 1 - <m^4>/(3 <m^2>^2) */
+    double C;   /* specific heat per spin, (<E^2> - <E>^2)/(N T^2) */
+    double chi; /* susceptibility per spin, N (<m^2> - <|m|>^2)/T */
+    double acceptance;
+} mc_stats;
+
+typedef struct mc_sim mc_sim; /* opaque handle */
+
+/* Elements per spin plane that a replica needs (the box, all colours). */
+mc_status mc_required_sites(const mc_replica_desc *d, uint64_t *sites_per_component);
+
+/* Occupied sites N of a replica (sphere mask applied). */
+mc_status mc_occupied_sites(const mc_replica_desc *d, uint64_t *n_sites);
+
+/* Bytes of device scratch the handle needs for n_reps replicas (descriptors,
+ * work list, per-workgroup FP64 partial sums, observable records, counters). */
+mc_status mc_required_scratch(const mc_replica_desc *reps, int32_t n_reps, uint64_t *bytes);
+
+/* Create a handle over n_reps replicas of one lattice kind and precision, and
+ * write the initial state into the caller's buffers (unless MC_INIT_USER:
+ * then the buffers already hold the state in the layout above).
+ *  bufs[n_reps]  spin planes per replica (device memory);
+ *  scratch       device memory of at least mc_required_scratch bytes, 256-byte
+ *                aligned, owned by the caller, used only by this handle;
+ *  hip_stream    hipStream_t every call enqueues on (NULL = default stream).
+ * Random start: spin s = sphere(Philox(seed, (s, replica_id, 0, 1))).
+ * Errors: MC_E_ARG (n_reps < 1, lengths < 1, T < 0 or NaN, |e| = 0, mixed
+ * lattice kinds, NULL out), MC_E_UNSUPPORTED (sc with odd Lx or with an odd
+ * periodic length; box over 2^31 sites), MC_E_BUFFER (NULL / short /
+ * misaligned / host memory), MC_E_DEVICE. */
+mc_status mc_init_lattice(const mc_replica_desc *reps, int32_t n_reps, mc_precision prec,
+                          uint64_t seed, mc_init_mode init, const mc_spin_buffers *bufs,
+                          void *scratch, uint64_t scratch_bytes, void *hip_stream, mc_sim **out);
+
+/* Enqueue n_sweeps sweeps of every replica (colour passes 0..C-1 each, sweep
+ * counters t, t+1, ...).  With MC_MEASURE every sweep also reduces the FP64
+ * observables (fused into the passes; no extra spin traffic).  Asynchronous:
+ * returns once the work is enqueued; device faults surface at the next
+ * synchronising call. */
+mc_status mc_sweep(mc_sim *h, uint32_t n_sweeps, uint32_t flags);
+
+/* mc_sweep with HIP events recorded on the handle's stream around every
+ * colour-pass launch; synchronises and returns the mean duration of one pass
+ * launch and the total time of the call (milliseconds).  For measuring the
+ * kernels in place; results are identical to mc_sweep. */
+mc_status mc_sweep_timed(mc_sim *h, uint32_t n_sweeps, uint32_t flags, double *pass_ms_avg,
+                         double *total_ms);
+
+/* Synchronise the stream and return the observables of the most recent
+ * measured sweep of each replica (out[n_reps]).  MC_E_STATE if no sweep has
+ * been measured since the handle was created. */
+mc_status mc_observables(mc_sim *h, mc_obs *out, int32_t n_reps);
+
+/* Observables of the current state recomputed from scratch (full energy over
+ * all bonds, FP64), independent of the fused reduction.  Synchronises. */
+mc_status mc_measure_state(mc_sim *h, mc_obs *out, int32_t n_reps);
+
+/* Run a temperature schedule.  Sweeps are replayed as captured HIP graphs.
+ * series receives the records in order [step][record][replica]; capacity is
+ * its length in mc_obs elements and must be at least
+ * n_T * (n_meas / measure_every) * n_reps.  n_written (may be NULL) receives
+ * the count.  Synchronises. */
+mc_status mc_run_schedule(mc_sim *h, const mc_schedule *s, mc_obs *series, uint64_t capacity,
+                          uint64_t *n_written);
+
+/* Change the temperatures (T[n_reps], same rules as the descriptor). */
+mc_status mc_set_temperatures(mc_sim *h, const double *T, int32_t n_reps);
+
+/* One colour pass of every replica at the current sweep counter, without
+ * advancing it, writing per-site diagnostics in the spin layout of the pass
+ * colour: dH (working precision, element type of the spins) and the decision
+ * (uint8 0/1).  Sites of other colours and unoccupied sites are not written.
+ * Buffers are device memory of capacity_sites elements per replica, indexed
+ * as the spin planes (pointer arrays of n_reps entries).  For checking
+ * single-pass accuracy against a reference; not part of a sweep. */
+mc_status mc_debug_pass(mc_sim *h, int32_t colour, void *const *dh, void *const *accepted);
+
+/* Copy a replica's spins between the library layout and natural order
+ * (canonical index s, see above) on the device.  to_natural != 0: packed ->
+ * natural; 0: natural -> packed.  nx, ny, nz are device arrays of
+ * mc_required_sites elements of the precision's type. */
+mc_status mc_layout_copy(mc_sim *h, int32_t replica, int32_t to_natural, void *nx, void *ny,
+                         void *nz);
+
+/* Checkpoint / resume: the state is the spin buffers plus the sweep counter
+ * (the counter-based stream makes a resumed run bitwise identical). */
+mc_status mc_get_sweep(const mc_sim *h, uint64_t *t);
+mc_status mc_set_sweep(mc_sim *h, uint64_t t);
+
+/* Tile shape of the sweep kernels: tx x ty threads per workgroup (tx*ty <=
+ * 256) over (row column, row) and zc planes walked per thread.  The spins do
+ * not depend on it (only the FP64 summation order of observables does).  A
+ * shape whose work list does not fit the handle's scratch gives MC_E_BUFFER.
+ * Discards the record of the last measured sweep.  Synchronises. */
+mc_status mc_set_tile(mc_sim *h, int32_t tx, int32_t ty, int32_t zc);
+mc_status mc_get_tile(const mc_sim *h, int32_t *tx, int32_t *ty, int32_t *zc, uint64_t *n_items);
+
+/* Number of colours (passes per sweep) of the handle's lattice kind. */
+mc_status mc_num_colours(const mc_sim *h, int32_t *n_colours);
+
+/* Equilibrium statistics of one replica's records (stride: elements between
+ * consecutive records of that replica, e.g. n_reps for mc_run_schedule
+ * output), at temperature T (used by C and chi). */
+mc_status mc_series_stats(const mc_obs *series, uint64_t n, uint64_t stride, double T,
+                          mc_stats *out);
+
+/* Release the handle (never the caller's buffers, scratch or stream). */
+void mc_destroy(mc_sim *h);
+
+/* Message of the last error on this thread ("" if none). */
+const char *mc_last_error(void);
+
+/* Library version string. */
+const char *mc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MCHEIS_H */

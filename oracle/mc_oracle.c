@@ -166,11 +166,45 @@ void orc_lattice_free(orc_lattice *L)
     free(L);
 }
 
-/* Build the lattice by brute force: a neighbour is any site at the
- * nearest-neighbour distance, looking at all basis sites of the 27 surrounding
- * cells, wrapping periodic axes and dropping open-face and unoccupied sites.
- * Neighbours are listed in loop order (dz, dy, dx, b') ascending, which fixes
- * the summation order of the local field. */
+/* Nearest neighbours of site (x, y, z, b) by brute force: every basis site of
+ * the 27 surrounding cells at the nearest-neighbour distance, wrapping
+ * periodic axes and dropping open-face and unoccupied sites.  They are listed
+ * in loop order (dz, dy, dx, b') ascending, which fixes the summation order of
+ * the local field.  Returns the count, or -1 if it exceeds the coordination. */
+static int neighbours_of(const orc_lattice *L, int x, int y, int z, int b, int32_t *out)
+{
+    const int (*B)[3] = basis2_of(L->kind);
+    const int d2nn = nn_dist2_half(L->kind);
+    const int dims[3] = {L->Lx, L->Ly, L->Lz};
+    int cnt = 0;
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx)
+                for (int b2 = 0; b2 < L->nb; ++b2) {
+                    int ex = 2 * dx + B[b2][0] - B[b][0];
+                    int ey = 2 * dy + B[b2][1] - B[b][1];
+                    int ez = 2 * dz + B[b2][2] - B[b][2];
+                    if (ex * ex + ey * ey + ez * ez != d2nn) continue;
+                    int c[3] = {x + dx, y + dy, z + dz};
+                    int ok = 1;
+                    for (int a = 0; a < 3; ++a) {
+                        if (c[a] < 0 || c[a] >= dims[a]) {
+                            if (L->periodic_mask & (1u << a))
+                                c[a] = (c[a] + dims[a]) % dims[a];
+                            else
+                                ok = 0;
+                        }
+                    }
+                    if (!ok) continue;
+                    if (!site_occupied(L, c[0], c[1], c[2], b2)) continue;
+                    if (cnt >= L->zmax) return -1;
+                    out[cnt++] = (int32_t)orc_site_index(L, c[0], c[1], c[2], b2);
+                }
+    return cnt;
+}
+
+/* Build the lattice: site table, colours and the neighbour list of every
+ * occupied site (see neighbours_of). */
 orc_lattice *orc_lattice_new(int kind, int Lx, int Ly, int Lz, uint32_t periodic_mask,
                              double sphere_radius)
 {
@@ -190,9 +224,6 @@ orc_lattice *orc_lattice_new(int kind, int Lx, int Ly, int Lz, uint32_t periodic
     L->nbr = (int32_t *)malloc((size_t)L->n_box * L->zmax * sizeof(int32_t));
     if (!L->occ || !L->colour || !L->nnb || !L->nbr) { orc_lattice_free(L); return NULL; }
 
-    const int (*B)[3] = basis2_of(kind);
-    const int d2nn = nn_dist2_half(kind);
-    const int dims[3] = {Lx, Ly, Lz};
     int64_t n_occ = 0;
     for (int z = 0; z < Lz; ++z)
         for (int y = 0; y < Ly; ++y)
@@ -213,38 +244,35 @@ orc_lattice *orc_lattice_new(int kind, int Lx, int Ly, int Lz, uint32_t periodic
                 for (int b = 0; b < L->nb; ++b) {
                     int64_t s = orc_site_index(L, x, y, z, b);
                     if (!L->occ[s]) continue;
-                    int cnt = 0;
-                    for (int dz = -1; dz <= 1; ++dz)
-                        for (int dy = -1; dy <= 1; ++dy)
-                            for (int dx = -1; dx <= 1; ++dx)
-                                for (int b2 = 0; b2 < L->nb; ++b2) {
-                                    int ex = 2 * dx + B[b2][0] - B[b][0];
-                                    int ey = 2 * dy + B[b2][1] - B[b][1];
-                                    int ez = 2 * dz + B[b2][2] - B[b][2];
-                                    if (ex * ex + ey * ey + ez * ez != d2nn) continue;
-                                    int c[3] = {x + dx, y + dy, z + dz};
-                                    int ok = 1;
-                                    for (int a = 0; a < 3; ++a) {
-                                        if (c[a] < 0 || c[a] >= dims[a]) {
-                                            if (periodic_mask & (1u << a))
-                                                c[a] = (c[a] + dims[a]) % dims[a];
-                                            else
-                                                ok = 0;
-                                        }
-                                    }
-                                    if (!ok) continue;
-                                    int64_t j = orc_site_index(L, c[0], c[1], c[2], b2);
-                                    if (!L->occ[j]) continue;
-                                    if (cnt >= L->zmax) { orc_lattice_free(L); return NULL; }
-                                    L->nbr[s * L->zmax + cnt] = (int32_t)j;
-                                    ++cnt;
-                                    if (L->colour[j] == L->colour[s]) same = 1;
-                                }
+                    int cnt = neighbours_of(L, x, y, z, b, L->nbr + s * L->zmax);
+                    if (cnt < 0) { orc_lattice_free(L); return NULL; }
+                    for (int k = 0; k < cnt; ++k)
+                        if (L->colour[L->nbr[s * L->zmax + k]] == L->colour[s]) same = 1;
                     L->nnb[s] = (int8_t)cnt;
                     n_half_bonds += cnt;
                 }
     L->n_bonds = n_half_bonds / 2;
     L->same_colour_bonds = same;
+    return L;
+}
+
+/* Geometry only (no tables): for evaluating single sites of lattices too
+ * large to tabulate.  Free with orc_lattice_free. */
+orc_lattice *orc_geometry_new(int kind, int Lx, int Ly, int Lz, uint32_t periodic_mask,
+                              double sphere_radius)
+{
+    if (kind < 0 || kind > 2 || Lx < 1 || Ly < 1 || Lz < 1) return NULL;
+    if ((double)Lx * Ly * Lz * nbasis_of(kind) >= 2147483647.0) return NULL;
+    orc_lattice *L = (orc_lattice *)calloc(1, sizeof(orc_lattice));
+    L->kind = kind; L->Lx = Lx; L->Ly = Ly; L->Lz = Lz;
+    L->nb = nbasis_of(kind);
+    L->periodic_mask = periodic_mask;
+    L->sphere_radius = sphere_radius;
+    L->n_box = (int64_t)Lx * Ly * Lz * L->nb;
+    L->n_colours = kind == ORC_SC ? 2 : L->nb;
+    L->zmax = zmax_of(kind);
+    L->n_occ = -1;
+    L->n_bonds = -1;
     return L;
 }
 
@@ -316,16 +344,45 @@ double orc_delta_h(const double h[3], const double S[3], const double Sn[3], dou
     return dex - K * (pn * pn - po * po);
 }
 
+/* One Metropolis attempt (the three steps of the Metropolis paragraph) at
+ * canonical site s with local field h = J sum_j S_j and current spin S.
+ * Writes the proposal outcome: dH, the decision, beta*dH + ln P (accept iff
+ * <= 0 when dH > 0) and the spin after the attempt. */
+static int attempt(const orc_params *p, const double e[3], uint32_t t, uint32_t s,
+                   const double h[3], const double S[3], double *dH_out, double *margin_out,
+                   double S_after[3])
+{
+    const double beta = (p->T > 0.0) ? 1.0 / p->T : 0.0; /* T = +inf gives 0 */
+    uint32_t w[4];
+    philox_site(p->seed, s, p->replica_id, t, 0u, w);
+    double Sn[3];
+    orc_sphere_point(orc_uniform(w[0]), orc_uniform(w[1]), Sn);
+    double P = orc_uniform(w[2]);
+    double dH = orc_delta_h(h, S, Sn, p->K, e);
+    int accept;
+    if (dH <= 0.0) accept = 1;
+    else if (p->T > 0.0) accept = (P <= exp(-beta * dH));
+    else accept = 0;
+    *dH_out = dH;
+    *margin_out = beta * dH + log(P);
+    if (accept) {
+        double n = sqrt(Sn[0] * Sn[0] + Sn[1] * Sn[1] + Sn[2] * Sn[2]);
+        S_after[0] = Sn[0] / n; S_after[1] = Sn[1] / n; S_after[2] = Sn[2] / n;
+    } else {
+        S_after[0] = S[0]; S_after[1] = S[1]; S_after[2] = S[2];
+    }
+    return accept;
+}
+
 /* One colour pass at sweep t: every occupied site of colour c gets one
  * Metropolis attempt.  Optional per-site outputs (indexed by canonical site;
- * untouched elsewhere): dH, the decision, and beta*dH + ln P (the decision
- * variable: accept iff <= 0 when dH > 0).  Returns the number accepted. */
+ * untouched elsewhere): dH, the decision, and beta*dH + ln P.  Returns the
+ * number accepted. */
 int64_t orc_pass(const orc_lattice *L, const orc_params *p, int c, uint32_t t, double *sx,
                  double *sy, double *sz, double *out_dh, uint8_t *out_acc, double *out_margin)
 {
     double e[3];
     unit_axis(p->e, e);
-    const double beta = (p->T > 0.0) ? 1.0 / p->T : 0.0; /* T = +inf gives 0 */
     int64_t n_acc = 0;
 #pragma omp parallel for schedule(static) reduction(+ : n_acc)
     for (int64_t s = 0; s < L->n_box; ++s) {
@@ -336,28 +393,49 @@ int64_t orc_pass(const orc_lattice *L, const orc_params *p, int c, uint32_t t, d
             h[0] += sx[j]; h[1] += sy[j]; h[2] += sz[j];
         }
         h[0] *= p->J; h[1] *= p->J; h[2] *= p->J;
-
-        uint32_t w[4];
-        philox_site(p->seed, (uint32_t)s, p->replica_id, t, 0u, w);
-        double Sn[3];
-        orc_sphere_point(orc_uniform(w[0]), orc_uniform(w[1]), Sn);
-        double P = orc_uniform(w[2]);
-        double S[3] = {sx[s], sy[s], sz[s]};
-        double dH = orc_delta_h(h, S, Sn, p->K, e);
-        int accept;
-        if (dH <= 0.0) accept = 1;
-        else if (p->T > 0.0) accept = (P <= exp(-beta * dH));
-        else accept = 0;
+        double S[3] = {sx[s], sy[s], sz[s]}, Sa[3], dH, mg;
+        int accept = attempt(p, e, t, (uint32_t)s, h, S, &dH, &mg, Sa);
         if (out_dh) out_dh[s] = dH;
         if (out_acc) out_acc[s] = (uint8_t)accept;
-        if (out_margin) out_margin[s] = beta * dH + log(P);
+        if (out_margin) out_margin[s] = mg;
         if (accept) {
-            double n = sqrt(Sn[0] * Sn[0] + Sn[1] * Sn[1] + Sn[2] * Sn[2]);
-            sx[s] = Sn[0] / n; sy[s] = Sn[1] / n; sz[s] = Sn[2] / n;
+            sx[s] = Sa[0]; sy[s] = Sa[1]; sz[s] = Sa[2];
             n_acc += 1;
         }
     }
     return n_acc;
+}
+
+/* The attempt of one site at sweep t on a geometry without tables, for
+ * lattices too large to tabulate: neighbours by brute force (neighbours_of),
+ * spins in natural order.  out = {dH, accepted, beta*dH + ln P, S_after[3],
+ * h[3]}.  Returns 0, or -1 for an unoccupied site or an invalid index. */
+int orc_site_attempt(const orc_lattice *G, const orc_params *p, uint32_t t, const double *sx,
+                     const double *sy, const double *sz, int64_t s, double out[9])
+{
+    if (s < 0 || s >= G->n_box) return -1;
+    const int b = (int)(s % G->nb);
+    const int64_t cell = s / G->nb;
+    const int x = (int)(cell % G->Lx);
+    const int y = (int)((cell / G->Lx) % G->Ly);
+    const int z = (int)(cell / ((int64_t)G->Lx * G->Ly));
+    if (!site_occupied(G, x, y, z, b)) return -1;
+    int32_t nb[12];
+    int cnt = neighbours_of(G, x, y, z, b, nb);
+    if (cnt < 0) return -1;
+    double e[3];
+    unit_axis(p->e, e);
+    double h[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < cnt; ++k) {
+        h[0] += sx[nb[k]]; h[1] += sy[nb[k]]; h[2] += sz[nb[k]];
+    }
+    h[0] *= p->J; h[1] *= p->J; h[2] *= p->J;
+    double S[3] = {sx[s], sy[s], sz[s]}, Sa[3], dH, mg;
+    int accept = attempt(p, e, t, (uint32_t)s, h, S, &dH, &mg, Sa);
+    out[0] = dH; out[1] = accept; out[2] = mg;
+    out[3] = Sa[0]; out[4] = Sa[1]; out[5] = Sa[2];
+    out[6] = h[0]; out[7] = h[1]; out[8] = h[2];
+    return 0;
 }
 
 /* Observables of a state, from scratch, serial and in fixed order:

@@ -91,6 +91,10 @@ def lib():
             L.orc_sweep.restype = i64
             L.orc_observables.argtypes = [vp, P, vp, vp, vp, dp]
             L.orc_observables.restype = None
+            L.orc_geometry_new.argtypes = [i32, i32, i32, i32, u32, ctypes.c_double]
+            L.orc_geometry_new.restype = vp
+            L.orc_site_attempt.argtypes = [vp, P, u32, vp, vp, vp, i64, dp]
+            L.orc_site_attempt.restype = i32
             L.orc_run.argtypes = [vp, P, u32, u32, vp, vp, vp, vp]
             L.orc_run.restype = None
             L.orc_num_threads.argtypes = []
@@ -196,6 +200,39 @@ class Lattice:
 
     def new_spins(self):
         return [np.zeros(self.n_box, np.float64) for _ in range(3)]
+
+
+class Geometry:
+    """Lattice geometry without tables, for single-site evaluation of lattices
+    too large to tabulate (neighbours found by brute force per site)."""
+
+    def __init__(self, kind, Lx, Ly=None, Lz=None, periodic_mask=7, sphere_radius=0.0):
+        Ly = Lx if Ly is None else Ly
+        Lz = Lx if Lz is None else Lz
+        h = lib().orc_geometry_new(int(kind), int(Lx), int(Ly), int(Lz), int(periodic_mask),
+                                   float(sphere_radius))
+        if not h:
+            raise ValueError("oracle: invalid geometry")
+        self._h = ctypes.c_void_p(h)
+        self.n_box = int(Lx) * int(Ly) * int(Lz) * {SC: 1, BCC: 2, FCC: 4}[int(kind)]
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.orc_lattice_free(h)
+            self._h = None
+
+    def site_attempt(self, p: Params, t: int, spins, s: int):
+        """One site's attempt at sweep t from natural-order FP64 spins:
+        dict(dH, accepted, margin, S_after, h); None if s is unoccupied."""
+        out = (ctypes.c_double * 9)()
+        pc = p.c()
+        rc = lib().orc_site_attempt(self._h, ctypes.byref(pc), int(t), *[_ptr(a) for a in spins],
+                                    int(s), out)
+        if rc != 0:
+            return None
+        return {"dH": out[0], "accepted": bool(out[1]), "margin": out[2],
+                "S_after": np.array(out[3:6]), "h": np.array(out[6:9])}
 
 
 def init(lat: Lattice, p: Params, mode=INIT_RANDOM):

@@ -1,0 +1,916 @@
+// abi.cpp -- host runtime behind the C ABI (include/mcheis.h): argument and
+// buffer validation, the colouring/tiling plan, the scratch layout, sweep
+// scheduling with HIP graph replay, observable records and series statistics.
+//
+// The library allocates no spin or scratch memory: the caller owns both (in
+// practice as framework tensors) and the stream.  The only allocation it makes
+// is a small pinned host ring for observable records.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "launch.hpp"
+#include "mc_internal.hpp"
+#include "mcheis.h"
+
+using namespace mc;
+
+namespace {
+
+thread_local std::string g_err;
+
+mc_status fail(mc_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(MC_E_DEVICE, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_),     \
+                        __FILE__, __LINE__);                                             \
+    } while (0)
+
+constexpr uint32_t kRing = 256;       // observable records kept per replica
+constexpr uint32_t kTargetItems = 8192; // work items aimed for per pass
+constexpr uint32_t kGraphChunk = 64;  // sweeps per captured graph
+
+int n_basis(int kind) { return kind == SC ? 1 : (kind == BCC ? 2 : 4); }
+int n_colours_of(int kind) { return kind == SC ? 2 : n_basis(kind); }
+
+uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
+
+mc_status check_desc(const mc_replica_desc &d, int idx)
+{
+    if (d.kind < MC_SC || d.kind > MC_FCC)
+        return fail(MC_E_ARG, "replica %d: unknown lattice kind %d", idx, d.kind);
+    if (d.Lx < 1 || d.Ly < 1 || d.Lz < 1)
+        return fail(MC_E_ARG, "replica %d: lengths must be >= 1 (got %d %d %d)", idx, d.Lx,
+                    d.Ly, d.Lz);
+    if (d.periodic_mask > 7u) return fail(MC_E_ARG, "replica %d: periodic_mask > 7", idx);
+    if (!(d.T >= 0.0)) return fail(MC_E_ARG, "replica %d: T must be >= 0 (got %g)", idx, d.T);
+    if (!std::isfinite(d.J) || !std::isfinite(d.K))
+        return fail(MC_E_ARG, "replica %d: J and K must be finite", idx);
+    const double en = std::sqrt(d.e[0] * d.e[0] + d.e[1] * d.e[1] + d.e[2] * d.e[2]);
+    if (!(en > 0.0) || !std::isfinite(en))
+        return fail(MC_E_ARG, "replica %d: easy axis must be nonzero and finite", idx);
+    if (std::isnan(d.sphere_radius)) return fail(MC_E_ARG, "replica %d: sphere_radius is NaN", idx);
+    const double nbox = (double)d.Lx * d.Ly * d.Lz * n_basis(d.kind);
+    if (nbox >= 2147483647.0)
+        return fail(MC_E_UNSUPPORTED, "replica %d: box of %.0f sites exceeds 2^31", idx, nbox);
+    if (d.kind == MC_SC) {
+        if (d.Lx % 2)
+            return fail(MC_E_UNSUPPORTED, "replica %d: simple cubic needs even Lx (colour packing)",
+                        idx);
+        const int L[3] = {d.Lx, d.Ly, d.Lz};
+        for (int a = 0; a < 3; ++a)
+            if ((d.periodic_mask >> a & 1u) && (L[a] % 2))
+                return fail(MC_E_UNSUPPORTED,
+                            "replica %d: simple cubic with odd periodic length on axis %d cannot "
+                            "be two-coloured",
+                            idx, a);
+    }
+    return MC_OK;
+}
+
+uint64_t box_sites(const mc_replica_desc &d)
+{
+    return (uint64_t)d.Lx * d.Ly * d.Lz * n_basis(d.kind);
+}
+
+bool site_occupied(const mc_replica_desc &d, int x, int y, int z, int b)
+{
+    if (!(d.sphere_radius > 0.0)) return true;
+    static const int B2[3][4][3] = {{{0, 0, 0}},
+                                    {{0, 0, 0}, {1, 1, 1}},
+                                    {{0, 0, 0}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1}}};
+    const int64_t qx = 2 * (int64_t)x + B2[d.kind][b][0] - d.Lx;
+    const int64_t qy = 2 * (int64_t)y + B2[d.kind][b][1] - d.Ly;
+    const int64_t qz = 2 * (int64_t)z + B2[d.kind][b][2] - d.Lz;
+    return (double)(qx * qx + qy * qy + qz * qz) <= 4.0 * d.sphere_radius * d.sphere_radius;
+}
+
+uint64_t count_occupied(const mc_replica_desc &d)
+{
+    if (!(d.sphere_radius > 0.0)) return box_sites(d);
+    uint64_t n = 0;
+    const int nb = n_basis(d.kind);
+    for (int z = 0; z < d.Lz; ++z)
+        for (int y = 0; y < d.Ly; ++y)
+            for (int x = 0; x < d.Lx; ++x)
+                for (int b = 0; b < nb; ++b) n += site_occupied(d, x, y, z, b);
+    return n;
+}
+
+int row_len(const mc_replica_desc &d) { return d.kind == MC_SC ? d.Lx / 2 : d.Lx; }
+
+int pow2_at_least(int v)
+{
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+Tile default_tile(const mc_replica_desc *reps, int n)
+{
+    int W = 1, Ly = 1;
+    for (int r = 0; r < n; ++r) {
+        W = std::max(W, row_len(reps[r]));
+        Ly = std::max(Ly, reps[r].Ly);
+    }
+    Tile t;
+    t.tx = std::min(64, pow2_at_least(W));
+    t.ty = std::min(256 / t.tx, pow2_at_least(Ly));
+    uint64_t cols = 0, planes = 0;
+    for (int r = 0; r < n; ++r) {
+        const uint64_t c = (uint64_t)((row_len(reps[r]) + t.tx - 1) / t.tx) *
+                           ((reps[r].Ly + t.ty - 1) / t.ty);
+        cols += c * reps[r].Lz;
+        planes = std::max<uint64_t>(planes, reps[r].Lz);
+    }
+    uint64_t zc = (cols + kTargetItems - 1) / kTargetItems;
+    t.zc = (int)std::max<uint64_t>(1, std::min<uint64_t>(zc, planes));
+    return t;
+}
+
+// minimum of q^2 for q in [lo, hi]
+int64_t min_sq(int64_t lo, int64_t hi)
+{
+    if (lo <= 0 && hi >= 0) return 0;
+    const int64_t a = lo > 0 ? lo : -hi;
+    return a * a;
+}
+
+// Tiles of every replica in (z, y, x) order; fully unoccupied tiles dropped.
+void make_work(const mc_replica_desc *reps, int n, const Tile &t, std::vector<WorkItem> &work,
+               std::vector<uint32_t> &begin, std::vector<uint32_t> &end)
+{
+    work.clear();
+    begin.assign(n, 0);
+    end.assign(n, 0);
+    for (int r = 0; r < n; ++r) {
+        const mc_replica_desc &d = reps[r];
+        begin[r] = (uint32_t)work.size();
+        const int W = row_len(d);
+        const bool sc = d.kind == MC_SC;
+        for (int z0 = 0; z0 < d.Lz; z0 += t.zc)
+            for (int y0 = 0; y0 < d.Ly; y0 += t.ty)
+                for (int x0 = 0; x0 < W; x0 += t.tx) {
+                    if (d.sphere_radius > 0.0) {
+                        // cells covered, then half-unit site positions relative to the centre
+                        const int cx0 = sc ? 2 * x0 : x0;
+                        const int cx1 = sc ? std::min(d.Lx, 2 * (x0 + t.tx)) - 1
+                                           : std::min(d.Lx, x0 + t.tx) - 1;
+                        const int cy1 = std::min(d.Ly, y0 + t.ty) - 1;
+                        const int cz1 = std::min(d.Lz, z0 + t.zc) - 1;
+                        const int64_t m = min_sq(2 * cx0 - d.Lx, 2 * cx1 + 1 - d.Lx) +
+                                          min_sq(2 * y0 - d.Ly, 2 * cy1 + 1 - d.Ly) +
+                                          min_sq(2 * z0 - d.Lz, 2 * cz1 + 1 - d.Lz);
+                        if ((double)m > 4.0 * d.sphere_radius * d.sphere_radius) continue;
+                    }
+                    work.push_back(WorkItem{(uint32_t)r, x0, y0, z0});
+                }
+        end[r] = (uint32_t)work.size();
+    }
+}
+
+struct ScratchLayout {
+    uint64_t off_ctr, off_reps, off_work, off_partials, off_records, total;
+};
+
+ScratchLayout scratch_layout(int n_reps, uint64_t n_items, int n_colours)
+{
+    ScratchLayout L;
+    uint64_t o = 0;
+    L.off_ctr = o;
+    o += 256;
+    L.off_reps = o;
+    o = align_up(o + sizeof(RepDev) * n_reps, 256);
+    L.off_work = o;
+    o = align_up(o + sizeof(WorkItem) * std::max<uint64_t>(n_items, 1), 256);
+    L.off_partials = o;
+    o = align_up(o + sizeof(double) * NQ * n_colours * std::max<uint64_t>(n_items, 1), 256);
+    L.off_records = o;
+    // ring of records plus one slot for from-scratch measurements
+    o = align_up(o + sizeof(double) * NR * n_reps * (kRing + 1), 256);
+    L.total = o;
+    return L;
+}
+
+mc_status check_device_buffer(const void *p, uint64_t bytes, const char *what, int rep)
+{
+    if (!p) return fail(MC_E_BUFFER, "replica %d: %s is NULL", rep, what);
+    if (reinterpret_cast<uintptr_t>(p) % 16)
+        return fail(MC_E_BUFFER, "replica %d: %s is not 16-byte aligned", rep, what);
+    hipPointerAttribute_t attr;
+    std::memset(&attr, 0, sizeof attr);
+    hipError_t e = hipPointerGetAttributes(&attr, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(MC_E_BUFFER, "replica %d: %s is not HIP memory (%s)", rep, what,
+                    hipGetErrorString(e));
+    }
+    if (attr.type != hipMemoryTypeDevice)
+        return fail(MC_E_BUFFER, "replica %d: %s is not device memory", rep, what);
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    e = hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)p);
+    if (e == hipSuccess && base) {
+        const uint64_t avail = (uint64_t)((const char *)base + size - (const char *)p);
+        if (avail < bytes)
+            return fail(MC_E_BUFFER, "replica %d: %s holds %llu bytes, %llu needed", rep, what,
+                        (unsigned long long)avail, (unsigned long long)bytes);
+    } else {
+        (void)hipGetLastError();
+    }
+    return MC_OK;
+}
+
+} // namespace
+
+struct mc_sim {
+    int32_t n_reps = 0, kind = 0, n_colours = 0;
+    mc_precision prec = MC_F32;
+    uint64_t seed = 0;
+    std::vector<mc_replica_desc> desc;
+    std::vector<RepDev> reps;
+    std::vector<uint64_t> n_occ;
+    std::vector<WorkItem> work;
+    Tile tile{};
+    hipStream_t stream = nullptr;
+    char *scratch = nullptr;
+    uint64_t scratch_bytes = 0;
+    ScratchLayout lay{};
+    uint32_t *tctr = nullptr;
+    RepDev *reps_dev = nullptr;
+    WorkItem *work_dev = nullptr;
+    double *partials = nullptr;
+    double *records = nullptr;
+    double *host_rec = nullptr; // pinned, (kRing + 1) * n_reps * NR
+    uint64_t t = 0;             // sweeps done
+    uint64_t n_measured = 0;
+    int64_t last_slot = -1;
+    std::map<std::pair<uint32_t, uint32_t>, hipGraphExec_t> graphs;
+    uint32_t magic = 0x4d434831u;
+};
+
+namespace {
+
+bool alive(const mc_sim *h) { return h && h->magic == 0x4d434831u; }
+
+PassLaunch pass_args(mc_sim *h, uint32_t item_base, uint32_t n_blocks, uint32_t t_off)
+{
+    PassLaunch p;
+    p.reps_dev = h->reps_dev;
+    p.work_dev = h->work_dev;
+    p.item_base = item_base;
+    p.n_blocks = n_blocks;
+    p.n_items = (uint32_t)h->work.size();
+    p.tctr_dev = h->tctr;
+    p.t_off = t_off;
+    p.seed_lo = (uint32_t)h->seed;
+    p.seed_hi = (uint32_t)(h->seed >> 32);
+    p.tile = h->tile;
+    p.partials_dev = h->partials;
+    p.dbg_dh = nullptr;
+    p.dbg_acc = nullptr;
+    return p;
+}
+
+// Enqueue n sweeps (passes, optional finalise into ring slots slot0.., then
+// the counter advance).  Pure launches: safe inside stream capture.
+mc_status enqueue_sweeps(mc_sim *h, uint32_t n, bool measure, uint32_t slot0)
+{
+    const bool f64 = h->prec == MC_F64;
+    const uint32_t n_items = (uint32_t)h->work.size();
+    for (uint32_t i = 0; i < n; ++i) {
+        const PassLaunch p = pass_args(h, 0, n_items, i);
+        for (int c = 0; c < h->n_colours; ++c) HIP_TRY(launch_pass(h->kind, f64, c, measure, 0, p, h->stream));
+        if (measure) {
+            const uint32_t slot = (slot0 + i) % kRing;
+            HIP_TRY(launch_finalize(h->reps_dev, h->n_reps, h->n_colours, h->partials, n_items,
+                                    h->tctr, i, h->records + (size_t)slot * h->n_reps * NR,
+                                    h->stream));
+        }
+    }
+    HIP_TRY(launch_advance(h->tctr, n, h->stream));
+    return MC_OK;
+}
+
+void record_to_obs(const mc_sim *h, const double *rec, int r, mc_obs *o)
+{
+    const double N = (double)h->n_occ[r];
+    o->sweep = (uint64_t)rec[R_SWEEP];
+    o->n_sites = h->n_occ[r];
+    o->n_accepted = (uint64_t)rec[R_NACC];
+    for (int a = 0; a < 3; ++a) o->M[a] = rec[R_MX + a] / N;
+    o->absM = std::sqrt(o->M[0] * o->M[0] + o->M[1] * o->M[1] + o->M[2] * o->M[2]);
+    o->E_exch = rec[R_EEX];
+    o->E_anis = rec[R_EAN];
+    o->E = o->E_exch + o->E_anis;
+}
+
+mc_status upload_reps(mc_sim *h)
+{
+    HIP_TRY(hipMemcpyAsync(h->reps_dev, h->reps.data(), sizeof(RepDev) * h->n_reps,
+                           hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return MC_OK;
+}
+
+void set_temperature(RepDev &R, double T)
+{
+    R.greedy = T == 0.0;
+    R.beta = (T > 0.0 && std::isfinite(T)) ? 1.0 / T : 0.0;
+}
+
+mc_status run_chunk(mc_sim *h, uint32_t n, bool measure, uint32_t slot0)
+{
+    if (n == 0) return MC_OK;
+    if (!h->stream) return enqueue_sweeps(h, n, measure, slot0);
+    // replay a captured graph of n sweeps; graphs bake the ring slots, so a
+    // measured graph is keyed by its first slot too (callers use slot 0)
+    const std::pair<uint32_t, uint32_t> key(n, measure ? 1u + slot0 : 0u);
+    auto it = h->graphs.find(key);
+    if (it == h->graphs.end()) {
+        HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+        mc_status s = enqueue_sweeps(h, n, measure, slot0);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(h->stream, &g);
+        if (s != MC_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return s;
+        }
+        if (e != hipSuccess) return fail(MC_E_DEVICE, "graph capture: %s", hipGetErrorString(e));
+        hipGraphExec_t ex = nullptr;
+        e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return fail(MC_E_DEVICE, "graph instantiate: %s", hipGetErrorString(e));
+        it = h->graphs.emplace(key, ex).first;
+    }
+    HIP_TRY(hipGraphLaunch(it->second, h->stream));
+    return MC_OK;
+}
+
+// ---- statistics (product side) ------------------------------------------
+double mean_of(const std::vector<double> &x)
+{
+    double s = 0.0;
+    for (double v : x) s += v;
+    return x.empty() ? 0.0 : s / (double)x.size();
+}
+
+// Standard error of the mean of a correlated series: repeated pairwise
+// blocking (Flyvbjerg & Petersen 1989), maximum over levels with >= 32 blocks.
+double blocked_error(std::vector<double> x)
+{
+    double best = 0.0;
+    while (x.size() >= 32) {
+        const double m = mean_of(x);
+        double v = 0.0;
+        for (double a : x) v += (a - m) * (a - m);
+        v /= (double)(x.size() - 1);
+        best = std::max(best, std::sqrt(v / (double)x.size()));
+        std::vector<double> y(x.size() / 2);
+        for (size_t i = 0; i < y.size(); ++i) y[i] = 0.5 * (x[2 * i] + x[2 * i + 1]);
+        x.swap(y);
+    }
+    if (best == 0.0 && x.size() > 1) {
+        const double m = mean_of(x);
+        double v = 0.0;
+        for (double a : x) v += (a - m) * (a - m);
+        best = std::sqrt(v / (double)(x.size() - 1) / (double)x.size());
+    }
+    return best;
+}
+
+} // namespace
+
+extern "C" {
+
+const char *mc_last_error(void) { return g_err.c_str(); }
+
+const char *mc_version(void) { return "mcheis 0.1 (gfx950)"; }
+
+mc_status mc_required_sites(const mc_replica_desc *d, uint64_t *sites)
+{
+    if (!d || !sites) return fail(MC_E_ARG, "NULL argument");
+    mc_status s = check_desc(*d, 0);
+    if (s != MC_OK) return s;
+    *sites = box_sites(*d);
+    return MC_OK;
+}
+
+mc_status mc_occupied_sites(const mc_replica_desc *d, uint64_t *n)
+{
+    if (!d || !n) return fail(MC_E_ARG, "NULL argument");
+    mc_status s = check_desc(*d, 0);
+    if (s != MC_OK) return s;
+    *n = count_occupied(*d);
+    return MC_OK;
+}
+
+mc_status mc_required_scratch(const mc_replica_desc *reps, int32_t n_reps, uint64_t *bytes)
+{
+    if (!reps || !bytes) return fail(MC_E_ARG, "NULL argument");
+    if (n_reps < 1) return fail(MC_E_ARG, "n_reps must be >= 1");
+    for (int r = 0; r < n_reps; ++r) {
+        mc_status s = check_desc(reps[r], r);
+        if (s != MC_OK) return s;
+        if (reps[r].kind != reps[0].kind)
+            return fail(MC_E_ARG, "replica %d: all replicas must share one lattice kind", r);
+    }
+    const Tile t = default_tile(reps, n_reps);
+    std::vector<WorkItem> work;
+    std::vector<uint32_t> b, e;
+    make_work(reps, n_reps, t, work, b, e);
+    *bytes = scratch_layout(n_reps, work.size(), n_colours_of(reps[0].kind)).total;
+    return MC_OK;
+}
+
+mc_status mc_init_lattice(const mc_replica_desc *reps, int32_t n_reps, mc_precision prec,
+                          uint64_t seed, mc_init_mode init, const mc_spin_buffers *bufs,
+                          void *scratch, uint64_t scratch_bytes, void *hip_stream, mc_sim **out)
+{
+    if (!out) return fail(MC_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!reps || !bufs) return fail(MC_E_ARG, "reps or bufs is NULL");
+    if (n_reps < 1) return fail(MC_E_ARG, "n_reps must be >= 1");
+    if (prec != MC_F32 && prec != MC_F64) return fail(MC_E_ARG, "unknown precision %d", (int)prec);
+    if (init < MC_INIT_RANDOM || init > MC_INIT_USER)
+        return fail(MC_E_ARG, "unknown init mode %d", (int)init);
+    for (int r = 0; r < n_reps; ++r) {
+        mc_status s = check_desc(reps[r], r);
+        if (s != MC_OK) return s;
+        if (reps[r].kind != reps[0].kind)
+            return fail(MC_E_ARG, "replica %d: all replicas must share one lattice kind", r);
+    }
+    int dev_count = 0;
+    if (hipGetDeviceCount(&dev_count) != hipSuccess || dev_count < 1) {
+        (void)hipGetLastError();
+        return fail(MC_E_DEVICE, "no HIP device available");
+    }
+    const size_t esz = prec == MC_F64 ? sizeof(double) : sizeof(float);
+    for (int r = 0; r < n_reps; ++r) {
+        const uint64_t need = box_sites(reps[r]);
+        if (bufs[r].capacity_sites < need)
+            return fail(MC_E_BUFFER, "replica %d: capacity %llu < %llu sites", r,
+                        (unsigned long long)bufs[r].capacity_sites, (unsigned long long)need);
+        const void *pl[3] = {bufs[r].sx, bufs[r].sy, bufs[r].sz};
+        const char *nm[3] = {"sx", "sy", "sz"};
+        for (int a = 0; a < 3; ++a) {
+            mc_status s = check_device_buffer(pl[a], need * esz, nm[a], r);
+            if (s != MC_OK) return s;
+        }
+    }
+    mc_sim *h = new (std::nothrow) mc_sim();
+    if (!h) return fail(MC_E_ARG, "out of host memory");
+    h->n_reps = n_reps;
+    h->kind = reps[0].kind;
+    h->n_colours = n_colours_of(h->kind);
+    h->prec = prec;
+    h->seed = seed;
+    h->stream = (hipStream_t)hip_stream;
+    h->desc.assign(reps, reps + n_reps);
+    h->tile = default_tile(reps, n_reps);
+    std::vector<uint32_t> b, e;
+    make_work(reps, n_reps, h->tile, h->work, b, e);
+    h->lay = scratch_layout(n_reps, h->work.size(), h->n_colours);
+    auto cleanup = [&](mc_status s) {
+        mc_destroy(h);
+        return s;
+    };
+    if (!scratch) return cleanup(fail(MC_E_BUFFER, "scratch is NULL"));
+    if (reinterpret_cast<uintptr_t>(scratch) % 256)
+        return cleanup(fail(MC_E_BUFFER, "scratch must be 256-byte aligned"));
+    if (scratch_bytes < h->lay.total)
+        return cleanup(fail(MC_E_BUFFER, "scratch has %llu bytes, %llu needed",
+                            (unsigned long long)scratch_bytes, (unsigned long long)h->lay.total));
+    {
+        mc_status s = check_device_buffer(scratch, h->lay.total, "scratch", -1);
+        if (s != MC_OK) return cleanup(s);
+    }
+    h->scratch = (char *)scratch;
+    h->scratch_bytes = scratch_bytes;
+    h->tctr = (uint32_t *)(h->scratch + h->lay.off_ctr);
+    h->reps_dev = (RepDev *)(h->scratch + h->lay.off_reps);
+    h->work_dev = (WorkItem *)(h->scratch + h->lay.off_work);
+    h->partials = (double *)(h->scratch + h->lay.off_partials);
+    h->records = (double *)(h->scratch + h->lay.off_records);
+
+    h->reps.resize(n_reps);
+    h->n_occ.resize(n_reps);
+    for (int r = 0; r < n_reps; ++r) {
+        const mc_replica_desc &d = reps[r];
+        RepDev &R = h->reps[r];
+        std::memset(&R, 0, sizeof R);
+        R.sx = bufs[r].sx;
+        R.sy = bufs[r].sy;
+        R.sz = bufs[r].sz;
+        R.Lx = d.Lx;
+        R.Ly = d.Ly;
+        R.Lz = d.Lz;
+        R.Lxh = row_len(d);
+        R.pmask = d.periodic_mask;
+        R.rid = d.replica_id;
+        R.n_box = (uint32_t)box_sites(d);
+        R.plane = d.kind == MC_SC ? R.n_box / 2 : (uint32_t)d.Lx * d.Ly * d.Lz;
+        R.J = d.J;
+        R.K = d.K;
+        const double en = std::sqrt(d.e[0] * d.e[0] + d.e[1] * d.e[1] + d.e[2] * d.e[2]);
+        for (int a = 0; a < 3; ++a) R.e[a] = d.e[a] / en;
+        set_temperature(R, d.T);
+        R.sphere = d.sphere_radius > 0.0;
+        R.r2x4 = 4.0 * d.sphere_radius * d.sphere_radius;
+        R.item_begin = b[r];
+        R.item_end = e[r];
+        h->n_occ[r] = count_occupied(d);
+        if (h->n_occ[r] == 0) return cleanup(fail(MC_E_ARG, "replica %d has no occupied site", r));
+    }
+    if (hipHostMalloc((void **)&h->host_rec, sizeof(double) * NR * n_reps * (kRing + 1),
+                      hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        h->host_rec = nullptr;
+        return cleanup(fail(MC_E_DEVICE, "pinned host allocation failed"));
+    }
+    mc_status s;
+    if ((s = upload_reps(h)) != MC_OK) return cleanup(s);
+    if (hipMemcpyAsync(h->work_dev, h->work.data(), sizeof(WorkItem) * h->work.size(),
+                       hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+        launch_set_counter(h->tctr, 0u, h->stream) != hipSuccess)
+        return cleanup(fail(MC_E_DEVICE, "upload failed: %s", hipGetErrorString(hipGetLastError())));
+    if (init != MC_INIT_USER) {
+        for (int r = 0; r < n_reps; ++r) {
+            hipError_t er = launch_init(prec == MC_F64, h->kind, &h->reps[r],
+                                        init == MC_INIT_ALIGNED ? 1 : 0, (uint32_t)seed,
+                                        (uint32_t)(seed >> 32), h->stream);
+            if (er != hipSuccess)
+                return cleanup(fail(MC_E_DEVICE, "init launch: %s", hipGetErrorString(er)));
+        }
+    }
+    if (hipStreamSynchronize(h->stream) != hipSuccess)
+        return cleanup(fail(MC_E_DEVICE, "init: %s", hipGetErrorString(hipGetLastError())));
+    *out = h;
+    return MC_OK;
+}
+
+mc_status mc_sweep(mc_sim *h, uint32_t n_sweeps, uint32_t flags)
+{
+    if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
+    if (flags & ~MC_MEASURE) return fail(MC_E_ARG, "unknown flags 0x%x", flags);
+    if (n_sweeps == 0) return MC_OK;
+    if (h->t + n_sweeps > 0xFFFFFFFFull) return fail(MC_E_STATE, "sweep counter would exceed 2^32-1");
+    const bool measure = flags & MC_MEASURE;
+    const uint32_t slot0 = (uint32_t)(h->n_measured % kRing);
+    mc_status s = enqueue_sweeps(h, n_sweeps, measure, slot0);
+    if (s != MC_OK) return s;
+    h->t += n_sweeps;
+    if (measure) {
+        h->n_measured += n_sweeps;
+        h->last_slot = (int64_t)((slot0 + n_sweeps - 1) % kRing);
+    }
+    return MC_OK;
+}
+
+mc_status mc_sweep_timed(mc_sim *h, uint32_t n_sweeps, uint32_t flags, double *pass_ms_avg,
+                         double *total_ms)
+{
+    if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
+    if (flags & ~MC_MEASURE) return fail(MC_E_ARG, "unknown flags 0x%x", flags);
+    if (!pass_ms_avg || !total_ms) return fail(MC_E_ARG, "NULL out-pointer");
+    if (n_sweeps == 0) return fail(MC_E_ARG, "n_sweeps must be >= 1");
+    if (h->t + n_sweeps > 0xFFFFFFFFull) return fail(MC_E_STATE, "sweep counter would exceed 2^32-1");
+    const bool measure = flags & MC_MEASURE;
+    const bool f64 = h->prec == MC_F64;
+    const uint32_t n_items = (uint32_t)h->work.size();
+    const uint32_t n_pass = n_sweeps * (uint32_t)h->n_colours;
+    std::vector<hipEvent_t> ev(2 * (size_t)n_pass + 2, nullptr);
+    for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
+    auto release = [&]() {
+        for (auto &e : ev)
+            if (e) (void)hipEventDestroy(e);
+    };
+    const uint32_t slot0 = (uint32_t)(h->n_measured % kRing);
+    hipError_t err = hipEventRecord(ev[2 * n_pass], h->stream);
+    for (uint32_t i = 0; i < n_sweeps && err == hipSuccess; ++i) {
+        const PassLaunch p = pass_args(h, 0, n_items, i);
+        for (int c = 0; c < h->n_colours && err == hipSuccess; ++c) {
+            const uint32_t k = i * h->n_colours + c;
+            err = hipEventRecord(ev[2 * k], h->stream);
+            if (err == hipSuccess) err = launch_pass(h->kind, f64, c, measure, 0, p, h->stream);
+            if (err == hipSuccess) err = hipEventRecord(ev[2 * k + 1], h->stream);
+        }
+        if (measure && err == hipSuccess)
+            err = launch_finalize(h->reps_dev, h->n_reps, h->n_colours, h->partials, n_items,
+                                  h->tctr, i,
+                                  h->records + (size_t)((slot0 + i) % kRing) * h->n_reps * NR,
+                                  h->stream);
+    }
+    if (err == hipSuccess) err = launch_advance(h->tctr, n_sweeps, h->stream);
+    if (err == hipSuccess) err = hipEventRecord(ev[2 * n_pass + 1], h->stream);
+    if (err == hipSuccess) err = hipEventSynchronize(ev[2 * n_pass + 1]);
+    if (err != hipSuccess) {
+        release();
+        return fail(MC_E_DEVICE, "timed sweep: %s", hipGetErrorString(err));
+    }
+    double sum = 0.0;
+    for (uint32_t k = 0; k < n_pass; ++k) {
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]);
+        sum += ms;
+    }
+    float tot = 0.f;
+    (void)hipEventElapsedTime(&tot, ev[2 * n_pass], ev[2 * n_pass + 1]);
+    release();
+    *pass_ms_avg = sum / n_pass;
+    *total_ms = tot;
+    h->t += n_sweeps;
+    if (measure) {
+        h->n_measured += n_sweeps;
+        h->last_slot = (int64_t)((slot0 + n_sweeps - 1) % kRing);
+    }
+    return MC_OK;
+}
+
+mc_status mc_observables(mc_sim *h, mc_obs *out, int32_t n_reps)
+{
+    if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
+    if (!out) return fail(MC_E_ARG, "out is NULL");
+    if (n_reps != h->n_reps) return fail(MC_E_ARG, "n_reps %d != handle's %d", n_reps, h->n_reps);
+    if (h->last_slot < 0) return fail(MC_E_STATE, "no measured sweep yet");
+    const size_t sz = sizeof(double) * NR * h->n_reps;
+    HIP_TRY(hipMemcpyAsync(h->host_rec, h->records + (size_t)h->last_slot * h->n_reps * NR, sz,
+                           hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    for (int r = 0; r < h->n_reps; ++r) record_to_obs(h, h->host_rec + (size_t)r * NR, r, &out[r]);
+    return MC_OK;
+}
+
+mc_status mc_measure_state(mc_sim *h, mc_obs *out, int32_t n_reps)
+{
+    if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
+    if (!out) return fail(MC_E_ARG, "out is NULL");
+    if (n_reps != h->n_reps) return fail(MC_E_ARG, "n_reps %d != handle's %d", n_reps, h->n_reps);
+    const bool f64 = h->prec == MC_F64;
+    const uint32_t n_items = (uint32_t)h->work.size();
+    const PassLaunch p = pass_args(h, 0, n_items, 0);
+    for (int c = 0; c < h->n_colours; ++c) HIP_TRY(launch_pass(h->kind, f64, c, true, 1, p, h->stream));
+    double *dst = h->records + (size_t)kRing * h->n_reps * NR;
+    HIP_TRY(launch_finalize(h->reps_dev, h->n_reps, h->n_colours, h->partials, n_items, h->tctr,
+                            0, dst, h->stream));
+    HIP_TRY(hipMemcpyAsync(h->host_rec, dst, sizeof(double) * NR * h->n_reps,
+                           hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    for (int r = 0; r < h->n_reps; ++r) {
+        record_to_obs(h, h->host_rec + (size_t)r * NR, r, &out[r]);
+        out[r].sweep = h->t;
+        out[r].n_accepted = 0;
+    }
+    return MC_OK;
+}
+
+mc_status mc_set_temperatures(mc_sim *h, const double *T, int32_t n_reps)
+{
+    if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
+    if (!T) return fail(MC_E_ARG, "T is NULL");
+    if (n_reps != h->n_reps) return fail(MC_E_ARG, "n_reps %d != handle's %d", n_reps, h->n_reps);
+    for (int r = 0; r < n_reps; ++r)
+        if (!(T[r] >= 0.0)) return fail(MC_E_ARG, "replica %d: T must be >= 0", r);
+    for (int r = 0; r < n_reps; ++r) {
+        h->desc[r].T = T[r];
+        set_temperature(h->reps[r], T[r]);
+    }
+    return upload_reps(h);
+}
+
+mc_status mc_run_schedule(mc_sim *h, const mc_schedule *s, mc_obs *series, uint64_t capacity,
+                          uint64_t *n_written)
+{
+    if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
+    if (!s || !s->T) return fail(MC_E_ARG, "schedule or its T is NULL");
+    if (s->n_T < 1 || s->measure_every < 1) return fail(MC_E_ARG, "n_T and measure_every must be >= 1");
+    const uint64_t per_step = s->n_meas / s->measure_every;
+    const uint64_t need = (uint64_t)s->n_T * per_step * h->n_reps;
+    if (need > 0 && !series) return fail(MC_E_ARG, "series is NULL");
+    if (capacity < need)
+        return fail(MC_E_ARG, "series capacity %llu < %llu", (unsigned long long)capacity,
+                    (unsigned long long)need);
+    const uint64_t total_sweeps = (uint64_t)s->n_T * ((uint64_t)s->n_equil + s->n_meas);
+    if (h->t + total_sweeps > 0xFFFFFFFFull) return fail(MC_E_STATE, "sweep counter would exceed 2^32-1");
+    for (int64_t i = 0; i < (int64_t)s->n_T * h->n_reps; ++i)
+        if (!(s->T[i] >= 0.0)) return fail(MC_E_ARG, "schedule T[%lld] must be >= 0", (long long)i);
+    uint64_t written = 0;
+    for (int step = 0; step < s->n_T; ++step) {
+        mc_status st = mc_set_temperatures(h, s->T + (size_t)step * h->n_reps, h->n_reps);
+        if (st != MC_OK) return st;
+        for (uint32_t done = 0; done < s->n_equil;) {
+            const uint32_t k = std::min(kGraphChunk, s->n_equil - done);
+            if ((st = run_chunk(h, k, false, 0)) != MC_OK) return st;
+            done += k;
+            h->t += k;
+        }
+        uint32_t meas_idx = 0;
+        for (uint32_t done = 0; done < s->n_meas;) {
+            const uint32_t k = std::min(kGraphChunk, s->n_meas - done);
+            if ((st = run_chunk(h, k, true, 0)) != MC_OK) return st;
+            h->t += k;
+            h->n_measured += k;
+            h->last_slot = k - 1;
+            const size_t sz = sizeof(double) * NR * h->n_reps * k;
+            HIP_TRY(hipMemcpyAsync(h->host_rec, h->records, sz, hipMemcpyDeviceToHost, h->stream));
+            HIP_TRY(hipStreamSynchronize(h->stream));
+            for (uint32_t j = 0; j < k; ++j, ++meas_idx) {
+                if ((meas_idx + 1) % s->measure_every) continue;
+                for (int r = 0; r < h->n_reps; ++r)
+                    record_to_obs(h, h->host_rec + ((size_t)j * h->n_reps + r) * NR, r,
+                                  &series[written++]);
+            }
+            done += k;
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    if (n_written) *n_written = written;
+    return MC_OK;
+}
+
+mc_status mc_debug_pass(mc_sim *h, int32_t colour, void *const *dh, void *const *accepted)
+{
+    if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
+    if (colour < 0 || colour >= h->n_colours)
+        return fail(MC_E_ARG, "colour %d out of range [0, %d)", colour, h->n_colours);
+    if (!dh || !accepted) return fail(MC_E_ARG, "dh or accepted is NULL");
+    const size_t esz = h->prec == MC_F64 ? sizeof(double) : sizeof(float);
+    for (int r = 0; r < h->n_reps; ++r) {
+        mc_status s = check_device_buffer(dh[r], h->reps[r].n_box * esz, "dh", r);
+        if (s != MC_OK) return s;
+        s = check_device_buffer(accepted[r], h->reps[r].n_box, "accepted", r);
+        if (s != MC_OK) return s;
+    }
+    for (int r = 0; r < h->n_reps; ++r) {
+        const RepDev &R = h->reps[r];
+        PassLaunch p = pass_args(h, R.item_begin, R.item_end - R.item_begin, 0);
+        p.dbg_dh = dh[r];
+        p.dbg_acc = (uint8_t *)accepted[r];
+        HIP_TRY(launch_pass(h->kind, h->prec == MC_F64, colour, false, 0, p, h->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return MC_OK;
+}
+
+mc_status mc_layout_copy(mc_sim *h, int32_t replica, int32_t to_natural, void *nx, void *ny,
+                         void *nz)
+{
+    if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
+    if (replica < 0 || replica >= h->n_reps) return fail(MC_E_ARG, "replica %d out of range", replica);
+    const size_t esz = h->prec == MC_F64 ? sizeof(double) : sizeof(float);
+    void *pl[3] = {nx, ny, nz};
+    for (int a = 0; a < 3; ++a) {
+        mc_status s = check_device_buffer(pl[a], h->reps[replica].n_box * esz, "natural plane", replica);
+        if (s != MC_OK) return s;
+    }
+    HIP_TRY(launch_layout(h->prec == MC_F64, h->kind, &h->reps[replica], to_natural != 0, nx, ny,
+                          nz, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return MC_OK;
+}
+
+mc_status mc_set_tile(mc_sim *h, int32_t tx, int32_t ty, int32_t zc)
+{
+    if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
+    if (tx < 1 || ty < 1 || zc < 1 || tx * ty > 256)
+        return fail(MC_E_ARG, "tile %d x %d x %d invalid (need >= 1 and tx*ty <= 256)", tx, ty, zc);
+    Tile t{tx, ty, zc};
+    std::vector<WorkItem> work;
+    std::vector<uint32_t> b, e;
+    make_work(h->desc.data(), h->n_reps, t, work, b, e);
+    const ScratchLayout lay = scratch_layout(h->n_reps, work.size(), h->n_colours);
+    if (lay.total > h->scratch_bytes)
+        return fail(MC_E_BUFFER, "tile %d x %d x %d needs %llu scratch bytes, handle has %llu", tx,
+                    ty, zc, (unsigned long long)lay.total, (unsigned long long)h->scratch_bytes);
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    for (auto &kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+    h->graphs.clear();
+    h->tile = t;
+    h->work.swap(work);
+    h->lay = lay;
+    h->reps_dev = (RepDev *)(h->scratch + lay.off_reps);
+    h->work_dev = (WorkItem *)(h->scratch + lay.off_work);
+    h->partials = (double *)(h->scratch + lay.off_partials);
+    h->records = (double *)(h->scratch + lay.off_records);
+    h->last_slot = -1;
+    for (int r = 0; r < h->n_reps; ++r) {
+        h->reps[r].item_begin = b[r];
+        h->reps[r].item_end = e[r];
+    }
+    HIP_TRY(hipMemcpyAsync(h->work_dev, h->work.data(), sizeof(WorkItem) * h->work.size(),
+                           hipMemcpyHostToDevice, h->stream));
+    return upload_reps(h);
+}
+
+mc_status mc_get_tile(const mc_sim *h, int32_t *tx, int32_t *ty, int32_t *zc, uint64_t *n_items)
+{
+    if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
+    if (tx) *tx = h->tile.tx;
+    if (ty) *ty = h->tile.ty;
+    if (zc) *zc = h->tile.zc;
+    if (n_items) *n_items = h->work.size();
+    return MC_OK;
+}
+
+mc_status mc_get_sweep(const mc_sim *h, uint64_t *t)
+{
+    if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
+    if (!t) return fail(MC_E_ARG, "t is NULL");
+    *t = h->t;
+    return MC_OK;
+}
+
+mc_status mc_set_sweep(mc_sim *h, uint64_t t)
+{
+    if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
+    if (t > 0xFFFFFFFFull) return fail(MC_E_ARG, "sweep counter must be < 2^32");
+    HIP_TRY(launch_set_counter(h->tctr, (uint32_t)t, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    h->t = t;
+    return MC_OK;
+}
+
+mc_status mc_num_colours(const mc_sim *h, int32_t *n)
+{
+    if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
+    if (!n) return fail(MC_E_ARG, "NULL argument");
+    *n = h->n_colours;
+    return MC_OK;
+}
+
+mc_status mc_series_stats(const mc_obs *series, uint64_t n, uint64_t stride, double T,
+                          mc_stats *out)
+{
+    if (!series || !out) return fail(MC_E_ARG, "NULL argument");
+    if (n < 2 || stride < 1) return fail(MC_E_ARG, "need n >= 2 records and stride >= 1");
+    std::vector<double> am(n), m2(n), m4(n), e(n), E(n);
+    double acc = 0.0;
+    const double N = (double)series[0].n_sites;
+    for (uint64_t i = 0; i < n; ++i) {
+        const mc_obs &o = series[i * stride];
+        const double q = o.M[0] * o.M[0] + o.M[1] * o.M[1] + o.M[2] * o.M[2];
+        am[i] = std::sqrt(q);
+        m2[i] = q;
+        m4[i] = q * q;
+        E[i] = o.E;
+        e[i] = o.E / N;
+        acc += (double)o.n_accepted / N;
+    }
+    std::memset(out, 0, sizeof *out);
+    out->n = n;
+    out->abs_m = mean_of(am);
+    out->abs_m_err = blocked_error(am);
+    out->m2 = mean_of(m2);
+    out->m2_err = blocked_error(m2);
+    out->m4 = mean_of(m4);
+    out->m4_err = blocked_error(m4);
+    out->e = mean_of(e);
+    out->e_err = blocked_error(e);
+    out->U4 = 1.0 - out->m4 / (3.0 * out->m2 * out->m2);
+    out->acceptance = acc / (double)n;
+    if (T > 0.0 && std::isfinite(T)) {
+        const double mE = mean_of(E);
+        double vE = 0.0;
+        for (double v : E) vE += (v - mE) * (v - mE);
+        vE /= (double)n;
+        out->C = vE / (N * T * T);
+        out->chi = N * (out->m2 - out->abs_m * out->abs_m) / T;
+    } else {
+        out->C = NAN;
+        out->chi = NAN;
+    }
+    return MC_OK;
+}
+
+void mc_destroy(mc_sim *h)
+{
+    if (!alive(h)) return;
+    if (h->stream || h->scratch) (void)hipStreamSynchronize(h->stream);
+    for (auto &kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+    h->graphs.clear();
+    if (h->host_rec) (void)hipHostFree(h->host_rec);
+    h->magic = 0;
+    delete h;
+}
+
+} // extern "C"

@@ -1,0 +1,629 @@
+// kernels.hip -- CDNA4 (gfx950) kernels of the colour-sweep Metropolis method
+// for the anisotropic classical Heisenberg model, Eq. (1) of arXiv:2106.11286:
+//     H = -J sum_<ij> S_i.S_j - K sum_i (S_i.e)^2.
+//
+// One launch = one colour pass: every occupied site of one sublattice colour
+// gets one Metropolis attempt (propose uniformly on the sphere; accept if
+// dH <= 0 or P <= exp(-beta dH), the rule of the paper's Monte Carlo
+// paragraph).  No bond joins two sites of one colour, so all sites of a pass
+// are independent and the result does not depend on tiling or thread order.
+//
+// Memory: spins are structure-of-arrays planes (x, y, z components) in the
+// working precision, colour-major, so a pass reads its own colour and the
+// other colour(s) as dense, coalesced rows.  Random numbers are computed in
+// registers from a counter-based generator (no state in memory).  Observables
+// (magnetisation, Eq. (2), and both energy terms) are reduced in FP64 inside
+// the pass from values that are final after it, so measuring adds no spin
+// traffic.
+#include <hip/hip_runtime.h>
+
+#include "launch.hpp"
+#include "mc_internal.hpp"
+
+namespace mc {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32
+// multiplications; the high halves are mixed with the other counter words and
+// the key, which is bumped by the Weyl increments between rounds.
+// ---------------------------------------------------------------------------
+struct Words {
+    uint32_t w0, w1, w2, w3;
+};
+
+__device__ __forceinline__ Words philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                          uint32_t k0, uint32_t k1)
+{
+    constexpr uint32_t kMulA = 0xD2511F53u, kMulB = 0xCD9E8D57u;
+    constexpr uint32_t kWeylA = 0x9E3779B9u, kWeylB = 0xBB67AE85u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo_a = kMulA * c0, hi_a = __umulhi(kMulA, c0);
+        const uint32_t lo_b = kMulB * c2, hi_b = __umulhi(kMulB, c2);
+        const uint32_t n0 = hi_b ^ c1 ^ k0;
+        const uint32_t n2 = hi_a ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo_b;
+        c2 = n2;
+        c3 = lo_a;
+        k0 += kWeylA;
+        k1 += kWeylB;
+    }
+    return {c0, c1, c2, c3};
+}
+
+// u = (k + 1/2) 2^-23 from the top 23 bits: exact in binary32 and binary64.
+template <typename T> __device__ __forceinline__ T uniform23(uint32_t w);
+template <> __device__ __forceinline__ float uniform23<float>(uint32_t w)
+{
+    return __uint2float_rn(w >> 9) * 0x1p-23f + 0x1p-24f;
+}
+template <> __device__ __forceinline__ double uniform23<double>(uint32_t w)
+{
+    return __uint2double_rn(w >> 9) * 0x1p-23 + 0x1p-24;
+}
+
+// Uniform point on the unit sphere (z uniform on [-1,1], azimuth 2 pi u1).
+__device__ __forceinline__ void sphere_point(float u0, float u1, float &x, float &y, float &z)
+{
+    z = 2.0f * u0 - 1.0f;
+    const float r = sqrtf(1.0f - z * z);
+    float s, c;
+    sincospif(2.0f * u1, &s, &c);
+    x = r * c;
+    y = r * s;
+}
+__device__ __forceinline__ void sphere_point(double u0, double u1, double &x, double &y, double &z)
+{
+    z = 2.0 * u0 - 1.0;
+    const double r = sqrt(1.0 - z * z);
+    double s, c;
+    sincospi(2.0 * u1, &s, &c);
+    x = r * c;
+    y = r * s;
+}
+
+__device__ __forceinline__ float fast_exp(float v) { return __expf(v); }
+__device__ __forceinline__ double fast_exp(double v) { return exp(v); }
+__device__ __forceinline__ float inv_norm(float v) { return rsqrtf(v); }
+__device__ __forceinline__ double inv_norm(double v) { return 1.0 / sqrt(v); }
+
+// Basis positions of the conventional cubic cell, in half-cell units.
+__host__ __device__ constexpr int basis_count(int kind) { return kind == SC ? 1 : (kind == BCC ? 2 : 4); }
+__host__ __device__ constexpr int basis2(int kind, int b, int axis)
+{
+    // fcc: (0,0,0) (1,1,0) (1,0,1) (0,1,1); bcc: (0,0,0) (1,1,1)
+    return kind == FCC ? ((b == 0) ? 0 : (b == 1 ? (axis != 2) : (b == 2 ? (axis != 1) : (axis != 0))))
+                       : (kind == BCC ? (b == 1 ? 1 : 0) : 0);
+}
+
+// Exact sphere occupancy (half-cell units are integers).
+__device__ __forceinline__ bool occupied(const RepDev &R, int x, int y, int z, int bx, int by,
+                                         int bz)
+{
+    if (!R.sphere) return true;
+    const int qx = 2 * x + bx - R.Lx, qy = 2 * y + by - R.Ly, qz = 2 * z + bz - R.Lz;
+    return (double)(qx * qx + qy * qy + qz * qz) <= R.r2x4;
+}
+
+// ---------------------------------------------------------------------------
+// Block reduction of NQ doubles (fixed order: wave butterflies, then waves in
+// index order), written to one partial slot.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void block_store_partials(double (&a)[Q_N], double *dst)
+{
+    __shared__ double red[4][Q_N];
+#pragma unroll
+    for (int q = 0; q < Q_N; ++q) {
+        double v = a[q];
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+        a[q] = v;
+    }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int n_waves = (blockDim.x + 63) >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < Q_N; ++q) red[wave][q] = a[q];
+    }
+    __syncthreads();
+    if (threadIdx.x < Q_N) {
+        double s = 0.0;
+        for (int w = 0; w < n_waves; ++w) s += red[w][threadIdx.x];
+        dst[threadIdx.x] = s;
+    }
+    if (threadIdx.x >= Q_N && threadIdx.x < NQ) dst[threadIdx.x] = 0.0;
+}
+
+// One Metropolis attempt at a site with local field h (J already applied).
+// Returns the final spin in (sx, sy, sz).  Canonical site s keys the stream.
+template <typename T>
+__device__ __forceinline__ bool metropolis(T &sx, T &sy, T &sz, T hx, T hy, T hz, uint32_t s,
+                                           uint32_t rid, uint32_t t, uint32_t k0, uint32_t k1,
+                                           T K, T ex, T ey, T ez, T beta, bool greedy, T *dh_out)
+{
+    const Words w = philox10(s, rid, t, 0u, k0, k1);
+    T nx, ny, nz;
+    sphere_point(uniform23<T>(w.w0), uniform23<T>(w.w1), nx, ny, nz);
+    const T P = uniform23<T>(w.w2);
+    const T dx = nx - sx, dy = ny - sy, dz = nz - sz;
+    const T pn = nx * ex + ny * ey + nz * ez;
+    const T po = sx * ex + sy * ey + sz * ez;
+    // Eq. (1): dH = -h.(S'-S) - K[(S'.e)^2 - (S.e)^2]
+    const T dH = -(hx * dx + hy * dy + hz * dz) - K * ((pn - po) * (pn + po));
+    if (dh_out) *dh_out = dH;
+    const bool acc = (dH <= T(0)) || (!greedy && P <= fast_exp(-beta * dH));
+    if (acc) {
+        const T inv = inv_norm(nx * nx + ny * ny + nz * nz);
+        sx = nx * inv;
+        sy = ny * inv;
+        sz = nz * inv;
+    }
+    return acc;
+}
+
+// ---------------------------------------------------------------------------
+// Simple cubic, two colours, colour-packed rows.  A site (x, y, z) of colour
+// c = (x+y+z)&1 sits at packed column xh = x/2 of row (y, z) in plane c.  Its
+// six neighbours all have the other colour: the same column of rows y+-1 and
+// planes z+-1, and in its own row the columns xh and xh-1 (x even) or xh and
+// xh+1 (x odd).  Each thread owns one (xh, y) column of a tile and walks the
+// tile's z range.
+// ---------------------------------------------------------------------------
+template <typename T, bool MEASURE, int MODE>
+__global__ void __launch_bounds__(256)
+k_sc_pass(PassLaunch P, int colour)
+{
+    const WorkItem w = P.work_dev[P.item_base + blockIdx.x];
+    const RepDev &R = P.reps_dev[w.rep];
+    const int Ly = R.Ly, Lz = R.Lz, Lxh = R.Lxh;
+    const int lx = threadIdx.x % P.tile.tx, ly = threadIdx.x / P.tile.tx;
+    const int xh = w.x0 + lx, y = w.y0 + ly;
+    const bool active = xh < Lxh && y < Ly && ly < P.tile.ty;
+    const uint32_t t = *P.tctr_dev + P.t_off;
+    const uint32_t plane = R.plane;
+    T *__restrict__ gx = (T *)R.sx;
+    T *__restrict__ gy = (T *)R.sy;
+    T *__restrict__ gz = (T *)R.sz;
+    const uint32_t own = colour ? plane : 0u, oth = colour ? 0u : plane;
+    const T J = (T)R.J, K = (T)R.K, ex = (T)R.e[0], ey = (T)R.e[1], ez = (T)R.e[2];
+    const T beta = (T)R.beta;
+    const bool greedy = R.greedy != 0;
+    const bool px = R.pmask & 1u, py = R.pmask & 2u, pz = R.pmask & 4u;
+
+    double acc[Q_N] = {0, 0, 0, 0, 0, 0};
+    if (active) {
+        // neighbour rows (y +- 1) with wrap or open face
+        const int ym = y > 0 ? y - 1 : (py ? Ly - 1 : -1);
+        const int yp = y < Ly - 1 ? y + 1 : (py ? 0 : -1);
+        const int xm = xh > 0 ? xh - 1 : (px ? Lxh - 1 : -1);
+        const int xp = xh < Lxh - 1 ? xh + 1 : (px ? 0 : -1);
+        const int z1 = min(w.z0 + P.tile.zc, Lz);
+        for (int z = w.z0; z < z1; ++z) {
+            const int p = (colour + y + z) & 1;
+            const int zm = z > 0 ? z - 1 : (pz ? Lz - 1 : -1);
+            const int zp = z < Lz - 1 ? z + 1 : (pz ? 0 : -1);
+            const uint32_t i = (uint32_t)(z * Ly + y) * Lxh + xh;
+            T hx = 0, hy = 0, hz = 0;
+            auto add = [&](int valid, uint32_t j) {
+                if (valid) {
+                    hx += gx[oth + j];
+                    hy += gy[oth + j];
+                    hz += gz[oth + j];
+                }
+            };
+            // fixed order: -z, -y, -x, +x, +y, +z
+            add(zm >= 0, (uint32_t)(zm * Ly + y) * Lxh + xh);
+            add(ym >= 0, (uint32_t)(z * Ly + ym) * Lxh + xh);
+            {
+                const int xl = p ? xh : xm; // x-1
+                const int xr = p ? xp : xh; // x+1
+                const uint32_t row = (uint32_t)(z * Ly + y) * Lxh;
+                add(xl >= 0, row + xl);
+                add(xr >= 0, row + xr);
+            }
+            add(yp >= 0, (uint32_t)(z * Ly + yp) * Lxh + xh);
+            add(zp >= 0, (uint32_t)(zp * Ly + y) * Lxh + xh);
+            hx *= J;
+            hy *= J;
+            hz *= J;
+            T sx = gx[own + i], sy = gy[own + i], sz = gz[own + i];
+            if (MODE == 0) {
+                const uint32_t s = (uint32_t)(z * Ly + y) * (uint32_t)R.Lx + 2u * xh + p;
+                T *dh = P.dbg_dh ? (T *)P.dbg_dh + own + i : nullptr;
+                const bool a = metropolis<T>(sx, sy, sz, hx, hy, hz, s, R.rid, t, P.seed_lo,
+                                             P.seed_hi, K, ex, ey, ez, beta, greedy, dh);
+                if (P.dbg_acc) P.dbg_acc[own + i] = a ? 1 : 0;
+                if (a) {
+                    gx[own + i] = sx;
+                    gy[own + i] = sy;
+                    gz[own + i] = sz;
+                }
+                if (MEASURE) acc[Q_NACC] += a ? 1.0 : 0.0;
+            }
+            if (MEASURE) {
+                const double dx = sx, dy = sy, dz = sz;
+                acc[Q_MX] += dx;
+                acc[Q_MY] += dy;
+                acc[Q_MZ] += dz;
+                const double pe = dx * (double)ex + dy * (double)ey + dz * (double)ez;
+                acc[Q_PE2] += pe * pe;
+                // every bond has exactly one colour-1 end: count it there,
+                // against colour-0 neighbours that are final after pass 0
+                if (colour == 1) acc[Q_SH] += dx * (double)hx + dy * (double)hy + dz * (double)hz;
+            }
+        }
+    }
+    if (MEASURE)
+        block_store_partials(acc, P.partials_dev +
+                                      ((size_t)colour * P.n_items + P.item_base + blockIdx.x) * NQ);
+}
+
+// ---------------------------------------------------------------------------
+// bcc / fcc: colour = basis site B, one dense plane per basis site.  The
+// neighbours of a B site in basis b2 sit at cell offsets o with o_a = 0 on
+// axes where the two basis vectors agree and o_a in {0, -sign(d_a)} where
+// they differ (d = basis(b2) - basis(B), half-cell units): 4 cells per other
+// basis for fcc, 8 for bcc.  Unoccupied sites hold zero, so the field sum is
+// branch-free inside the box.
+// ---------------------------------------------------------------------------
+template <int KIND, int B, typename T, bool MEASURE, int MODE>
+__global__ void __launch_bounds__(256)
+k_basis_pass(PassLaunch P)
+{
+    constexpr int NB = basis_count(KIND);
+    const WorkItem w = P.work_dev[P.item_base + blockIdx.x];
+    const RepDev &R = P.reps_dev[w.rep];
+    const int Lx = R.Lx, Ly = R.Ly, Lz = R.Lz;
+    const int lx = threadIdx.x % P.tile.tx, ly = threadIdx.x / P.tile.tx;
+    const int x = w.x0 + lx, y = w.y0 + ly;
+    const bool active = x < Lx && y < Ly && ly < P.tile.ty;
+    const uint32_t t = *P.tctr_dev + P.t_off;
+    const uint32_t plane = R.plane;
+    T *__restrict__ gx = (T *)R.sx;
+    T *__restrict__ gy = (T *)R.sy;
+    T *__restrict__ gz = (T *)R.sz;
+    const T J = (T)R.J, K = (T)R.K, ex = (T)R.e[0], ey = (T)R.e[1], ez = (T)R.e[2];
+    const T beta = (T)R.beta;
+    const bool greedy = R.greedy != 0;
+    const bool pxm = R.pmask & 1u, pym = R.pmask & 2u, pzm = R.pmask & 4u;
+    constexpr int bx = basis2(KIND, B, 0), by = basis2(KIND, B, 1), bz = basis2(KIND, B, 2);
+
+    double acc[Q_N] = {0, 0, 0, 0, 0, 0};
+    if (active) {
+        const int z1 = min(w.z0 + P.tile.zc, Lz);
+        for (int z = w.z0; z < z1; ++z) {
+            if (!occupied(R, x, y, z, bx, by, bz)) continue;
+            const uint32_t cell = (uint32_t)(z * Ly + y) * Lx + x;
+            T hx = 0, hy = 0, hz = 0;    // all neighbours
+            T lx_ = 0, ly_ = 0, lz_ = 0; // neighbours of lower colour (final)
+#pragma unroll
+            for (int b2 = 0; b2 < NB; ++b2) {
+                if (b2 == B) continue;
+                const int dx = basis2(KIND, b2, 0) - bx;
+                const int dy = basis2(KIND, b2, 1) - by;
+                const int dz = basis2(KIND, b2, 2) - bz;
+                const int nox = dx ? 2 : 1, noy = dy ? 2 : 1, noz = dz ? 2 : 1;
+                T ax = 0, ay = 0, az = 0;
+#pragma unroll
+                for (int iz = 0; iz < noz; ++iz)
+#pragma unroll
+                    for (int iy = 0; iy < noy; ++iy)
+#pragma unroll
+                        for (int ix = 0; ix < nox; ++ix) {
+                            int cx = x - ix * dx, cy = y - iy * dy, cz = z - iz * dz;
+                            bool ok = true;
+                            if (cx < 0) { cx += Lx; ok &= pxm; }
+                            if (cx >= Lx) { cx -= Lx; ok &= pxm; }
+                            if (cy < 0) { cy += Ly; ok &= pym; }
+                            if (cy >= Ly) { cy -= Ly; ok &= pym; }
+                            if (cz < 0) { cz += Lz; ok &= pzm; }
+                            if (cz >= Lz) { cz -= Lz; ok &= pzm; }
+                            if (ok) {
+                                const uint32_t j = (uint32_t)b2 * plane +
+                                                   (uint32_t)(cz * Ly + cy) * Lx + cx;
+                                ax += gx[j];
+                                ay += gy[j];
+                                az += gz[j];
+                            }
+                        }
+                hx += ax;
+                hy += ay;
+                hz += az;
+                if (b2 < B) {
+                    lx_ += ax;
+                    ly_ += ay;
+                    lz_ += az;
+                }
+            }
+            hx *= J;
+            hy *= J;
+            hz *= J;
+            const uint32_t i = (uint32_t)B * plane + cell;
+            T sx = gx[i], sy = gy[i], sz = gz[i];
+            if (MODE == 0) {
+                const uint32_t s = cell * NB + B;
+                T *dh = P.dbg_dh ? (T *)P.dbg_dh + i : nullptr;
+                const bool a = metropolis<T>(sx, sy, sz, hx, hy, hz, s, R.rid, t, P.seed_lo,
+                                             P.seed_hi, K, ex, ey, ez, beta, greedy, dh);
+                if (P.dbg_acc) P.dbg_acc[i] = a ? 1 : 0;
+                if (a) {
+                    gx[i] = sx;
+                    gy[i] = sy;
+                    gz[i] = sz;
+                }
+                if (MEASURE) acc[Q_NACC] += a ? 1.0 : 0.0;
+            }
+            if (MEASURE) {
+                const double dsx = sx, dsy = sy, dsz = sz;
+                acc[Q_MX] += dsx;
+                acc[Q_MY] += dsy;
+                acc[Q_MZ] += dsz;
+                const double pe = dsx * (double)ex + dsy * (double)ey + dsz * (double)ez;
+                acc[Q_PE2] += pe * pe;
+                // bonds to lower colours, whose spins are final after their pass
+                acc[Q_SH] += (double)J * (dsx * (double)lx_ + dsy * (double)ly_ + dsz * (double)lz_);
+            }
+        }
+    }
+    if (MEASURE)
+        block_store_partials(acc, P.partials_dev +
+                                      ((size_t)B * P.n_items + P.item_base + blockIdx.x) * NQ);
+}
+
+// ---------------------------------------------------------------------------
+// Initial state and layout conversion (one replica per launch).
+// ---------------------------------------------------------------------------
+struct SiteCoord {
+    int x, y, z, b;
+    uint32_t s; // canonical index
+};
+
+__device__ __forceinline__ SiteCoord decode(const RepDev &R, int kind, uint32_t i)
+{
+    SiteCoord c;
+    const uint32_t colour = i / R.plane, j = i - colour * R.plane;
+    if (kind == SC) {
+        const uint32_t xh = j % (uint32_t)R.Lxh, r = j / (uint32_t)R.Lxh;
+        c.y = (int)(r % (uint32_t)R.Ly);
+        c.z = (int)(r / (uint32_t)R.Ly);
+        c.x = 2 * (int)xh + (int)((colour + c.y + c.z) & 1u);
+        c.b = 0;
+        c.s = (uint32_t)(c.z * R.Ly + c.y) * (uint32_t)R.Lx + c.x;
+    } else {
+        c.x = (int)(j % (uint32_t)R.Lx);
+        const uint32_t r = j / (uint32_t)R.Lx;
+        c.y = (int)(r % (uint32_t)R.Ly);
+        c.z = (int)(r / (uint32_t)R.Ly);
+        c.b = (int)colour;
+        c.s = j * (uint32_t)basis_count(kind) + colour;
+    }
+    return c;
+}
+
+__device__ __forceinline__ bool occupied_site(const RepDev &R, int kind, const SiteCoord &c)
+{
+    int bx = 0, by = 0, bz = 0;
+    if (kind == BCC) bx = by = bz = c.b;
+    if (kind == FCC) {
+        bx = c.b == 1 || c.b == 2;
+        by = c.b == 1 || c.b == 3;
+        bz = c.b == 2 || c.b == 3;
+    }
+    return occupied(R, c.x, c.y, c.z, bx, by, bz);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_init(RepDev R, int kind, int mode, uint32_t k0, uint32_t k1)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < R.n_box;
+         i += gridDim.x * blockDim.x) {
+        const SiteCoord c = decode(R, kind, i);
+        T vx = 0, vy = 0, vz = 0;
+        if (occupied_site(R, kind, c)) {
+            if (mode == 1) {
+                vx = (T)R.e[0];
+                vy = (T)R.e[1];
+                vz = (T)R.e[2];
+            } else {
+                const Words w = philox10(c.s, R.rid, 0u, 1u, k0, k1);
+                sphere_point(uniform23<T>(w.w0), uniform23<T>(w.w1), vx, vy, vz);
+            }
+        }
+        ((T *)R.sx)[i] = vx;
+        ((T *)R.sy)[i] = vy;
+        ((T *)R.sz)[i] = vz;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_layout(RepDev R, int kind, int to_natural, T *nx, T *ny, T *nz)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < R.n_box;
+         i += gridDim.x * blockDim.x) {
+        const SiteCoord c = decode(R, kind, i);
+        T *px = (T *)R.sx, *py = (T *)R.sy, *pz = (T *)R.sz;
+        if (to_natural) {
+            nx[c.s] = px[i];
+            ny[c.s] = py[i];
+            nz[c.s] = pz[i];
+        } else {
+            px[i] = nx[c.s];
+            py[i] = ny[c.s];
+            pz[i] = nz[c.s];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Finalise: one block per replica sums its partial slots of every pass in a
+// fixed order and writes one FP64 record.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_finalize(const RepDev *__restrict__ reps, int n_colours, const double *__restrict__ partials,
+           uint32_t n_items, const uint32_t *__restrict__ tctr, uint32_t t_off,
+           double *__restrict__ records)
+{
+    const RepDev &R = reps[blockIdx.x];
+    double a[Q_N] = {0, 0, 0, 0, 0, 0};
+    for (int c = 0; c < n_colours; ++c)
+        for (uint32_t it = R.item_begin + threadIdx.x; it < R.item_end; it += blockDim.x) {
+            const double *p = partials + ((size_t)c * n_items + it) * NQ;
+#pragma unroll
+            for (int q = 0; q < Q_N; ++q) a[q] += p[q];
+        }
+    __shared__ double out[NQ];
+    block_store_partials(a, out);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double *r = records + (size_t)blockIdx.x * NR;
+        r[R_MX] = out[Q_MX];
+        r[R_MY] = out[Q_MY];
+        r[R_MZ] = out[Q_MZ];
+        r[R_EEX] = -out[Q_SH];
+        r[R_EAN] = -R.K * out[Q_PE2];
+        r[R_NACC] = out[Q_NACC];
+        r[R_SWEEP] = (double)(*tctr + t_off) + 1.0;
+        r[7] = 0.0;
+    }
+}
+
+__global__ void k_advance(uint32_t *tctr, uint32_t n)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *tctr += n;
+}
+
+__global__ void k_set_counter(uint32_t *tctr, uint32_t v)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *tctr = v;
+}
+
+__global__ void k_fill_zero(double *p, uint64_t n)
+{
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+template <typename T, bool MEASURE, int MODE>
+static hipError_t sc_launch(int colour, const PassLaunch &p, hipStream_t st)
+{
+    const int threads = ((p.tile.tx * p.tile.ty + 63) / 64) * 64;
+    hipLaunchKernelGGL((k_sc_pass<T, MEASURE, MODE>), dim3(p.n_blocks), dim3(threads), 0, st, p,
+                       colour);
+    return hipGetLastError();
+}
+
+template <int KIND, typename T, bool MEASURE, int MODE>
+static hipError_t basis_launch(int colour, const PassLaunch &p, hipStream_t st)
+{
+    const int threads = ((p.tile.tx * p.tile.ty + 63) / 64) * 64;
+    const dim3 g(p.n_blocks), b(threads);
+    switch (colour) {
+    case 0: hipLaunchKernelGGL((k_basis_pass<KIND, 0, T, MEASURE, MODE>), g, b, 0, st, p); break;
+    case 1: hipLaunchKernelGGL((k_basis_pass<KIND, 1, T, MEASURE, MODE>), g, b, 0, st, p); break;
+    case 2:
+        if constexpr (KIND == FCC) hipLaunchKernelGGL((k_basis_pass<KIND, 2, T, MEASURE, MODE>), g, b, 0, st, p);
+        break;
+    case 3:
+        if constexpr (KIND == FCC) hipLaunchKernelGGL((k_basis_pass<KIND, 3, T, MEASURE, MODE>), g, b, 0, st, p);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T, bool MEASURE, int MODE>
+static hipError_t pass_dispatch(int kind, int colour, const PassLaunch &p, hipStream_t st)
+{
+    switch (kind) {
+    case SC: return sc_launch<T, MEASURE, MODE>(colour, p, st);
+    case BCC: return basis_launch<BCC, T, MEASURE, MODE>(colour, p, st);
+    case FCC: return basis_launch<FCC, T, MEASURE, MODE>(colour, p, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_pass(int kind, bool f64, int colour, bool measure, int mode, const PassLaunch &p,
+                       hipStream_t st)
+{
+    if (p.n_blocks == 0) return hipSuccess;
+    if (mode == 1) {
+        return f64 ? pass_dispatch<double, true, 1>(kind, colour, p, st)
+                   : pass_dispatch<float, true, 1>(kind, colour, p, st);
+    }
+    if (f64)
+        return measure ? pass_dispatch<double, true, 0>(kind, colour, p, st)
+                       : pass_dispatch<double, false, 0>(kind, colour, p, st);
+    return measure ? pass_dispatch<float, true, 0>(kind, colour, p, st)
+                   : pass_dispatch<float, false, 0>(kind, colour, p, st);
+}
+
+static unsigned grid_for(uint32_t n)
+{
+    uint32_t g = (n + 255) / 256;
+    return g < 8192 ? (g ? g : 1) : 8192;
+}
+
+hipError_t launch_init(bool f64, int kind, const RepDev *rep_host, int mode, uint32_t seed_lo,
+                       uint32_t seed_hi, hipStream_t st)
+{
+    const unsigned g = grid_for(rep_host->n_box);
+    if (f64)
+        hipLaunchKernelGGL((k_init<double>), dim3(g), dim3(256), 0, st, *rep_host, kind, mode,
+                           seed_lo, seed_hi);
+    else
+        hipLaunchKernelGGL((k_init<float>), dim3(g), dim3(256), 0, st, *rep_host, kind, mode,
+                           seed_lo, seed_hi);
+    return hipGetLastError();
+}
+
+hipError_t launch_layout(bool f64, int kind, const RepDev *rep_host, bool to_natural, void *nx,
+                         void *ny, void *nz, hipStream_t st)
+{
+    const unsigned g = grid_for(rep_host->n_box);
+    if (f64)
+        hipLaunchKernelGGL((k_layout<double>), dim3(g), dim3(256), 0, st, *rep_host, kind,
+                           (int)to_natural, (double *)nx, (double *)ny, (double *)nz);
+    else
+        hipLaunchKernelGGL((k_layout<float>), dim3(g), dim3(256), 0, st, *rep_host, kind,
+                           (int)to_natural, (float *)nx, (float *)ny, (float *)nz);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const RepDev *reps_dev, int n_reps, int n_colours,
+                           const double *partials_dev, uint32_t n_items,
+                           const uint32_t *tctr_dev, uint32_t t_off, double *records_dev,
+                           hipStream_t st)
+{
+    hipLaunchKernelGGL(k_finalize, dim3(n_reps), dim3(256), 0, st, reps_dev, n_colours,
+                       partials_dev, n_items, tctr_dev, t_off, records_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance(uint32_t *tctr_dev, uint32_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, st, tctr_dev, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_counter(uint32_t *tctr_dev, uint32_t v, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_set_counter, dim3(1), dim3(64), 0, st, tctr_dev, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(double *p, uint64_t n, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    const unsigned g = grid_for((uint32_t)(n < 0xFFFFFFFFull ? n : 0xFFFFFFFFull));
+    hipLaunchKernelGGL(k_fill_zero, dim3(g), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
+} // namespace mc

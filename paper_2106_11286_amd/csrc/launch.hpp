@@ -1,0 +1,47 @@
+// launch.hpp -- host-callable launchers of the device kernels (kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+#include "mc_internal.hpp"
+
+namespace mc {
+
+// Everything a pass launch needs; device pointers point into the scratch.
+struct PassLaunch {
+    const RepDev *reps_dev;   // [n_reps]
+    const WorkItem *work_dev; // [n_items]
+    uint32_t item_base;       // first work item of this launch
+    uint32_t n_blocks;        // work items in this launch
+    uint32_t n_items;         // items in the whole work list (partials stride)
+    const uint32_t *tctr_dev; // sweep counter t (device)
+    uint32_t t_off;           // added to t
+    uint32_t seed_lo, seed_hi;
+    Tile tile;
+    double *partials_dev;     // [n_colours][n_items][NQ]
+    void *dbg_dh;             // debug: per-site dH (or null)
+    uint8_t *dbg_acc;         // debug: per-site decision (or null)
+};
+
+// mode: 0 = Metropolis update, 1 = observables of the current state only
+hipError_t launch_pass(int kind, bool f64, int colour, bool measure, int mode,
+                       const PassLaunch &p, hipStream_t st);
+
+hipError_t launch_init(bool f64, int kind, const RepDev *rep_host, int mode, uint32_t seed_lo,
+                       uint32_t seed_hi, hipStream_t st);
+
+hipError_t launch_layout(bool f64, int kind, const RepDev *rep_host, bool to_natural, void *nx,
+                         void *ny, void *nz, hipStream_t st);
+
+// Reduce partials of every pass into one record per replica.
+hipError_t launch_finalize(const RepDev *reps_dev, int n_reps, int n_colours,
+                           const double *partials_dev, uint32_t n_items,
+                           const uint32_t *tctr_dev, uint32_t t_off, double *records_dev,
+                           hipStream_t st);
+
+hipError_t launch_advance(uint32_t *tctr_dev, uint32_t n, hipStream_t st);
+hipError_t launch_set_counter(uint32_t *tctr_dev, uint32_t v, hipStream_t st);
+hipError_t launch_fill_zero(double *p, uint64_t n, hipStream_t st);
+
+} // namespace mc

@@ -1,0 +1,49 @@
+// mc_internal.hpp -- structures shared by the host runtime (abi.cpp) and the
+// device kernels (kernels.hip).  Plain-old-data only: copied verbatim into the
+// caller's scratch buffer.
+#pragma once
+
+#include <stdint.h>
+
+namespace mc {
+
+enum Kind : int32_t { SC = 0, BCC = 1, FCC = 2 };
+
+// Per-replica descriptor as the kernels see it (lives in device scratch).
+struct alignas(16) RepDev {
+    void *sx, *sy, *sz;       // colour-major planes (library layout)
+    int32_t Lx, Ly, Lz;       // cells
+    int32_t Lxh;              // sc: Lx/2 (packed row length); basis kinds: Lx
+    uint32_t pmask;           // periodic axes
+    uint32_t rid;             // replica id (Philox counter word 1)
+    uint32_t n_box;           // sites in the box (all colours)
+    uint32_t plane;           // elements per colour (sc: N/2, basis: Lx*Ly*Lz)
+    double J, K;
+    double e[3];              // unit easy axis
+    double beta;              // 1/T (0 for T = +inf)
+    int32_t greedy;           // T == 0
+    int32_t sphere;           // 1 if a sphere mask applies
+    double r2x4;              // 4 R^2 (half-cell units squared)
+    uint32_t item_begin, item_end; // this replica's range in the work list
+};
+
+// One workgroup's work: replica and the origin of its tile.
+struct alignas(16) WorkItem {
+    uint32_t rep;
+    int32_t x0, y0, z0;
+};
+
+// Observable slots accumulated per workgroup and pass (FP64).
+enum : int { Q_MX = 0, Q_MY, Q_MZ, Q_PE2, Q_SH, Q_NACC, Q_N };
+constexpr int NQ = 8; // padded slot width (doubles)
+
+// Record written by the finalise kernel (FP64), per replica per measured sweep.
+enum : int { R_MX = 0, R_MY, R_MZ, R_EEX, R_EAN, R_NACC, R_SWEEP, R_N };
+constexpr int NR = 8;
+
+// Tile shape (threads TX x TY per workgroup, ZC planes streamed per thread).
+struct Tile {
+    int32_t tx, ty, zc;
+};
+
+} // namespace mc

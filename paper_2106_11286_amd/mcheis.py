@@ -1,0 +1,392 @@
+"""Python binding of ``libmcheis.so`` (the C ABI in ``include/mcheis.h``).
+
+Argument marshalling only: every step of the sweep runs in the library's HIP
+kernels.  PyTorch supplies device memory (spin planes, scratch) and the HIP
+stream.  If the built library is missing, importing this module raises.
+
+Model: Eq. (1) of arXiv:2106.11286 (anisotropic classical Heisenberg
+Hamiltonian); dynamics: single-spin Metropolis by sublattice colour; the
+magnetisation follows Eq. (2).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch  # loads the HIP runtime the library binds to
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmcheis.so")
+
+SC, BCC, FCC = 0, 1, 2
+F32, F64 = 0, 1
+INIT_RANDOM, INIT_ALIGNED, INIT_USER = 0, 1, 2
+MEASURE = 1
+STATUS = {0: "MC_OK", -1: "MC_E_ARG", -2: "MC_E_UNSUPPORTED", -3: "MC_E_BUFFER",
+          -4: "MC_E_DEVICE", -5: "MC_E_STATE"}
+KINDS = {"sc": SC, "bcc": BCC, "fcc": FCC}
+
+
+class MCError(RuntimeError):
+    def __init__(self, func, status, message):
+        super().__init__(f"{func}: {STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class ReplicaDesc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("Lx", ctypes.c_int32), ("Ly", ctypes.c_int32),
+                ("Lz", ctypes.c_int32), ("periodic_mask", ctypes.c_uint32),
+                ("replica_id", ctypes.c_uint32), ("sphere_radius", ctypes.c_double),
+                ("J", ctypes.c_double), ("K", ctypes.c_double), ("e", ctypes.c_double * 3),
+                ("T", ctypes.c_double)]
+
+
+class SpinBuffers(ctypes.Structure):
+    _fields_ = [("sx", ctypes.c_void_p), ("sy", ctypes.c_void_p), ("sz", ctypes.c_void_p),
+                ("capacity_sites", ctypes.c_uint64)]
+
+
+class Obs(ctypes.Structure):
+    _fields_ = [("sweep", ctypes.c_uint64), ("n_sites", ctypes.c_uint64),
+                ("n_accepted", ctypes.c_uint64), ("M", ctypes.c_double * 3),
+                ("absM", ctypes.c_double), ("E", ctypes.c_double), ("E_exch", ctypes.c_double),
+                ("E_anis", ctypes.c_double)]
+
+
+class Schedule(ctypes.Structure):
+    _fields_ = [("n_T", ctypes.c_int32), ("T", ctypes.POINTER(ctypes.c_double)),
+                ("n_equil", ctypes.c_uint32), ("n_meas", ctypes.c_uint32),
+                ("measure_every", ctypes.c_uint32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64)] + [(k, ctypes.c_double) for k in (
+        "abs_m", "abs_m_err", "m2", "m2_err", "m4", "m4_err", "e", "e_err", "U4", "C", "chi",
+        "acceptance")]
+
+
+# Every exported symbol with its argument types (checked against the header in
+# the CPU test suite).
+_SIGNATURES = {
+    "mc_required_sites": (ctypes.c_int, [ctypes.POINTER(ReplicaDesc), ctypes.POINTER(ctypes.c_uint64)]),
+    "mc_occupied_sites": (ctypes.c_int, [ctypes.POINTER(ReplicaDesc), ctypes.POINTER(ctypes.c_uint64)]),
+    "mc_required_scratch": (ctypes.c_int, [ctypes.POINTER(ReplicaDesc), ctypes.c_int32,
+                                           ctypes.POINTER(ctypes.c_uint64)]),
+    "mc_init_lattice": (ctypes.c_int, [ctypes.POINTER(ReplicaDesc), ctypes.c_int32, ctypes.c_int,
+                                       ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(SpinBuffers),
+                                       ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
+                                       ctypes.POINTER(ctypes.c_void_p)]),
+    "mc_sweep": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32]),
+    "mc_sweep_timed": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
+                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    "mc_observables": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Obs), ctypes.c_int32]),
+    "mc_measure_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Obs), ctypes.c_int32]),
+    "mc_run_schedule": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Schedule), ctypes.POINTER(Obs),
+                                       ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]),
+    "mc_set_temperatures": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.c_int32]),
+    "mc_debug_pass": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32,
+                                     ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p)]),
+    "mc_layout_copy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_void_p]),
+    "mc_set_tile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "mc_get_tile": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                   ctypes.POINTER(ctypes.c_uint64)]),
+    "mc_get_sweep": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
+    "mc_set_sweep": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
+    "mc_num_colours": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
+    "mc_series_stats": (ctypes.c_int, [ctypes.POINTER(Obs), ctypes.c_uint64, ctypes.c_uint64,
+                                       ctypes.c_double, ctypes.POINTER(Stats)]),
+    "mc_destroy": (None, [ctypes.c_void_p]),
+    "mc_last_error": (ctypes.c_char_p, []),
+    "mc_version": (ctypes.c_char_p, []),
+}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_2106_11286_amd.build` "
+            "(there is no fallback implementation)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+LIB = _load()
+
+
+def _check(name, status):
+    if status != 0:
+        raise MCError(name, status, LIB.mc_last_error().decode())
+
+
+def last_error() -> str:
+    return LIB.mc_last_error().decode()
+
+
+def version() -> str:
+    return LIB.mc_version().decode()
+
+
+@dataclass
+class Replica:
+    """One lattice replica (see ``mc_replica_desc``)."""
+    kind: str = "sc"
+    L: Sequence[int] = (16, 16, 16)
+    periodic_mask: int = 7
+    sphere_radius: float = 0.0
+    J: float = 1.0
+    K: float = 0.0
+    e: Sequence[float] = (0.0, 0.0, 1.0)
+    T: float = 1.0
+    replica_id: int = 0
+
+    def desc(self) -> ReplicaDesc:
+        d = ReplicaDesc()
+        d.kind = KINDS[self.kind] if isinstance(self.kind, str) else int(self.kind)
+        L = list(self.L) if not isinstance(self.L, int) else [self.L] * 3
+        d.Lx, d.Ly, d.Lz = int(L[0]), int(L[1]), int(L[2])
+        d.periodic_mask = int(self.periodic_mask)
+        d.replica_id = int(self.replica_id)
+        d.sphere_radius = float(self.sphere_radius)
+        d.J, d.K, d.T = float(self.J), float(self.K), float(self.T)
+        for i in range(3):
+            d.e[i] = float(self.e[i])
+        return d
+
+
+def required_sites(rep: Replica) -> int:
+    n = ctypes.c_uint64()
+    d = rep.desc()
+    _check("mc_required_sites", LIB.mc_required_sites(ctypes.byref(d), ctypes.byref(n)))
+    return int(n.value)
+
+
+def occupied_sites(rep: Replica) -> int:
+    n = ctypes.c_uint64()
+    d = rep.desc()
+    _check("mc_occupied_sites", LIB.mc_occupied_sites(ctypes.byref(d), ctypes.byref(n)))
+    return int(n.value)
+
+
+def required_scratch(reps: Sequence[Replica]) -> int:
+    arr = (ReplicaDesc * len(reps))(*[r.desc() for r in reps])
+    n = ctypes.c_uint64()
+    _check("mc_required_scratch", LIB.mc_required_scratch(arr, len(reps), ctypes.byref(n)))
+    return int(n.value)
+
+
+def obs_to_dict(o: Obs) -> dict:
+    return {"sweep": int(o.sweep), "n_sites": int(o.n_sites), "n_accepted": int(o.n_accepted),
+            "M": np.array(o.M[:]), "absM": o.absM, "E": o.E, "E_exch": o.E_exch,
+            "E_anis": o.E_anis}
+
+
+def obs_array_to_numpy(arr, n) -> np.ndarray:
+    """(n, 10) float64: sweep, n_accepted, Mx, My, Mz, |M|, E, E_exch, E_anis, n_sites."""
+    out = np.empty((n, 10))
+    for i in range(n):
+        o = arr[i]
+        out[i] = (o.sweep, o.n_accepted, o.M[0], o.M[1], o.M[2], o.absM, o.E, o.E_exch,
+                  o.E_anis, o.n_sites)
+    return out
+
+
+class Simulation:
+    """A handle over one or more replicas of one lattice kind (``mc_init_lattice``).
+
+    Spin planes and scratch are torch tensors on ``device``; all work runs on
+    ``stream`` (a dedicated ``torch.cuda.Stream`` by default, so schedules can
+    be replayed as HIP graphs)."""
+
+    def __init__(self, replicas: Sequence[Replica], precision: str = "f32", seed: int = 0,
+                 init: str = "random", device: str = "cuda:0", stream=None,
+                 user_spins: Optional[List] = None, scratch: Optional[torch.Tensor] = None):
+        if not torch.cuda.is_available():
+            raise MCError("mc_init_lattice", -4, "no GPU visible to torch")
+        self.replicas = list(replicas)
+        self.n_reps = len(self.replicas)
+        self.prec = F64 if precision in ("f64", "fp64", F64) else F32
+        self.dtype = torch.float64 if self.prec == F64 else torch.float32
+        self.device = torch.device(device)
+        self.seed = int(seed)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        self.sites = [required_sites(r) for r in self.replicas]
+        self.n_occ = [occupied_sites(r) for r in self.replicas]
+        self.spins = [[torch.zeros(n, dtype=self.dtype, device=self.device) for _ in range(3)]
+                      for n in self.sites]
+        nbytes = required_scratch(self.replicas)
+        if scratch is None:
+            scratch = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.scratch = scratch
+        self._descs = (ReplicaDesc * self.n_reps)(*[r.desc() for r in self.replicas])
+        bufs = (SpinBuffers * self.n_reps)()
+        for i, (pl, n) in enumerate(zip(self.spins, self.sites)):
+            bufs[i].sx, bufs[i].sy, bufs[i].sz = pl[0].data_ptr(), pl[1].data_ptr(), pl[2].data_ptr()
+            bufs[i].capacity_sites = n
+        mode = {"random": INIT_RANDOM, "aligned": INIT_ALIGNED, "user": INIT_USER}[init]
+        torch.cuda.synchronize(self.device)
+        h = ctypes.c_void_p()
+        _check("mc_init_lattice",
+               LIB.mc_init_lattice(self._descs, self.n_reps, self.prec,
+                                   ctypes.c_uint64(self.seed & (2**64 - 1)), mode, bufs,
+                                   ctypes.c_void_p(self.scratch.data_ptr()),
+                                   self.scratch.numel(), ctypes.c_void_p(self.stream.cuda_stream),
+                                   ctypes.byref(h)))
+        self._h = h
+        if user_spins is not None:
+            for r, xyz in enumerate(user_spins):
+                self.from_natural(r, xyz)
+
+    # -- lifetime --------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            LIB.mc_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise MCError("handle", -5, "simulation was closed")
+        return self._h
+
+    # -- the four entry points --------------------------------------------
+    def sweep(self, n: int = 1, measure: bool = False):
+        """``mc_sweep``: enqueue n sweeps (asynchronous)."""
+        _check("mc_sweep", LIB.mc_sweep(self.handle, int(n), MEASURE if measure else 0))
+
+    def sweep_timed(self, n: int, measure: bool = False):
+        """``mc_sweep_timed``: (mean ms per colour-pass launch, total ms)."""
+        a, b = ctypes.c_double(), ctypes.c_double()
+        _check("mc_sweep_timed", LIB.mc_sweep_timed(self.handle, int(n), MEASURE if measure else 0,
+                                                    ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def observables(self) -> List[dict]:
+        """``mc_observables``: records of the last measured sweep."""
+        out = (Obs * self.n_reps)()
+        _check("mc_observables", LIB.mc_observables(self.handle, out, self.n_reps))
+        return [obs_to_dict(o) for o in out]
+
+    def measure_state(self) -> List[dict]:
+        out = (Obs * self.n_reps)()
+        _check("mc_measure_state", LIB.mc_measure_state(self.handle, out, self.n_reps))
+        return [obs_to_dict(o) for o in out]
+
+    def run_schedule(self, T, n_equil: int, n_meas: int, measure_every: int = 1) -> np.ndarray:
+        """``mc_run_schedule``: T is (n_T,) or (n_T, n_reps).  Returns an array
+        (n_T, n_rec, n_reps, 10) of records (see ``obs_array_to_numpy``)."""
+        T = np.asarray(T, dtype=np.float64)
+        if T.ndim == 1:
+            T = np.repeat(T[:, None], self.n_reps, axis=1)
+        T = np.ascontiguousarray(T)
+        n_T = T.shape[0]
+        n_rec = n_meas // measure_every
+        cap = n_T * n_rec * self.n_reps
+        series = (Obs * max(cap, 1))()
+        s = Schedule()
+        s.n_T = n_T
+        s.T = T.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        s.n_equil, s.n_meas, s.measure_every = int(n_equil), int(n_meas), int(measure_every)
+        nw = ctypes.c_uint64()
+        _check("mc_run_schedule", LIB.mc_run_schedule(self.handle, ctypes.byref(s), series, cap,
+                                                      ctypes.byref(nw)))
+        self.last_series = series
+        return obs_array_to_numpy(series, int(nw.value)).reshape(n_T, n_rec, self.n_reps, 10)
+
+    # -- helpers -----------------------------------------------------------
+    def set_temperatures(self, T):
+        arr = (ctypes.c_double * self.n_reps)(*[float(v) for v in np.broadcast_to(T, (self.n_reps,))])
+        _check("mc_set_temperatures", LIB.mc_set_temperatures(self.handle, arr, self.n_reps))
+
+    def num_colours(self) -> int:
+        n = ctypes.c_int32()
+        _check("mc_num_colours", LIB.mc_num_colours(self.handle, ctypes.byref(n)))
+        return int(n.value)
+
+    def get_sweep(self) -> int:
+        t = ctypes.c_uint64()
+        _check("mc_get_sweep", LIB.mc_get_sweep(self.handle, ctypes.byref(t)))
+        return int(t.value)
+
+    def set_sweep(self, t: int):
+        _check("mc_set_sweep", LIB.mc_set_sweep(self.handle, int(t)))
+
+    def set_tile(self, tx: int, ty: int, zc: int):
+        _check("mc_set_tile", LIB.mc_set_tile(self.handle, int(tx), int(ty), int(zc)))
+
+    def get_tile(self):
+        a, b, c, n = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_uint64()
+        _check("mc_get_tile", LIB.mc_get_tile(self.handle, ctypes.byref(a), ctypes.byref(b),
+                                              ctypes.byref(c), ctypes.byref(n)))
+        return int(a.value), int(b.value), int(c.value), int(n.value)
+
+    def debug_pass(self, colour: int):
+        """``mc_debug_pass``: one colour pass at the current counter; returns
+        per-replica (dH, accepted) tensors in the spin layout."""
+        dh = [torch.full((n,), float("nan"), dtype=self.dtype, device=self.device)
+              for n in self.sites]
+        acc = [torch.full((n,), 255, dtype=torch.uint8, device=self.device) for n in self.sites]
+        torch.cuda.synchronize(self.device)
+        pd = (ctypes.c_void_p * self.n_reps)(*[t.data_ptr() for t in dh])
+        pa = (ctypes.c_void_p * self.n_reps)(*[t.data_ptr() for t in acc])
+        _check("mc_debug_pass", LIB.mc_debug_pass(self.handle, int(colour), pd, pa))
+        return dh, acc
+
+    def to_natural(self, replica: int = 0):
+        """Spins of one replica in natural order (x, y, z component tensors)."""
+        n = self.sites[replica]
+        out = [torch.empty(n, dtype=self.dtype, device=self.device) for _ in range(3)]
+        torch.cuda.synchronize(self.device)
+        _check("mc_layout_copy", LIB.mc_layout_copy(self.handle, replica, 1, *[t.data_ptr() for t in out]))
+        return out
+
+    def from_natural(self, replica: int, xyz):
+        """Set one replica's spins from natural-order components (arrays or tensors)."""
+        n = self.sites[replica]
+        src = [torch.as_tensor(np.asarray(a) if not torch.is_tensor(a) else a, dtype=self.dtype)
+               .to(self.device).contiguous() for a in xyz]
+        for t in src:
+            if t.numel() != n:
+                raise ValueError(f"expected {n} sites, got {t.numel()}")
+        torch.cuda.synchronize(self.device)
+        _check("mc_layout_copy", LIB.mc_layout_copy(self.handle, replica, 0, *[t.data_ptr() for t in src]))
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+
+def init_lattice(replicas, **kw) -> Simulation:
+    """``mc_init_lattice``: create a Simulation (see ``Simulation``)."""
+    return Simulation(replicas, **kw)
+
+
+def series_stats(records: np.ndarray, n_sites: int, T: float) -> dict:
+    """``mc_series_stats`` over an (n, 10) record array of one replica."""
+    n = records.shape[0]
+    arr = (Obs * n)()
+    for i, r in enumerate(records):
+        arr[i].sweep = int(r[0])
+        arr[i].n_accepted = int(r[1])
+        for a in range(3):
+            arr[i].M[a] = r[2 + a]
+        arr[i].absM, arr[i].E, arr[i].E_exch, arr[i].E_anis = r[5], r[6], r[7], r[8]
+        arr[i].n_sites = int(n_sites)
+    st = Stats()
+    _check("mc_series_stats", LIB.mc_series_stats(arr, n, 1, float(T), ctypes.byref(st)))
+    return {k: getattr(st, k) for k, _ in Stats._fields_}

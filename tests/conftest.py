@@ -3,6 +3,11 @@ import sys
 
 import pytest
 
+try:  # load the HIP runtime before the library (and off the per-test timers)
+    import torch  # noqa: F401
+except ImportError:  # pragma: no cover
+    torch = None
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)

@@ -1,0 +1,308 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 CPU oracle.
+
+Bars:
+  * FP64 path: same chain as the oracle; per-sweep magnetisation within 1e-12,
+    energy within 1e-10 relative, identical accepted-move counts (a decision
+    flip needs |beta dH + ln P| below rounding, odds ~1e-15 per attempt).
+  * FP32 path, one colour pass from an identical FP32-representable state:
+    |dH32 - dH64| <= 1e-5 max(|dH64|, J); decisions equal unless
+    |beta dH64 + ln P| < 1e-4; accepted spins within 2e-6.
+  * Spins are bitwise independent of tile shape, batching and resume.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2106_11286_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+KIND = {"sc": O.SC, "bcc": O.BCC, "fcc": O.FCC}
+
+
+@pytest.fixture(scope="module")
+def M():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    from paper_2106_11286_amd import mcheis
+
+    return mcheis
+
+
+def oracle_lattice(rep):
+    L = rep.L if not isinstance(rep.L, int) else (rep.L,) * 3
+    return O.Lattice(KIND[rep.kind], *L, periodic_mask=rep.periodic_mask,
+                     sphere_radius=rep.sphere_radius)
+
+
+def oracle_params(rep, seed):
+    return O.Params(J=rep.J, K=rep.K, e=rep.e, T=rep.T, seed=seed, replica_id=rep.replica_id)
+
+
+def natural(sim, r=0):
+    return [t.double().cpu().numpy() for t in sim.to_natural(r)]
+
+
+def packed_index(rep):
+    """Library layout index of every canonical site (the ABI's layout rule)."""
+    L = rep.L if not isinstance(rep.L, int) else (rep.L,) * 3
+    Lx, Ly, Lz = L
+    nb = {"sc": 1, "bcc": 2, "fcc": 4}[rep.kind]
+    s = np.arange(Lx * Ly * Lz * nb)
+    if rep.kind == "sc":
+        x = s % Lx
+        y = (s // Lx) % Ly
+        z = s // (Lx * Ly)
+        c = (x + y + z) & 1
+        return c * (Lx * Ly * Lz // 2) + s // 2
+    b = s % nb
+    cell = s // nb
+    return b * (Lx * Ly * Lz) + cell
+
+
+SMALL_CASES = [
+    # ragged multi-tile sc, periodic
+    W.replica_fields(W.C1_SC16_TRAJECTORY, L=(40, 38, 34), K=0.1, T=1.2),
+    # sc open in y and z with odd lengths
+    dict(kind="sc", L=(10, 7, 5), periodic_mask=1, J=0.9, K=0.3, e=(1.0, 0.5, -0.2), T=0.9),
+    # bcc periodic
+    dict(kind="bcc", L=(10, 9, 8), periodic_mask=7, J=1.0, K=0.2, e=(0.0, 1.0, 1.0), T=1.7),
+    # fcc nanoparticle, open surface
+    dict(kind="fcc", L=(14, 14, 14), periodic_mask=0, sphere_radius=5.3, J=1.0, K=0.05,
+         e=(1.0, 1.0, 1.0), T=0.9),
+    # fcc periodic, ragged
+    dict(kind="fcc", L=(9, 7, 6), periodic_mask=7, J=1.1, K=0.4, e=(0.0, 0.0, 1.0), T=2.5),
+]
+
+
+@pytest.mark.parametrize("case", range(len(SMALL_CASES)))
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_random_init_matches_oracle(M, case, prec):
+    rep = M.Replica(**SMALL_CASES[case], replica_id=3)
+    sim = M.Simulation([rep], precision=prec, seed=77)
+    g = natural(sim)
+    lat = oracle_lattice(rep)
+    o = O.init(lat, oracle_params(rep, 77))
+    tol = 1e-14 if prec == "f64" else 2e-7
+    for a, b in zip(g, o):
+        assert np.max(np.abs(a - b)) <= tol
+    occ = lat.tables()[0]
+    assert np.all(g[0][~occ] == 0) and np.all(g[2][~occ] == 0)
+
+
+def test_c1_trajectory_fp64(M):
+    """sc L=16, K=0.1, T=1.2, seed 0, 1000 sweeps: per-sweep m and E equal the
+    oracle's; accepted counts identical."""
+    w = W.C1_SC16_TRAJECTORY
+    rep = M.Replica(**W.replica_fields(w))
+    sim = M.Simulation([rep], precision="f64", seed=w["seed"])
+    lat = oracle_lattice(rep)
+    p = oracle_params(rep, w["seed"])
+    s = O.init(lat, p)
+    for a, b in zip(natural(sim), s):
+        assert np.max(np.abs(a - b)) <= 1e-14
+    n = w["sweeps"]
+    rec = sim.run_schedule([rep.T], n_equil=0, n_meas=n)[0, :, 0, :]
+    ref = O.run(lat, p, 0, n, s)
+    N = lat.n_occ
+    assert np.array_equal(rec[:, 0], np.arange(1, n + 1))
+    assert np.array_equal(rec[:, 1], ref[:, 5])
+    assert np.max(np.abs(rec[:, 2:5] - ref[:, 0:3] / N)) <= 1e-12
+    E_ref = ref[:, 3] + ref[:, 4]
+    assert np.max(np.abs(rec[:, 6] - E_ref) / np.abs(E_ref)) <= 1e-10
+    assert np.max(np.abs(rec[:, 7] - ref[:, 3]) / np.abs(E_ref)) <= 1e-10
+    for a, b in zip(natural(sim), s):
+        assert np.max(np.abs(a - b)) <= 1e-12
+
+
+@pytest.mark.parametrize("case", range(len(SMALL_CASES)))
+def test_fp64_trajectory_all_lattices(M, case):
+    rep = M.Replica(**SMALL_CASES[case], replica_id=1)
+    sim = M.Simulation([rep], precision="f64", seed=5)
+    lat = oracle_lattice(rep)
+    p = oracle_params(rep, 5)
+    s = O.init(lat, p)
+    ref = O.run(lat, p, 0, 25, s)
+    recs = []
+    for t in range(25):
+        sim.sweep(1, measure=True)
+        recs.append(sim.observables()[0])
+    N = lat.n_occ
+    for t, o in enumerate(recs):
+        assert o["sweep"] == t + 1 and o["n_sites"] == N
+        assert o["n_accepted"] == ref[t, 5]
+        assert np.max(np.abs(o["M"] - ref[t, 0:3] / N)) <= 1e-12
+        E = ref[t, 3] + ref[t, 4]
+        assert abs(o["E"] - E) <= 1e-10 * max(1.0, abs(E))
+        assert abs(o["E_anis"] - ref[t, 4]) <= 1e-10 * max(1.0, abs(E))
+    for a, b in zip(natural(sim), s):
+        assert np.max(np.abs(a - b)) <= 1e-12
+    st = sim.measure_state()[0]
+    ob = O.observables(lat, p, s)
+    assert abs(st["E"] - ob["E"]) <= 1e-10 * max(1.0, abs(ob["E"]))
+
+
+def _single_pass_check(M, rep, seed, sweeps, prec="f32"):
+    sim = M.Simulation([rep], precision=prec, seed=seed)
+    lat = oracle_lattice(rep)
+    p = oracle_params(rep, seed)
+    occ, col, _, _ = lat.tables()
+    pidx = packed_index(rep)
+    beta = 0.0 if math.isinf(rep.T) else (1.0 / rep.T if rep.T > 0 else None)
+    n_checked = n_margin = 0
+    for t in range(sweeps):
+        sim.set_sweep(t)
+        for c in range(lat.n_colours):
+            state = natural(sim)
+            ref = [a.copy() for a in state]
+            n, dh64, acc64, mg = O.run_pass(lat, p, c, t, ref, outputs=True)
+            dh, acc = sim.debug_pass(c)
+            dh = dh[0].double().cpu().numpy()[pidx]
+            acc = acc[0].cpu().numpy()[pidx]
+            sel = occ & (col == c)
+            assert np.all(acc[sel] <= 1)
+            tol = 1e-5 * np.maximum(np.abs(dh64[sel]), abs(rep.J))
+            assert np.all(np.abs(dh[sel] - dh64[sel]) <= tol)
+            margin_ok = np.abs(mg[sel]) < 1e-4
+            same = acc[sel].astype(bool) == acc64[sel]
+            assert np.all(same | margin_ok)
+            n_checked += int(sel.sum())
+            n_margin += int((~same).sum())
+            after = natural(sim)
+            a_sel = sel & acc64.astype(bool) & (acc.astype(bool) == acc64)
+            for a, b in zip(after, ref):
+                assert np.max(np.abs(a[a_sel] - b[a_sel]), initial=0.0) <= 2e-6
+            # continue both from the oracle's state rounded to the working precision
+            sim.from_natural(0, [np.float32(a) if prec == "f32" else a for a in ref])
+    return n_checked, n_margin
+
+
+@pytest.mark.parametrize("case", range(len(SMALL_CASES)))
+def test_fp32_single_pass_parity(M, case):
+    rep = M.Replica(**SMALL_CASES[case], replica_id=2)
+    n, nm = _single_pass_check(M, rep, seed=11, sweeps=3)
+    assert n > 0 and nm <= max(2, n // 10000)
+
+
+def test_fp32_single_pass_edge_temperatures(M):
+    for T in (0.0, float("inf"), 0.05):
+        rep = M.Replica(kind="sc", L=(12, 10, 8), J=1.0, K=0.2, T=T)
+        _single_pass_check(M, rep, seed=3, sweeps=2)
+
+
+def test_tile_shape_and_batching_are_bitwise(M):
+    import torch
+
+    base = dict(kind="sc", periodic_mask=7, J=1.0, K=0.1, e=(0.0, 0.0, 1.0))
+    reps = [M.Replica(L=(24, 24, 24), T=1.0, replica_id=0, **base),
+            M.Replica(L=(40, 38, 34), T=1.5, replica_id=1, **base),
+            M.Replica(L=(16, 16, 16), T=0.7, replica_id=2, **base)]
+    batched = M.Simulation(reps, precision="f32", seed=9)
+    batched.sweep(6, measure=True)
+    obs_b = batched.observables()
+    for r, rep in enumerate(reps):
+        for tile in (None, (8, 8, 3), (64, 4, 34), (16, 2, 1)):
+            scratch = torch.empty(16 << 20, dtype=torch.uint8, device="cuda")
+            one = M.Simulation([rep], precision="f32", seed=9, scratch=scratch)
+            if tile:
+                one.set_tile(*tile)
+            one.sweep(6, measure=True)
+            for a, b in zip(natural(one), natural(batched, r)):
+                assert np.array_equal(a, b)
+            o = one.observables()[0]
+            assert o["n_accepted"] == obs_b[r]["n_accepted"]
+            assert abs(o["E"] - obs_b[r]["E"]) <= 1e-9 * abs(o["E"])
+
+
+def test_checkpoint_resume_is_bitwise(M):
+    rep = M.Replica(kind="fcc", L=(10, 10, 10), periodic_mask=7, K=0.1, T=1.3)
+    a = M.Simulation([rep], precision="f32", seed=21)
+    a.sweep(10)
+    b = M.Simulation([rep], precision="f32", seed=21)
+    b.sweep(4)
+    ck = natural(b)
+    t = b.get_sweep()
+    assert t == 4
+    c = M.Simulation([rep], precision="f32", seed=21, init="user", user_spins=[ck])
+    c.set_sweep(t)
+    c.sweep(6)
+    for x, y in zip(natural(a), natural(c)):
+        assert np.array_equal(x, y)
+
+
+def test_graph_replay_matches_eager(M):
+    """run_schedule replays captured graphs; the chain and the records equal
+    eager sweeps, replay after replay, with other stream work in between."""
+    import torch
+
+    rep = M.Replica(kind="sc", L=(32, 32, 32), K=0.1, T=1.3)
+    g = M.Simulation([rep], precision="f32", seed=4)
+    e = M.Simulation([rep], precision="f32", seed=4, stream=torch.cuda.default_stream())
+    rec_g = []
+    for rnd in range(3):
+        rec_g.append(g.run_schedule([1.3], n_equil=70, n_meas=130)[0, :, 0, :])
+        torch.ones(1000, device="cuda").sum().item()  # unrelated eager work between replays
+    rec_e = []
+    for rnd in range(3):
+        e.sweep(70)
+        for i in range(130):
+            e.sweep(1, measure=True)
+            o = e.observables()[0]
+            rec_e.append([o["sweep"], o["n_accepted"], o["E"]])
+    rec_e = np.array(rec_e).reshape(3, 130, 3)
+    for rnd in range(3):
+        assert np.array_equal(rec_g[rnd][:, 0], rec_e[rnd][:, 0])
+        assert np.array_equal(rec_g[rnd][:, 1], rec_e[rnd][:, 1])
+        assert np.allclose(rec_g[rnd][:, 6], rec_e[rnd][:, 2], rtol=1e-12, atol=0)
+    for x, y in zip(natural(g), natural(e)):
+        assert np.array_equal(x, y)
+
+
+def test_zero_and_infinite_temperature(M):
+    rep = M.Replica(kind="bcc", L=(8, 8, 8), K=0.3, T=0.0)
+    sim = M.Simulation([rep], precision="f32", seed=1)
+    prev = sim.measure_state()[0]["E"]
+    for t in range(10):
+        sim.sweep(1, measure=True)
+        o = sim.observables()[0]
+        assert o["E"] <= prev + 1e-9 * abs(prev)
+        prev = o["E"]
+    sim.set_temperatures([float("inf")])
+    sim.sweep(3, measure=True)
+    o = sim.observables()[0]
+    assert o["n_accepted"] == o["n_sites"]
+
+
+def test_aligned_state_energy(M):
+    w = W.C4_FCC_PARTICLE
+    rep = M.Replica(**W.replica_fields(w))
+    sim = M.Simulation([rep], precision="f64", seed=0, init="aligned")
+    o = sim.measure_state()[0]
+    assert o["n_sites"] == 3618393
+    assert o["E"] == pytest.approx(-21518640 * w["J"] - w["K"] * 3618393, rel=1e-12)
+    assert np.allclose(o["M"], np.ones(3) / np.sqrt(3), atol=1e-12)
+
+
+def test_abi_errors(M):
+    import torch
+
+    with pytest.raises(M.MCError) as ei:
+        M.Simulation([M.Replica(kind="sc", L=(16, 15, 16))])
+    assert ei.value.status == -2
+    with pytest.raises(M.MCError) as ei:
+        M.Simulation([M.Replica(T=-1.0)])
+    assert ei.value.status == -1
+    small = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(M.MCError) as ei:
+        M.Simulation([M.Replica(L=(8, 8, 8))], scratch=small)
+    assert ei.value.status == -3
+    sim = M.Simulation([M.Replica(L=(8, 8, 8))])
+    with pytest.raises(M.MCError) as ei:
+        sim.observables()
+    assert ei.value.status == -5
+    with pytest.raises(M.MCError) as ei:
+        sim.set_tile(32, 16, 1)
+    assert ei.value.status == -1

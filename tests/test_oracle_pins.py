@@ -519,3 +519,25 @@ def test_replica_id_and_seed_change_streams():
     b = O.init(lat, O.Params(seed=1, replica_id=1))
     c = O.init(lat, O.Params(seed=2, replica_id=0))
     assert not np.array_equal(a[0], b[0]) and not np.array_equal(a[0], c[0])
+
+
+def test_single_site_attempt_equals_pass():
+    """The table-free single-site evaluation reproduces the tabulated pass
+    exactly (same neighbours, same stream) on every lattice kind."""
+    for kind, L, pm, R in ((O.SC, (6, 4, 5), 3, 0.0), (O.BCC, (4, 4, 4), 7, 0.0),
+                           (O.FCC, (6, 6, 6), 0, 2.4)):
+        lat = O.Lattice(kind, *L, periodic_mask=pm, sphere_radius=R)
+        geo = O.Geometry(kind, *L, periodic_mask=pm, sphere_radius=R)
+        p = O.Params(J=0.9, K=0.3, e=(1, 0, 1), T=1.1, seed=9, replica_id=2)
+        s = O.init(lat, p)
+        occ, col, nnb, nbr = lat.tables()
+        for c in range(lat.n_colours):
+            before = [a.copy() for a in s]
+            n, dh, acc, mg = O.run_pass(lat, p, c, 4, s, outputs=True)
+            for site in np.nonzero(occ & (col == c))[0]:
+                r = geo.site_attempt(p, 4, before, int(site))
+                assert r["dH"] == dh[site] and r["accepted"] == acc[site]
+                assert r["margin"] == mg[site]
+                assert np.array_equal(r["S_after"], [s[0][site], s[1][site], s[2][site]])
+            for site in np.nonzero(~occ)[0][:5]:
+                assert geo.site_attempt(p, 4, before, int(site)) is None
