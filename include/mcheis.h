@@ -210,13 +210,20 @@ mc_status mc_layout_copy(mc_sim *h, int32_t replica, int32_t to_natural, void *n
 mc_status mc_get_sweep(const mc_sim *h, uint64_t *t);
 mc_status mc_set_sweep(mc_sim *h, uint64_t t);
 
-/* Tile shape of the sweep kernels: tx x ty threads per workgroup (tx*ty <=
- * 256) over (row column, row) and zc planes walked per thread.  The spins do
- * not depend on it (only the FP64 summation order of observables does).  A
- * shape whose work list does not fit the handle's scratch gives MC_E_BUFFER.
- * Discards the record of the last measured sweep.  Synchronises. */
-mc_status mc_set_tile(mc_sim *h, int32_t tx, int32_t ty, int32_t zc);
-mc_status mc_get_tile(const mc_sim *h, int32_t *tx, int32_t *ty, int32_t *zc, uint64_t *n_items);
+/* Kernel and tile shape of the colour passes.  A tile is tx row columns x ty
+ * rows x zc planes (a row column is a packed pair of sites for sc, a cell for
+ * bcc/fcc).
+ *  kernel 0 (any lattice): tx*ty <= 256 threads, one column and row each;
+ *  kernel 1 (sc only): tx threads along the row (64, 128, 192 or 256), each
+ *    holding ty consecutive rows (1, 2, 4 or 8), with the other colour kept in
+ *    registers across planes.
+ * The spins do not depend on the choice (only the FP64 summation order of the
+ * observables does).  A shape whose work list does not fit the handle's
+ * scratch gives MC_E_BUFFER.  Discards the record of the last measured sweep.
+ * Synchronises. */
+mc_status mc_set_tile(mc_sim *h, int32_t kernel, int32_t tx, int32_t ty, int32_t zc);
+mc_status mc_get_tile(const mc_sim *h, int32_t *kernel, int32_t *tx, int32_t *ty, int32_t *zc,
+                      uint64_t *n_items);
 
 /* Number of colours (passes per sweep) of the handle's lattice kind. */
 mc_status mc_num_colours(const mc_sim *h, int32_t *n_colours);

@@ -126,16 +126,9 @@ int pow2_at_least(int v)
     return p;
 }
 
-Tile default_tile(const mc_replica_desc *reps, int n)
+// Planes per workgroup so that a pass has about kTargetItems workgroups.
+int z_chunk(const mc_replica_desc *reps, int n, const Tile &t)
 {
-    int W = 1, Ly = 1;
-    for (int r = 0; r < n; ++r) {
-        W = std::max(W, row_len(reps[r]));
-        Ly = std::max(Ly, reps[r].Ly);
-    }
-    Tile t;
-    t.tx = std::min(64, pow2_at_least(W));
-    t.ty = std::min(256 / t.tx, pow2_at_least(Ly));
     uint64_t cols = 0, planes = 0;
     for (int r = 0; r < n; ++r) {
         const uint64_t c = (uint64_t)((row_len(reps[r]) + t.tx - 1) / t.tx) *
@@ -143,9 +136,49 @@ Tile default_tile(const mc_replica_desc *reps, int n)
         cols += c * reps[r].Lz;
         planes = std::max<uint64_t>(planes, reps[r].Lz);
     }
-    uint64_t zc = (cols + kTargetItems - 1) / kTargetItems;
-    t.zc = (int)std::max<uint64_t>(1, std::min<uint64_t>(zc, planes));
+    const uint64_t zc = (cols + kTargetItems - 1) / kTargetItems;
+    return (int)std::max<uint64_t>(1, std::min<uint64_t>(zc, planes));
+}
+
+Tile default_tile(const mc_replica_desc *reps, int n)
+{
+    int W = 1, Ly = 1, Wmin = 1 << 30;
+    for (int r = 0; r < n; ++r) {
+        W = std::max(W, row_len(reps[r]));
+        Wmin = std::min(Wmin, row_len(reps[r]));
+        Ly = std::max(Ly, reps[r].Ly);
+    }
+    Tile t;
+    if (reps[0].kind == MC_SC && Wmin >= 48) {
+        // row strips: whole rows per workgroup (up to 256 columns), 4 rows per thread
+        t.kernel = KERNEL_STRIP;
+        t.tx = std::min(256, (W + 63) / 64 * 64);
+        t.ty = 4;
+    } else {
+        t.kernel = KERNEL_TILE;
+        t.tx = std::min(64, pow2_at_least(W));
+        t.ty = std::min(256 / t.tx, pow2_at_least(Ly));
+    }
+    t.zc = z_chunk(reps, n, t);
     return t;
+}
+
+mc_status check_tile(const Tile &t, int kind)
+{
+    if (t.kernel == KERNEL_STRIP) {
+        if (kind != MC_SC) return fail(MC_E_ARG, "the strip kernel is for simple cubic lattices");
+        if (t.tx < 64 || t.tx > 256 || t.tx % 64)
+            return fail(MC_E_ARG, "strip tile: tx must be 64, 128, 192 or 256 (got %d)", t.tx);
+        if (t.ty != 1 && t.ty != 2 && t.ty != 4 && t.ty != 8)
+            return fail(MC_E_ARG, "strip tile: ty (rows per thread) must be 1, 2, 4 or 8");
+    } else if (t.kernel == KERNEL_TILE) {
+        if (t.tx < 1 || t.ty < 1 || t.tx * t.ty > 256)
+            return fail(MC_E_ARG, "tile %d x %d invalid (need >= 1 and tx*ty <= 256)", t.tx, t.ty);
+    } else {
+        return fail(MC_E_ARG, "unknown kernel %d", t.kernel);
+    }
+    if (t.zc < 1) return fail(MC_E_ARG, "zc must be >= 1");
+    return MC_OK;
 }
 
 // minimum of q^2 for q in [lo, hi]
@@ -156,7 +189,8 @@ int64_t min_sq(int64_t lo, int64_t hi)
     return a * a;
 }
 
-// Tiles of every replica in (z, y, x) order; fully unoccupied tiles dropped.
+// Tiles of every replica in (z, x, y) order (y fastest, so that tiles sharing
+// halo rows are adjacent); fully unoccupied tiles dropped.
 void make_work(const mc_replica_desc *reps, int n, const Tile &t, std::vector<WorkItem> &work,
                std::vector<uint32_t> &begin, std::vector<uint32_t> &end)
 {
@@ -169,8 +203,8 @@ void make_work(const mc_replica_desc *reps, int n, const Tile &t, std::vector<Wo
         const int W = row_len(d);
         const bool sc = d.kind == MC_SC;
         for (int z0 = 0; z0 < d.Lz; z0 += t.zc)
-            for (int y0 = 0; y0 < d.Ly; y0 += t.ty)
-                for (int x0 = 0; x0 < W; x0 += t.tx) {
+            for (int x0 = 0; x0 < W; x0 += t.tx)
+                for (int y0 = 0; y0 < d.Ly; y0 += t.ty) {
                     if (d.sphere_radius > 0.0) {
                         // cells covered, then half-unit site positions relative to the centre
                         const int cx0 = sc ? 2 * x0 : x0;
@@ -789,12 +823,12 @@ mc_status mc_layout_copy(mc_sim *h, int32_t replica, int32_t to_natural, void *n
     return MC_OK;
 }
 
-mc_status mc_set_tile(mc_sim *h, int32_t tx, int32_t ty, int32_t zc)
+mc_status mc_set_tile(mc_sim *h, int32_t kernel, int32_t tx, int32_t ty, int32_t zc)
 {
     if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
-    if (tx < 1 || ty < 1 || zc < 1 || tx * ty > 256)
-        return fail(MC_E_ARG, "tile %d x %d x %d invalid (need >= 1 and tx*ty <= 256)", tx, ty, zc);
-    Tile t{tx, ty, zc};
+    Tile t{kernel, tx, ty, zc};
+    mc_status st = check_tile(t, h->kind);
+    if (st != MC_OK) return st;
     std::vector<WorkItem> work;
     std::vector<uint32_t> b, e;
     make_work(h->desc.data(), h->n_reps, t, work, b, e);
@@ -822,9 +856,11 @@ mc_status mc_set_tile(mc_sim *h, int32_t tx, int32_t ty, int32_t zc)
     return upload_reps(h);
 }
 
-mc_status mc_get_tile(const mc_sim *h, int32_t *tx, int32_t *ty, int32_t *zc, uint64_t *n_items)
+mc_status mc_get_tile(const mc_sim *h, int32_t *kernel, int32_t *tx, int32_t *ty, int32_t *zc,
+                      uint64_t *n_items)
 {
     if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
+    if (kernel) *kernel = h->tile.kernel;
     if (tx) *tx = h->tile.tx;
     if (ty) *ty = h->tile.ty;
     if (zc) *zc = h->tile.zc;

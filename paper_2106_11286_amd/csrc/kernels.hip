@@ -22,10 +22,19 @@
 
 namespace mc {
 
+// Spin planes are plain device allocations: address them as global memory so
+// loads take a scalar base plus a 32-bit vector offset.
+template <typename T> using gptr = __attribute__((address_space(1))) T *;
+template <typename T> __device__ __forceinline__ gptr<T> as_global(void *p)
+{
+    return (gptr<T>)(p);
+}
+
 // ---------------------------------------------------------------------------
-// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32
-// multiplications; the high halves are mixed with the other counter words and
-// the key, which is bumped by the Weyl increments between rounds.
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds, each with two
+// 32x32 -> 64-bit products (one v_mad_u64_u32 each); the high halves are mixed
+// with the other counter words and the key, which is bumped by the Weyl
+// increments between rounds.
 // ---------------------------------------------------------------------------
 struct Words {
     uint32_t w0, w1, w2, w3;
@@ -38,14 +47,14 @@ __device__ __forceinline__ Words philox10(uint32_t c0, uint32_t c1, uint32_t c2,
     constexpr uint32_t kWeylA = 0x9E3779B9u, kWeylB = 0xBB67AE85u;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo_a = kMulA * c0, hi_a = __umulhi(kMulA, c0);
-        const uint32_t lo_b = kMulB * c2, hi_b = __umulhi(kMulB, c2);
-        const uint32_t n0 = hi_b ^ c1 ^ k0;
-        const uint32_t n2 = hi_a ^ c3 ^ k1;
+        const uint64_t pa = (uint64_t)kMulA * c0;
+        const uint64_t pb = (uint64_t)kMulB * c2;
+        const uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
         c0 = n0;
-        c1 = lo_b;
+        c1 = (uint32_t)pb;
         c2 = n2;
-        c3 = lo_a;
+        c3 = (uint32_t)pa;
         k0 += kWeylA;
         k1 += kWeylB;
     }
@@ -63,15 +72,15 @@ template <> __device__ __forceinline__ double uniform23<double>(uint32_t w)
     return __uint2double_rn(w >> 9) * 0x1p-23 + 0x1p-24;
 }
 
-// Uniform point on the unit sphere (z uniform on [-1,1], azimuth 2 pi u1).
+// Uniform point on the unit sphere: z uniform on [-1,1], azimuth 2 pi u1.
+// FP32 uses the hardware sine/cosine, which take their argument in
+// revolutions (no range reduction), and the hardware square root.
 __device__ __forceinline__ void sphere_point(float u0, float u1, float &x, float &y, float &z)
 {
     z = 2.0f * u0 - 1.0f;
-    const float r = sqrtf(1.0f - z * z);
-    float s, c;
-    sincospif(2.0f * u1, &s, &c);
-    x = r * c;
-    y = r * s;
+    const float r = __builtin_amdgcn_sqrtf(1.0f - z * z);
+    x = r * __builtin_amdgcn_cosf(u1);
+    y = r * __builtin_amdgcn_sinf(u1);
 }
 __device__ __forceinline__ void sphere_point(double u0, double u1, double &x, double &y, double &z)
 {
@@ -85,8 +94,33 @@ __device__ __forceinline__ void sphere_point(double u0, double u1, double &x, do
 
 __device__ __forceinline__ float fast_exp(float v) { return __expf(v); }
 __device__ __forceinline__ double fast_exp(double v) { return exp(v); }
-__device__ __forceinline__ float inv_norm(float v) { return rsqrtf(v); }
+__device__ __forceinline__ float inv_norm(float v) { return __builtin_amdgcn_rsqf(v); }
 __device__ __forceinline__ double inv_norm(double v) { return 1.0 / sqrt(v); }
+
+// Lane shifts inside a wave64 (DPP): value of lane i-1 / lane i+1.  Lanes
+// without a source keep their own value.
+__device__ __forceinline__ float from_lower_lane(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v),
+                                                      0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float from_upper_lane(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v),
+                                                      0x130, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double from_lower_lane(double v)
+{
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xf, 0xf, false),
+                            __builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double from_upper_lane(double v)
+{
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, 0x130, 0xf, 0xf, false),
+                            __builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xf, 0xf, false));
+}
 
 // Basis positions of the conventional cubic cell, in half-cell units.
 __host__ __device__ constexpr int basis_count(int kind) { return kind == SC ? 1 : (kind == BCC ? 2 : 4); }
@@ -106,8 +140,21 @@ __device__ __forceinline__ bool occupied(const RepDev &R, int x, int y, int z, i
     return (double)(qx * qx + qy * qy + qz * qz) <= R.r2x4;
 }
 
+// Logical work item of this workgroup.  Workgroups are dealt to the XCDs in
+// turn, so consecutive dispatch indices land on different L2 caches; the
+// mapping below gives each XCD a contiguous run of the work list, whose
+// neighbouring tiles share halo rows.  Returns false for padding workgroups.
+__device__ __forceinline__ bool logical_item(const PassLaunch &P, uint32_t &item)
+{
+    const uint32_t q = (P.n_blocks + 7u) >> 3;
+    const uint32_t b = blockIdx.x;
+    const uint32_t l = (b & 7u) * q + (b >> 3);
+    item = P.item_base + l;
+    return l < P.n_blocks;
+}
+
 // ---------------------------------------------------------------------------
-// Block reduction of NQ doubles (fixed order: wave butterflies, then waves in
+// Block reduction of Q_N doubles (fixed order: wave butterflies, then waves in
 // index order), written to one partial slot.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void block_store_partials(double (&a)[Q_N], double *dst)
@@ -140,7 +187,7 @@ __device__ __forceinline__ void block_store_partials(double (&a)[Q_N], double *d
 template <typename T>
 __device__ __forceinline__ bool metropolis(T &sx, T &sy, T &sz, T hx, T hy, T hz, uint32_t s,
                                            uint32_t rid, uint32_t t, uint32_t k0, uint32_t k1,
-                                           T K, T ex, T ey, T ez, T beta, bool greedy, T *dh_out)
+                                           T K, T ex, T ey, T ez, T beta, bool greedy, T &dH)
 {
     const Words w = philox10(s, rid, t, 0u, k0, k1);
     T nx, ny, nz;
@@ -150,8 +197,7 @@ __device__ __forceinline__ bool metropolis(T &sx, T &sy, T &sz, T hx, T hy, T hz
     const T pn = nx * ex + ny * ey + nz * ez;
     const T po = sx * ex + sy * ey + sz * ez;
     // Eq. (1): dH = -h.(S'-S) - K[(S'.e)^2 - (S.e)^2]
-    const T dH = -(hx * dx + hy * dy + hz * dz) - K * ((pn - po) * (pn + po));
-    if (dh_out) *dh_out = dH;
+    dH = -(hx * dx + hy * dy + hz * dz) - K * ((pn - po) * (pn + po));
     const bool acc = (dH <= T(0)) || (!greedy && P <= fast_exp(-beta * dH));
     if (acc) {
         const T inv = inv_norm(nx * nx + ny * ny + nz * nz);
@@ -162,19 +208,40 @@ __device__ __forceinline__ bool metropolis(T &sx, T &sy, T &sz, T hx, T hy, T hz
     return acc;
 }
 
+// FP64 accumulation of the observables of one final spin.  sh is the spin
+// dotted with the field of its already-final neighbours (J applied); pass 0
+// of a bipartite lattice contributes none.
+template <typename T>
+__device__ __forceinline__ void accumulate(double (&acc)[Q_N], T sx, T sy, T sz, T ex, T ey, T ez,
+                                           T sh, bool accepted)
+{
+    acc[Q_MX] += (double)sx;
+    acc[Q_MY] += (double)sy;
+    acc[Q_MZ] += (double)sz;
+    const double pe = (double)sx * (double)ex + (double)sy * (double)ey + (double)sz * (double)ez;
+    acc[Q_PE2] += pe * pe;
+    acc[Q_SH] += (double)sh;
+    acc[Q_NACC] += accepted ? 1.0 : 0.0;
+}
+
 // ---------------------------------------------------------------------------
 // Simple cubic, two colours, colour-packed rows.  A site (x, y, z) of colour
 // c = (x+y+z)&1 sits at packed column xh = x/2 of row (y, z) in plane c.  Its
 // six neighbours all have the other colour: the same column of rows y+-1 and
 // planes z+-1, and in its own row the columns xh and xh-1 (x even) or xh and
-// xh+1 (x odd).  Each thread owns one (xh, y) column of a tile and walks the
-// tile's z range.
+// xh+1 (x odd).
+//
+// Tile kernel: each thread owns one (xh, y) column of a tx x ty tile and walks
+// the tile's z range; neighbours are loaded directly (cache hits).  Used for
+// short rows.
 // ---------------------------------------------------------------------------
 template <typename T, bool MEASURE, int MODE>
 __global__ void __launch_bounds__(256)
-k_sc_pass(PassLaunch P, int colour)
+k_sc_tile(PassLaunch P, int colour)
 {
-    const WorkItem w = P.work_dev[P.item_base + blockIdx.x];
+    uint32_t item;
+    if (!logical_item(P, item)) return;
+    const WorkItem w = P.work_dev[item];
     const RepDev &R = P.reps_dev[w.rep];
     const int Ly = R.Ly, Lz = R.Lz, Lxh = R.Lxh;
     const int lx = threadIdx.x % P.tile.tx, ly = threadIdx.x / P.tile.tx;
@@ -182,9 +249,7 @@ k_sc_pass(PassLaunch P, int colour)
     const bool active = xh < Lxh && y < Ly && ly < P.tile.ty;
     const uint32_t t = *P.tctr_dev + P.t_off;
     const uint32_t plane = R.plane;
-    T *__restrict__ gx = (T *)R.sx;
-    T *__restrict__ gy = (T *)R.sy;
-    T *__restrict__ gz = (T *)R.sz;
+    const gptr<T> gx = as_global<T>(R.sx), gy = as_global<T>(R.sy), gz = as_global<T>(R.sz);
     const uint32_t own = colour ? plane : 0u, oth = colour ? 0u : plane;
     const T J = (T)R.J, K = (T)R.K, ex = (T)R.e[0], ey = (T)R.e[1], ez = (T)R.e[2];
     const T beta = (T)R.beta;
@@ -193,7 +258,6 @@ k_sc_pass(PassLaunch P, int colour)
 
     double acc[Q_N] = {0, 0, 0, 0, 0, 0};
     if (active) {
-        // neighbour rows (y +- 1) with wrap or open face
         const int ym = y > 0 ? y - 1 : (py ? Ly - 1 : -1);
         const int yp = y < Ly - 1 ? y + 1 : (py ? 0 : -1);
         const int xm = xh > 0 ? xh - 1 : (px ? Lxh - 1 : -1);
@@ -228,35 +292,168 @@ k_sc_pass(PassLaunch P, int colour)
             hy *= J;
             hz *= J;
             T sx = gx[own + i], sy = gy[own + i], sz = gz[own + i];
+            bool a = false;
             if (MODE == 0) {
                 const uint32_t s = (uint32_t)(z * Ly + y) * (uint32_t)R.Lx + 2u * xh + p;
-                T *dh = P.dbg_dh ? (T *)P.dbg_dh + own + i : nullptr;
-                const bool a = metropolis<T>(sx, sy, sz, hx, hy, hz, s, R.rid, t, P.seed_lo,
-                                             P.seed_hi, K, ex, ey, ez, beta, greedy, dh);
+                T dH;
+                a = metropolis<T>(sx, sy, sz, hx, hy, hz, s, R.rid, t, P.seed_lo, P.seed_hi, K,
+                                  ex, ey, ez, beta, greedy, dH);
+                if (P.dbg_dh) ((T *)P.dbg_dh)[own + i] = dH;
                 if (P.dbg_acc) P.dbg_acc[own + i] = a ? 1 : 0;
                 if (a) {
                     gx[own + i] = sx;
                     gy[own + i] = sy;
                     gz[own + i] = sz;
                 }
-                if (MEASURE) acc[Q_NACC] += a ? 1.0 : 0.0;
             }
-            if (MEASURE) {
-                const double dx = sx, dy = sy, dz = sz;
-                acc[Q_MX] += dx;
-                acc[Q_MY] += dy;
-                acc[Q_MZ] += dz;
-                const double pe = dx * (double)ex + dy * (double)ey + dz * (double)ez;
-                acc[Q_PE2] += pe * pe;
-                // every bond has exactly one colour-1 end: count it there,
-                // against colour-0 neighbours that are final after pass 0
-                if (colour == 1) acc[Q_SH] += dx * (double)hx + dy * (double)hy + dz * (double)hz;
-            }
+            // every bond has exactly one colour-1 end: count it there,
+            // against colour-0 neighbours that are final after pass 0
+            if (MEASURE)
+                accumulate<T>(acc, sx, sy, sz, ex, ey, ez,
+                              colour == 1 ? sx * hx + sy * hy + sz * hz : T(0), a);
         }
     }
     if (MEASURE)
-        block_store_partials(acc, P.partials_dev +
-                                      ((size_t)colour * P.n_items + P.item_base + blockIdx.x) * NQ);
+        block_store_partials(acc, P.partials_dev + ((size_t)colour * P.n_items + item) * NQ);
+}
+
+// ---------------------------------------------------------------------------
+// Row-strip kernel (simple cubic).  The workgroup's tx threads lie along one
+// row segment (whole rows when they fit), each thread owns RY consecutive rows
+// of its column and walks the tile's planes in z:
+//  * the other colour's planes z-1, z, z+1 sit in registers and roll forward,
+//    so each element of the other colour is loaded once per tile (plus one
+//    halo row above and below the RY rows, and one halo plane at each end);
+//  * the +-y neighbours are the thread's own rows; the in-row neighbour comes
+//    from the adjacent lane through a DPP lane shift, or from memory at wave
+//    edges and at the periodic wrap.
+// All lanes run the loop (the DPP sources must be live); lanes and rows
+// outside the lattice read clamped in-bounds addresses and store nothing.
+// ---------------------------------------------------------------------------
+template <typename T> struct Vec3 {
+    T x, y, z;
+};
+
+template <typename T, bool MEASURE, int MODE, int RY>
+__global__ void __launch_bounds__(256)
+k_sc_strip(PassLaunch P, int colour)
+{
+    uint32_t item;
+    if (!logical_item(P, item)) return;
+    const WorkItem w = P.work_dev[item];
+    const RepDev &R = P.reps_dev[w.rep];
+    const int Ly = R.Ly, Lz = R.Lz, Lxh = R.Lxh, Lx = R.Lx;
+    const int lane = threadIdx.x & 63;
+    const int xraw = w.x0 + (int)threadIdx.x;
+    const bool xin = xraw < Lxh && (int)threadIdx.x < P.tile.tx;
+    const int xh = xin ? xraw : Lxh - 1;
+    const uint32_t t = *P.tctr_dev + P.t_off;
+    const uint32_t plane = R.plane;
+    const gptr<T> gx = as_global<T>(R.sx), gy = as_global<T>(R.sy), gz = as_global<T>(R.sz);
+    const uint32_t own = colour ? plane : 0u, oth = colour ? 0u : plane;
+    const T J = (T)R.J, K = (T)R.K, ex = (T)R.e[0], ey = (T)R.e[1], ez = (T)R.e[2];
+    const T beta = (T)R.beta;
+    const bool greedy = R.greedy != 0;
+    const bool px = R.pmask & 1u, py = R.pmask & 2u, pz = R.pmask & 4u;
+    const int xl = xh > 0 ? xh - 1 : (px ? Lxh - 1 : -1);
+    const int xr = xh < Lxh - 1 ? xh + 1 : (px ? 0 : -1);
+    const bool left_mem = lane == 0 || xh == 0;           // x-1 not held by lane-1
+    const bool right_mem = lane == 63 || xh >= Lxh - 1;   // x+1 not held by lane+1
+
+    // rows y0-1 .. y0+RY: lattice row index or -1 (open face / beyond)
+    int yrow[RY + 2];
+#pragma unroll
+    for (int k = -1; k <= RY; ++k) {
+        int y = w.y0 + k;
+        if (y < 0 || y >= Ly) y = py ? ((y % Ly) + Ly) % Ly : -1;
+        yrow[k + 1] = y;
+    }
+    auto load_other = [&](int y, int z) -> Vec3<T> {
+        if (y < 0 || z < 0) return {T(0), T(0), T(0)};
+        const uint32_t j = oth + (uint32_t)(z * Ly + y) * Lxh + xh;
+        return {gx[j], gy[j], gz[j]};
+    };
+
+    const int z0 = w.z0, z1 = min(w.z0 + P.tile.zc, Lz);
+    Vec3<T> om[RY], oc[RY + 2], op[RY + 2];
+    {
+        const int zm = z0 > 0 ? z0 - 1 : (pz ? Lz - 1 : -1);
+#pragma unroll
+        for (int k = 0; k < RY; ++k) om[k] = load_other(yrow[k + 1], zm);
+#pragma unroll
+        for (int k = 0; k < RY + 2; ++k) oc[k] = load_other(yrow[k], z0);
+    }
+    double acc[Q_N] = {0, 0, 0, 0, 0, 0};
+    for (int z = z0; z < z1; ++z) {
+        const int zp = z < Lz - 1 ? z + 1 : (pz ? 0 : -1);
+#pragma unroll
+        for (int k = 0; k < RY + 2; ++k) op[k] = load_other(yrow[k], zp);
+#pragma unroll
+        for (int k = 0; k < RY; ++k) {
+            const int yk = w.y0 + k;
+            const bool row_in = yk < Ly;
+            const int yc = row_in ? yk : Ly - 1;
+            const int p = (colour + yc + z) & 1; // uniform over the workgroup
+            const uint32_t i = own + (uint32_t)(z * Ly + yc) * Lxh + xh;
+            T sx = gx[i], sy = gy[i], sz = gz[i];
+            // in-row neighbour on the side given by the parity
+            const Vec3<T> c = oc[k + 1];
+            Vec3<T> nb;
+            if (p == 0) {
+                nb = {from_lower_lane(c.x), from_lower_lane(c.y), from_lower_lane(c.z)};
+                if (left_mem) {
+                    nb = {T(0), T(0), T(0)};
+                    if (xl >= 0) {
+                        const uint32_t j = oth + (uint32_t)(z * Ly + yc) * Lxh + xl;
+                        nb = {gx[j], gy[j], gz[j]};
+                    }
+                }
+            } else {
+                nb = {from_upper_lane(c.x), from_upper_lane(c.y), from_upper_lane(c.z)};
+                if (right_mem) {
+                    nb = {T(0), T(0), T(0)};
+                    if (xr >= 0) {
+                        const uint32_t j = oth + (uint32_t)(z * Ly + yc) * Lxh + xr;
+                        nb = {gx[j], gy[j], gz[j]};
+                    }
+                }
+            }
+            // fixed order: -z, -y, -x, +x, +y, +z
+            const Vec3<T> lo = p ? c : nb, hi = p ? nb : c;
+            T hx = om[k].x + oc[k].x + lo.x + hi.x + oc[k + 2].x + op[k + 1].x;
+            T hy = om[k].y + oc[k].y + lo.y + hi.y + oc[k + 2].y + op[k + 1].y;
+            T hz = om[k].z + oc[k].z + lo.z + hi.z + oc[k + 2].z + op[k + 1].z;
+            hx *= J;
+            hy *= J;
+            hz *= J;
+            const bool live = xin && row_in;
+            bool a = false;
+            if (MODE == 0) {
+                const uint32_t s = (uint32_t)(z * Ly + yc) * (uint32_t)Lx + 2u * xh + p;
+                T dH;
+                a = metropolis<T>(sx, sy, sz, hx, hy, hz, s, R.rid, t, P.seed_lo, P.seed_hi, K,
+                                  ex, ey, ez, beta, greedy, dH);
+                if (live) {
+                    if (P.dbg_dh) ((T *)P.dbg_dh)[i] = dH;
+                    if (P.dbg_acc) P.dbg_acc[i] = a ? 1 : 0;
+                    if (a) {
+                        gx[i] = sx;
+                        gy[i] = sy;
+                        gz[i] = sz;
+                    }
+                }
+            }
+            if (MEASURE && live)
+                accumulate<T>(acc, sx, sy, sz, ex, ey, ez,
+                              colour == 1 ? sx * hx + sy * hy + sz * hz : T(0), a);
+        }
+#pragma unroll
+        for (int k = 0; k < RY; ++k) om[k] = oc[k + 1];
+#pragma unroll
+        for (int k = 0; k < RY + 2; ++k) oc[k] = op[k];
+    }
+    if (MEASURE)
+        block_store_partials(acc, P.partials_dev + ((size_t)colour * P.n_items + item) * NQ);
 }
 
 // ---------------------------------------------------------------------------
@@ -272,7 +469,9 @@ __global__ void __launch_bounds__(256)
 k_basis_pass(PassLaunch P)
 {
     constexpr int NB = basis_count(KIND);
-    const WorkItem w = P.work_dev[P.item_base + blockIdx.x];
+    uint32_t item;
+    if (!logical_item(P, item)) return;
+    const WorkItem w = P.work_dev[item];
     const RepDev &R = P.reps_dev[w.rep];
     const int Lx = R.Lx, Ly = R.Ly, Lz = R.Lz;
     const int lx = threadIdx.x % P.tile.tx, ly = threadIdx.x / P.tile.tx;
@@ -280,9 +479,7 @@ k_basis_pass(PassLaunch P)
     const bool active = x < Lx && y < Ly && ly < P.tile.ty;
     const uint32_t t = *P.tctr_dev + P.t_off;
     const uint32_t plane = R.plane;
-    T *__restrict__ gx = (T *)R.sx;
-    T *__restrict__ gy = (T *)R.sy;
-    T *__restrict__ gz = (T *)R.sz;
+    const gptr<T> gx = as_global<T>(R.sx), gy = as_global<T>(R.sy), gz = as_global<T>(R.sz);
     const T J = (T)R.J, K = (T)R.K, ex = (T)R.e[0], ey = (T)R.e[1], ez = (T)R.e[2];
     const T beta = (T)R.beta;
     const bool greedy = R.greedy != 0;
@@ -341,34 +538,28 @@ k_basis_pass(PassLaunch P)
             hz *= J;
             const uint32_t i = (uint32_t)B * plane + cell;
             T sx = gx[i], sy = gy[i], sz = gz[i];
+            bool a = false;
             if (MODE == 0) {
                 const uint32_t s = cell * NB + B;
-                T *dh = P.dbg_dh ? (T *)P.dbg_dh + i : nullptr;
-                const bool a = metropolis<T>(sx, sy, sz, hx, hy, hz, s, R.rid, t, P.seed_lo,
-                                             P.seed_hi, K, ex, ey, ez, beta, greedy, dh);
+                T dH;
+                a = metropolis<T>(sx, sy, sz, hx, hy, hz, s, R.rid, t, P.seed_lo, P.seed_hi, K,
+                                  ex, ey, ez, beta, greedy, dH);
+                if (P.dbg_dh) ((T *)P.dbg_dh)[i] = dH;
                 if (P.dbg_acc) P.dbg_acc[i] = a ? 1 : 0;
                 if (a) {
                     gx[i] = sx;
                     gy[i] = sy;
                     gz[i] = sz;
                 }
-                if (MEASURE) acc[Q_NACC] += a ? 1.0 : 0.0;
             }
-            if (MEASURE) {
-                const double dsx = sx, dsy = sy, dsz = sz;
-                acc[Q_MX] += dsx;
-                acc[Q_MY] += dsy;
-                acc[Q_MZ] += dsz;
-                const double pe = dsx * (double)ex + dsy * (double)ey + dsz * (double)ez;
-                acc[Q_PE2] += pe * pe;
-                // bonds to lower colours, whose spins are final after their pass
-                acc[Q_SH] += (double)J * (dsx * (double)lx_ + dsy * (double)ly_ + dsz * (double)lz_);
-            }
+            // bonds to lower colours, whose spins are final after their pass
+            if (MEASURE)
+                accumulate<T>(acc, sx, sy, sz, ex, ey, ez, J * (sx * lx_ + sy * ly_ + sz * lz_),
+                              a);
         }
     }
     if (MEASURE)
-        block_store_partials(acc, P.partials_dev +
-                                      ((size_t)B * P.n_items + P.item_base + blockIdx.x) * NQ);
+        block_store_partials(acc, P.partials_dev + ((size_t)B * P.n_items + item) * NQ);
 }
 
 // ---------------------------------------------------------------------------
@@ -510,11 +701,24 @@ __global__ void k_fill_zero(double *p, uint64_t n)
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
+static dim3 pass_grid(const PassLaunch &p) { return dim3(((p.n_blocks + 7u) >> 3) << 3); }
+
 template <typename T, bool MEASURE, int MODE>
 static hipError_t sc_launch(int colour, const PassLaunch &p, hipStream_t st)
 {
+    if (p.tile.kernel == KERNEL_STRIP) {
+        const dim3 g = pass_grid(p), b(p.tile.tx);
+        switch (p.tile.ty) {
+        case 1: hipLaunchKernelGGL((k_sc_strip<T, MEASURE, MODE, 1>), g, b, 0, st, p, colour); break;
+        case 2: hipLaunchKernelGGL((k_sc_strip<T, MEASURE, MODE, 2>), g, b, 0, st, p, colour); break;
+        case 4: hipLaunchKernelGGL((k_sc_strip<T, MEASURE, MODE, 4>), g, b, 0, st, p, colour); break;
+        case 8: hipLaunchKernelGGL((k_sc_strip<T, MEASURE, MODE, 8>), g, b, 0, st, p, colour); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     const int threads = ((p.tile.tx * p.tile.ty + 63) / 64) * 64;
-    hipLaunchKernelGGL((k_sc_pass<T, MEASURE, MODE>), dim3(p.n_blocks), dim3(threads), 0, st, p,
+    hipLaunchKernelGGL((k_sc_tile<T, MEASURE, MODE>), pass_grid(p), dim3(threads), 0, st, p,
                        colour);
     return hipGetLastError();
 }
@@ -523,7 +727,7 @@ template <int KIND, typename T, bool MEASURE, int MODE>
 static hipError_t basis_launch(int colour, const PassLaunch &p, hipStream_t st)
 {
     const int threads = ((p.tile.tx * p.tile.ty + 63) / 64) * 64;
-    const dim3 g(p.n_blocks), b(threads);
+    const dim3 g = pass_grid(p), b(threads);
     switch (colour) {
     case 0: hipLaunchKernelGGL((k_basis_pass<KIND, 0, T, MEASURE, MODE>), g, b, 0, st, p); break;
     case 1: hipLaunchKernelGGL((k_basis_pass<KIND, 1, T, MEASURE, MODE>), g, b, 0, st, p); break;

@@ -41,9 +41,16 @@ constexpr int NQ = 8; // padded slot width (doubles)
 enum : int { R_MX = 0, R_MY, R_MZ, R_EEX, R_EAN, R_NACC, R_SWEEP, R_N };
 constexpr int NR = 8;
 
-// Tile shape (threads TX x TY per workgroup, ZC planes streamed per thread).
+// Kernel variants of a colour pass.
+enum : int32_t {
+    KERNEL_TILE = 0,  // one site per thread per plane, tx x ty threads (any lattice kind)
+    KERNEL_STRIP = 1, // sc only: tx threads along a row (multiple of 64), ty rows per thread
+};
+
+// Tile of one workgroup: tx row columns x ty rows x zc planes, and the kernel
+// that maps it onto threads.
 struct Tile {
-    int32_t tx, ty, zc;
+    int32_t kernel, tx, ty, zc;
 };
 
 } // namespace mc

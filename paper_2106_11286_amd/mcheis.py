@@ -93,10 +93,11 @@ _SIGNATURES = {
                                      ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p)]),
     "mc_layout_copy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_void_p]),
-    "mc_set_tile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "mc_set_tile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                   ctypes.c_int32]),
     "mc_get_tile": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
                                    ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
-                                   ctypes.POINTER(ctypes.c_uint64)]),
+                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_uint64)]),
     "mc_get_sweep": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
     "mc_set_sweep": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
     "mc_num_colours": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
@@ -327,14 +328,18 @@ class Simulation:
     def set_sweep(self, t: int):
         _check("mc_set_sweep", LIB.mc_set_sweep(self.handle, int(t)))
 
-    def set_tile(self, tx: int, ty: int, zc: int):
-        _check("mc_set_tile", LIB.mc_set_tile(self.handle, int(tx), int(ty), int(zc)))
+    def set_tile(self, tx: int, ty: int, zc: int, kernel: int = 0):
+        """``mc_set_tile``: kernel 0 = tile (tx x ty threads), 1 = sc row strip
+        (tx threads along the row, ty rows per thread); zc planes per tile."""
+        _check("mc_set_tile", LIB.mc_set_tile(self.handle, int(kernel), int(tx), int(ty), int(zc)))
 
     def get_tile(self):
-        a, b, c, n = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_uint64()
-        _check("mc_get_tile", LIB.mc_get_tile(self.handle, ctypes.byref(a), ctypes.byref(b),
-                                              ctypes.byref(c), ctypes.byref(n)))
-        return int(a.value), int(b.value), int(c.value), int(n.value)
+        """(kernel, tx, ty, zc, n_work_items)."""
+        k, a, b, c, n = (ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(),
+                         ctypes.c_uint64())
+        _check("mc_get_tile", LIB.mc_get_tile(self.handle, ctypes.byref(k), ctypes.byref(a),
+                                              ctypes.byref(b), ctypes.byref(c), ctypes.byref(n)))
+        return int(k.value), int(a.value), int(b.value), int(c.value), int(n.value)
 
     def debug_pass(self, colour: int):
         """``mc_debug_pass``: one colour pass at the current counter; returns

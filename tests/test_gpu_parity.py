@@ -75,6 +75,10 @@ SMALL_CASES = [
          e=(1.0, 1.0, 1.0), T=0.9),
     # fcc periodic, ragged
     dict(kind="fcc", L=(9, 7, 6), periodic_mask=7, J=1.1, K=0.4, e=(0.0, 0.0, 1.0), T=2.5),
+    # sc long rows (row-strip kernel), periodic, ragged rows per thread
+    dict(kind="sc", L=(150, 14, 12), periodic_mask=7, J=1.0, K=0.05, e=(0.0, 0.0, 1.0), T=1.4),
+    # sc long rows, open in y and z with odd lengths
+    dict(kind="sc", L=(130, 9, 7), periodic_mask=1, J=0.8, K=0.2, e=(0.3, 0.0, 1.0), T=1.1),
 ]
 
 
@@ -193,28 +197,47 @@ def test_fp32_single_pass_edge_temperatures(M):
         _single_pass_check(M, rep, seed=3, sweeps=2)
 
 
-def test_tile_shape_and_batching_are_bitwise(M):
+TILES = [None, (0, 8, 8, 3), (0, 64, 4, 34), (0, 16, 2, 1), (1, 64, 1, 5), (1, 64, 4, 34),
+         (1, 128, 8, 3), (1, 256, 2, 7), (1, 192, 4, 1)]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_tile_shape_and_batching_are_bitwise(M, prec):
+    """Spins after several sweeps are bitwise identical for every kernel and
+    tile shape, batched with other replicas or alone."""
     import torch
 
     base = dict(kind="sc", periodic_mask=7, J=1.0, K=0.1, e=(0.0, 0.0, 1.0))
     reps = [M.Replica(L=(24, 24, 24), T=1.0, replica_id=0, **base),
             M.Replica(L=(40, 38, 34), T=1.5, replica_id=1, **base),
-            M.Replica(L=(16, 16, 16), T=0.7, replica_id=2, **base)]
-    batched = M.Simulation(reps, precision="f32", seed=9)
+            M.Replica(L=(150, 14, 12), T=0.7, replica_id=2, **base),
+            M.Replica(L=(130, 9, 7), T=1.2, replica_id=3, kind="sc", periodic_mask=1, J=1.0,
+                      K=0.3, e=(1.0, 0.0, 0.0))]
+    batched = M.Simulation(reps, precision=prec, seed=9)
     batched.sweep(6, measure=True)
     obs_b = batched.observables()
     for r, rep in enumerate(reps):
-        for tile in (None, (8, 8, 3), (64, 4, 34), (16, 2, 1)):
+        for tile in TILES:
             scratch = torch.empty(16 << 20, dtype=torch.uint8, device="cuda")
-            one = M.Simulation([rep], precision="f32", seed=9, scratch=scratch)
+            one = M.Simulation([rep], precision=prec, seed=9, scratch=scratch)
             if tile:
-                one.set_tile(*tile)
+                one.set_tile(tile[1], tile[2], tile[3], kernel=tile[0])
             one.sweep(6, measure=True)
             for a, b in zip(natural(one), natural(batched, r)):
-                assert np.array_equal(a, b)
+                assert np.array_equal(a, b), (r, tile)
             o = one.observables()[0]
             assert o["n_accepted"] == obs_b[r]["n_accepted"]
             assert abs(o["E"] - obs_b[r]["E"]) <= 1e-9 * abs(o["E"])
+
+
+def test_strip_kernel_rejects_other_lattices(M):
+    sim = M.Simulation([M.Replica(kind="fcc", L=(6, 6, 6))])
+    with pytest.raises(M.MCError):
+        sim.set_tile(64, 4, 2, kernel=1)
+    sim = M.Simulation([M.Replica(kind="sc", L=(16, 16, 16))])
+    for bad in ((96, 4, 2), (64, 3, 2), (64, 4, 0), (512, 1, 1)):
+        with pytest.raises(M.MCError):
+            sim.set_tile(*bad, kernel=1)
 
 
 def test_checkpoint_resume_is_bitwise(M):
@@ -306,3 +329,125 @@ def test_abi_errors(M):
     with pytest.raises(M.MCError) as ei:
         sim.set_tile(32, 16, 1)
     assert ei.value.status == -1
+    with pytest.raises(M.MCError) as ei:
+        sim.set_tile(1, 1, 1)  # work list larger than the handle's scratch
+    assert ei.value.status == -3
+
+
+def _sampled_pass(M, sim, rep, geo, p, t, colour, rng, n_sample=4096):
+    """One debug pass of a big lattice; check sampled sites of the pass colour
+    one by one against the oracle's single-site evaluation."""
+    before = natural(sim)
+    dh, acc = sim.debug_pass(colour)
+    after = natural(sim)
+    Lx, Ly, Lz = rep.L
+    s = rng.integers(0, Lx * Ly * Lz, size=4 * n_sample)
+    x, y, z = s % Lx, (s // Lx) % Ly, s // (Lx * Ly)
+    s = s[((x + y + z) & 1) == colour][:n_sample]
+    idx = (colour * (Lx * Ly * Lz // 2) + s // 2)
+    dh = dh[0][torch_index(idx)].double().cpu().numpy()
+    acc = acc[0][torch_index(idx)].cpu().numpy()
+    n_flip = 0
+    for k, site in enumerate(s):
+        r = geo.site_attempt(p, t, before, int(site))
+        assert abs(dh[k] - r["dH"]) <= 1e-5 * max(abs(r["dH"]), abs(rep.J)), (site, dh[k], r)
+        if bool(acc[k]) != r["accepted"]:
+            assert abs(r["margin"]) < 1e-4, (site, r)
+            n_flip += 1
+            continue
+        got = np.array([after[0][site], after[1][site], after[2][site]])
+        assert np.max(np.abs(got - r["S_after"])) <= 2e-6
+    return before, after, dh, acc, n_flip
+
+
+def torch_index(idx):
+    import torch
+
+    return torch.as_tensor(idx, dtype=torch.int64, device="cuda")
+
+
+def test_full_size_sc464_sampled(M):
+    """The benchmark lattice (sc L=464, 99,897,344 spins, FP32, default tiles):
+    after 100 sweeps, both colour passes of sweep 100 checked at 4096 sampled
+    sites each against the oracle's single-site evaluation from the same
+    state, plus energy bookkeeping of the whole pass and fused-vs-recomputed
+    observables."""
+    w = W.C5_SC464_ROOFLINE
+    rep = M.Replica(**W.replica_fields(w))
+    sim = M.Simulation([rep], precision="f32", seed=w["seed"])
+    assert sim.get_tile()[0] == 1  # the row-strip kernel the benchmark times
+    sim.sweep(99)
+    sim.sweep(1, measure=True)
+    fused = sim.observables()[0]
+    full = sim.measure_state()[0]
+    assert fused["n_sites"] == 464**3
+    assert abs(fused["E"] - full["E"]) <= 1e-9 * abs(full["E"])
+    assert np.max(np.abs(fused["M"] - full["M"])) <= 1e-12
+    geo = O.Geometry(O.SC, *rep.L, periodic_mask=rep.periodic_mask)
+    p = oracle_params(rep, w["seed"])
+    rng = np.random.default_rng(464)
+    t = sim.get_sweep()
+    assert t == 100
+    n_flip = 0
+    for colour in (0, 1):
+        before, after, dh, acc, nf = _sampled_pass(M, sim, rep, geo, p, t, colour, rng)
+        n_flip += nf
+        del before, after
+    assert n_flip <= 2
+
+
+def test_full_size_pass_bookkeeping(M):
+    """Energy bookkeeping over every site of both passes at full size."""
+    import torch
+
+    w = W.C5_SC464_ROOFLINE
+    rep = M.Replica(**W.replica_fields(w))
+    sim = M.Simulation([rep], precision="f32", seed=w["seed"])
+    sim.sweep(20)
+    for colour in (0, 1):
+        e0 = sim.measure_state()[0]["E"]
+        dh, acc = sim.debug_pass(colour)
+        e1 = sim.measure_state()[0]["E"]
+        sel = acc[0] == 1
+        total = dh[0][sel].double().sum().item()
+        assert abs((e1 - e0) - total) <= 1e-6 * 464**3, (e1 - e0, total)
+        assert int((acc[0] > 1).sum().item()) == 464**3 // 2  # other colour untouched (255)
+
+
+def test_full_size_fcc_particle_sampled(M):
+    """The FCC nanoparticle (128^3 cells, R = 60, open surface): one sweep's
+    four passes at sampled sites against the oracle, after 20 sweeps."""
+    w = W.C4_FCC_PARTICLE
+    rep = M.Replica(**W.replica_fields(w))
+    sim = M.Simulation([rep], precision="f32", seed=w["seed"])
+    sim.sweep(20)
+    geo = O.Geometry(O.FCC, *rep.L, periodic_mask=rep.periodic_mask,
+                     sphere_radius=rep.sphere_radius)
+    p = oracle_params(rep, w["seed"])
+    rng = np.random.default_rng(128)
+    t = sim.get_sweep()
+    Lx, Ly, Lz = rep.L
+    for colour in range(4):
+        before = natural(sim)
+        dh, acc = sim.debug_pass(colour)
+        after = natural(sim)
+        cells = rng.integers(0, Lx * Ly * Lz, size=20000)
+        s = cells * 4 + colour
+        checked = 0
+        for cell, site in zip(cells, s):
+            r = geo.site_attempt(p, t, before, int(site))
+            k = colour * (Lx * Ly * Lz) + int(cell)
+            if r is None:
+                assert int(acc[0][k].item()) == 255  # unoccupied: never visited
+                continue
+            d = float(dh[0][k].item())
+            assert abs(d - r["dH"]) <= 1e-5 * max(abs(r["dH"]), 1.0)
+            if bool(acc[0][k].item()) == r["accepted"]:
+                got = np.array([after[0][site], after[1][site], after[2][site]])
+                assert np.max(np.abs(got - r["S_after"])) <= 2e-6
+            else:
+                assert abs(r["margin"]) < 1e-4
+            checked += 1
+            if checked >= 1500:
+                break
+        assert checked >= 1500
