@@ -149,7 +149,9 @@ Tile default_tile(const mc_replica_desc *reps, int n)
         Ly = std::max(Ly, reps[r].Ly);
     }
     Tile t;
-    if (reps[0].kind == MC_SC && Wmin >= 48) {
+    bool fits = true; // the strip kernel addresses each component array with 32-bit offsets
+    for (int r = 0; r < n; ++r) fits &= box_sites(reps[r]) * sizeof(double) <= 0xFFFFFFFFull;
+    if (reps[0].kind == MC_SC && Wmin >= 48 && fits) {
         // row strips: whole rows per workgroup (up to 256 columns), 4 rows per thread
         t.kernel = KERNEL_STRIP;
         t.tx = std::min(256, (W + 63) / 64 * 64);
@@ -163,10 +165,12 @@ Tile default_tile(const mc_replica_desc *reps, int n)
     return t;
 }
 
-mc_status check_tile(const Tile &t, int kind)
+mc_status check_tile(const Tile &t, int kind, uint64_t max_component_bytes)
 {
     if (t.kernel == KERNEL_STRIP) {
         if (kind != MC_SC) return fail(MC_E_ARG, "the strip kernel is for simple cubic lattices");
+        if (max_component_bytes > 0xFFFFFFFFull)
+            return fail(MC_E_UNSUPPORTED, "strip kernel: a spin component array exceeds 4 GiB");
         if (t.tx < 64 || t.tx > 256 || t.tx % 64)
             return fail(MC_E_ARG, "strip tile: tx must be 64, 128, 192 or 256 (got %d)", t.tx);
         if (t.ty != 1 && t.ty != 2 && t.ty != 4 && t.ty != 8)
@@ -800,7 +804,7 @@ mc_status mc_debug_pass(mc_sim *h, int32_t colour, void *const *dh, void *const 
         PassLaunch p = pass_args(h, R.item_begin, R.item_end - R.item_begin, 0);
         p.dbg_dh = dh[r];
         p.dbg_acc = (uint8_t *)accepted[r];
-        HIP_TRY(launch_pass(h->kind, h->prec == MC_F64, colour, false, 0, p, h->stream));
+        HIP_TRY(launch_pass(h->kind, h->prec == MC_F64, colour, false, 2, p, h->stream));
     }
     HIP_TRY(hipStreamSynchronize(h->stream));
     return MC_OK;
@@ -827,7 +831,11 @@ mc_status mc_set_tile(mc_sim *h, int32_t kernel, int32_t tx, int32_t ty, int32_t
 {
     if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
     Tile t{kernel, tx, ty, zc};
-    mc_status st = check_tile(t, h->kind);
+    uint64_t max_bytes = 0;
+    for (const RepDev &R : h->reps)
+        max_bytes = std::max<uint64_t>(max_bytes, (uint64_t)R.n_box *
+                                                      (h->prec == MC_F64 ? 8u : 4u));
+    mc_status st = check_tile(t, h->kind, max_bytes);
     if (st != MC_OK) return st;
     std::vector<WorkItem> work;
     std::vector<uint32_t> b, e;

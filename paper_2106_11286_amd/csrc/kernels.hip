@@ -45,6 +45,10 @@ __device__ __forceinline__ Words philox10(uint32_t c0, uint32_t c1, uint32_t c2,
 {
     constexpr uint32_t kMulA = 0xD2511F53u, kMulB = 0xCD9E8D57u;
     constexpr uint32_t kWeylA = 0x9E3779B9u, kWeylB = 0xBB67AE85u;
+    // The key is uniform: keep its schedule in scalar registers computed per
+    // call, instead of 20 hoisted loop invariants that would crowd out the
+    // sweep kernels' other scalar state.
+    asm volatile("" : "+s"(k0), "+s"(k1));
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         const uint64_t pa = (uint64_t)kMulA * c0;
@@ -293,13 +297,15 @@ k_sc_tile(PassLaunch P, int colour)
             hz *= J;
             T sx = gx[own + i], sy = gy[own + i], sz = gz[own + i];
             bool a = false;
-            if (MODE == 0) {
+            if (MODE != 1) {
                 const uint32_t s = (uint32_t)(z * Ly + y) * (uint32_t)R.Lx + 2u * xh + p;
                 T dH;
                 a = metropolis<T>(sx, sy, sz, hx, hy, hz, s, R.rid, t, P.seed_lo, P.seed_hi, K,
                                   ex, ey, ez, beta, greedy, dH);
-                if (P.dbg_dh) ((T *)P.dbg_dh)[own + i] = dH;
-                if (P.dbg_acc) P.dbg_acc[own + i] = a ? 1 : 0;
+                if (MODE == 2) {
+                    ((T *)P.dbg_dh)[own + i] = dH;
+                    P.dbg_acc[own + i] = a ? 1 : 0;
+                }
                 if (a) {
                     gx[own + i] = sx;
                     gy[own + i] = sy;
@@ -334,22 +340,60 @@ template <typename T> struct Vec3 {
     T x, y, z;
 };
 
+// Raw buffer access: a resource per spin component holds the array's base and
+// size in scalar registers; an access is one instruction with the lane's byte
+// offset in a vector register and the row's byte offset in a scalar register
+// (no per-lane 64-bit address arithmetic).  A component array must stay below
+// 4 GiB (checked on the host).
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+constexpr int kRsrcWord3 = 0x00020000; // raw dword access, gfx9-family descriptor
+
+template <typename T>
+__device__ __forceinline__ rsrc_t plane_rsrc(void *comp, uint32_t elem_off, uint32_t n_elems)
+{
+    return __builtin_amdgcn_make_buffer_rsrc((char *)comp + (size_t)elem_off * sizeof(T), (short)0,
+                                             (int)(n_elems * (uint32_t)sizeof(T)), kRsrcWord3);
+}
+__device__ __forceinline__ float buf_load(rsrc_t r, uint32_t voff, uint32_t soff, float)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ __forceinline__ double buf_load(rsrc_t r, uint32_t voff, uint32_t soff, double)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ __forceinline__ void buf_store(float v, rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
+}
+__device__ __forceinline__ void buf_store(double v, rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    typedef uint32_t v2u __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, v), r, voff, soff, 0);
+}
+template <typename T> struct PlaneRs {
+    rsrc_t x, y, z;
+};
+
 template <typename T, bool MEASURE, int MODE, int RY>
 __global__ void __launch_bounds__(256)
 k_sc_strip(PassLaunch P, int colour)
 {
     uint32_t item;
     if (!logical_item(P, item)) return;
+    // every descriptor field is read into registers before the first store, so
+    // the loads stay scalar (memory that the kernel may write cannot be)
     const WorkItem w = P.work_dev[item];
     const RepDev &R = P.reps_dev[w.rep];
     const int Ly = R.Ly, Lz = R.Lz, Lxh = R.Lxh, Lx = R.Lx;
+    void *const base_x = R.sx, *const base_y = R.sy, *const base_z = R.sz;
+    const uint32_t rid = R.rid;
     const int lane = threadIdx.x & 63;
     const int xraw = w.x0 + (int)threadIdx.x;
     const bool xin = xraw < Lxh && (int)threadIdx.x < P.tile.tx;
     const int xh = xin ? xraw : Lxh - 1;
     const uint32_t t = *P.tctr_dev + P.t_off;
     const uint32_t plane = R.plane;
-    const gptr<T> gx = as_global<T>(R.sx), gy = as_global<T>(R.sy), gz = as_global<T>(R.sz);
     const uint32_t own = colour ? plane : 0u, oth = colour ? 0u : plane;
     const T J = (T)R.J, K = (T)R.K, ex = (T)R.e[0], ey = (T)R.e[1], ez = (T)R.e[2];
     const T beta = (T)R.beta;
@@ -359,64 +403,74 @@ k_sc_strip(PassLaunch P, int colour)
     const int xr = xh < Lxh - 1 ? xh + 1 : (px ? 0 : -1);
     const bool left_mem = lane == 0 || xh == 0;           // x-1 not held by lane-1
     const bool right_mem = lane == 63 || xh >= Lxh - 1;   // x+1 not held by lane+1
+    // lane byte offsets within a row; row byte offsets are uniform
+    const uint32_t b_c = (uint32_t)xh * (uint32_t)sizeof(T);
+    const uint32_t b_l = (uint32_t)(xl < 0 ? 0 : xl) * (uint32_t)sizeof(T);
+    const uint32_t b_r = (uint32_t)(xr < 0 ? 0 : xr) * (uint32_t)sizeof(T);
+    const uint32_t row_bytes = (uint32_t)Lxh * (uint32_t)sizeof(T);
+    const PlaneRs<T> q = {plane_rsrc<T>(base_x, 0, R.n_box), plane_rsrc<T>(base_y, 0, R.n_box),
+                          plane_rsrc<T>(base_z, 0, R.n_box)};
+    const uint32_t own_b = own * (uint32_t)sizeof(T), oth_b = oth * (uint32_t)sizeof(T);
+    auto row_off = [&](int y, int z) -> uint32_t {
+        return ((uint32_t)z * (uint32_t)Ly + (uint32_t)y) * row_bytes;
+    };
+    auto load3 = [&](const PlaneRs<T> &q, uint32_t voff, uint32_t soff) -> Vec3<T> {
+        return {buf_load(q.x, voff, soff, T()), buf_load(q.y, voff, soff, T()),
+                buf_load(q.z, voff, soff, T())};
+    };
 
-    // rows y0-1 .. y0+RY: lattice row index or -1 (open face / beyond)
+    // rows y0-1 .. y0+RY: lattice row index or -1 (open face)
     int yrow[RY + 2];
 #pragma unroll
     for (int k = -1; k <= RY; ++k) {
         int y = w.y0 + k;
-        if (y < 0 || y >= Ly) y = py ? ((y % Ly) + Ly) % Ly : -1;
+        if (y < 0 || y >= Ly) {
+            if (!py) y = -1;
+            else {
+                while (y < 0) y += Ly;
+                while (y >= Ly) y -= Ly;
+            }
+        }
         yrow[k + 1] = y;
     }
-    auto load_other = [&](int y, int z) -> Vec3<T> {
-        if (y < 0 || z < 0) return {T(0), T(0), T(0)};
-        const uint32_t j = oth + (uint32_t)(z * Ly + y) * Lxh + xh;
-        return {gx[j], gy[j], gz[j]};
+    auto load_rows = [&](int z, Vec3<T> *dst, int k0, int n) {
+        if (z < 0) {
+            for (int k = 0; k < n; ++k) dst[k] = {T(0), T(0), T(0)};
+            return;
+        }
+        for (int k = 0; k < n; ++k) {
+            const int y = yrow[k0 + k];
+            dst[k] = y < 0 ? Vec3<T>{T(0), T(0), T(0)} : load3(q, b_c, oth_b + row_off(y, z));
+        }
     };
 
     const int z0 = w.z0, z1 = min(w.z0 + P.tile.zc, Lz);
     Vec3<T> om[RY], oc[RY + 2], op[RY + 2];
-    {
-        const int zm = z0 > 0 ? z0 - 1 : (pz ? Lz - 1 : -1);
-#pragma unroll
-        for (int k = 0; k < RY; ++k) om[k] = load_other(yrow[k + 1], zm);
-#pragma unroll
-        for (int k = 0; k < RY + 2; ++k) oc[k] = load_other(yrow[k], z0);
-    }
+    load_rows(z0 > 0 ? z0 - 1 : (pz ? Lz - 1 : -1), om, 1, RY);
+    load_rows(z0, oc, 0, RY + 2);
     double acc[Q_N] = {0, 0, 0, 0, 0, 0};
+    uint32_t n_acc = 0;
     for (int z = z0; z < z1; ++z) {
-        const int zp = z < Lz - 1 ? z + 1 : (pz ? 0 : -1);
-#pragma unroll
-        for (int k = 0; k < RY + 2; ++k) op[k] = load_other(yrow[k], zp);
+        load_rows(z < Lz - 1 ? z + 1 : (pz ? 0 : -1), op, 0, RY + 2);
 #pragma unroll
         for (int k = 0; k < RY; ++k) {
             const int yk = w.y0 + k;
             const bool row_in = yk < Ly;
             const int yc = row_in ? yk : Ly - 1;
             const int p = (colour + yc + z) & 1; // uniform over the workgroup
-            const uint32_t i = own + (uint32_t)(z * Ly + yc) * Lxh + xh;
-            T sx = gx[i], sy = gy[i], sz = gz[i];
+            const uint32_t soff = row_off(yc, z);
+            const uint32_t s_own = own_b + soff, s_oth = oth_b + soff;
+            T sx = buf_load(q.x, b_c, s_own, T()), sy = buf_load(q.y, b_c, s_own, T()),
+              sz = buf_load(q.z, b_c, s_own, T());
             // in-row neighbour on the side given by the parity
             const Vec3<T> c = oc[k + 1];
             Vec3<T> nb;
             if (p == 0) {
                 nb = {from_lower_lane(c.x), from_lower_lane(c.y), from_lower_lane(c.z)};
-                if (left_mem) {
-                    nb = {T(0), T(0), T(0)};
-                    if (xl >= 0) {
-                        const uint32_t j = oth + (uint32_t)(z * Ly + yc) * Lxh + xl;
-                        nb = {gx[j], gy[j], gz[j]};
-                    }
-                }
+                if (left_mem) nb = xl >= 0 ? load3(q, b_l, s_oth) : Vec3<T>{T(0), T(0), T(0)};
             } else {
                 nb = {from_upper_lane(c.x), from_upper_lane(c.y), from_upper_lane(c.z)};
-                if (right_mem) {
-                    nb = {T(0), T(0), T(0)};
-                    if (xr >= 0) {
-                        const uint32_t j = oth + (uint32_t)(z * Ly + yc) * Lxh + xr;
-                        nb = {gx[j], gy[j], gz[j]};
-                    }
-                }
+                if (right_mem) nb = xr >= 0 ? load3(q, b_r, s_oth) : Vec3<T>{T(0), T(0), T(0)};
             }
             // fixed order: -z, -y, -x, +x, +y, +z
             const Vec3<T> lo = p ? c : nb, hi = p ? nb : c;
@@ -428,32 +482,43 @@ k_sc_strip(PassLaunch P, int colour)
             hz *= J;
             const bool live = xin && row_in;
             bool a = false;
-            if (MODE == 0) {
+            if (MODE != 1) {
                 const uint32_t s = (uint32_t)(z * Ly + yc) * (uint32_t)Lx + 2u * xh + p;
                 T dH;
-                a = metropolis<T>(sx, sy, sz, hx, hy, hz, s, R.rid, t, P.seed_lo, P.seed_hi, K,
+                a = metropolis<T>(sx, sy, sz, hx, hy, hz, s, rid, t, P.seed_lo, P.seed_hi, K,
                                   ex, ey, ez, beta, greedy, dH);
                 if (live) {
-                    if (P.dbg_dh) ((T *)P.dbg_dh)[i] = dH;
-                    if (P.dbg_acc) P.dbg_acc[i] = a ? 1 : 0;
+                    const uint32_t i = own + (uint32_t)(z * Ly + yc) * Lxh + xh;
+                    if (MODE == 2) {
+                        ((T *)P.dbg_dh)[i] = dH;
+                        P.dbg_acc[i] = a ? 1 : 0;
+                    }
                     if (a) {
-                        gx[i] = sx;
-                        gy[i] = sy;
-                        gz[i] = sz;
+                        buf_store(sx, q.x, b_c, s_own);
+                        buf_store(sy, q.y, b_c, s_own);
+                        buf_store(sz, q.z, b_c, s_own);
                     }
                 }
             }
-            if (MEASURE && live)
-                accumulate<T>(acc, sx, sy, sz, ex, ey, ez,
-                              colour == 1 ? sx * hx + sy * hy + sz * hz : T(0), a);
+            if (MEASURE && live) {
+                acc[Q_MX] += (double)sx;
+                acc[Q_MY] += (double)sy;
+                acc[Q_MZ] += (double)sz;
+                const double pe = (double)(sx * ex + sy * ey + sz * ez);
+                acc[Q_PE2] += pe * pe;
+                if (colour == 1) acc[Q_SH] += (double)(sx * hx + sy * hy + sz * hz);
+                n_acc += a ? 1u : 0u;
+            }
         }
 #pragma unroll
         for (int k = 0; k < RY; ++k) om[k] = oc[k + 1];
 #pragma unroll
         for (int k = 0; k < RY + 2; ++k) oc[k] = op[k];
     }
-    if (MEASURE)
+    if (MEASURE) {
+        acc[Q_NACC] = (double)n_acc;
         block_store_partials(acc, P.partials_dev + ((size_t)colour * P.n_items + item) * NQ);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -539,13 +604,15 @@ k_basis_pass(PassLaunch P)
             const uint32_t i = (uint32_t)B * plane + cell;
             T sx = gx[i], sy = gy[i], sz = gz[i];
             bool a = false;
-            if (MODE == 0) {
+            if (MODE != 1) {
                 const uint32_t s = cell * NB + B;
                 T dH;
                 a = metropolis<T>(sx, sy, sz, hx, hy, hz, s, R.rid, t, P.seed_lo, P.seed_hi, K,
                                   ex, ey, ez, beta, greedy, dH);
-                if (P.dbg_dh) ((T *)P.dbg_dh)[i] = dH;
-                if (P.dbg_acc) P.dbg_acc[i] = a ? 1 : 0;
+                if (MODE == 2) {
+                    ((T *)P.dbg_dh)[i] = dH;
+                    P.dbg_acc[i] = a ? 1 : 0;
+                }
                 if (a) {
                     gx[i] = sx;
                     gy[i] = sy;
@@ -760,6 +827,11 @@ hipError_t launch_pass(int kind, bool f64, int colour, bool measure, int mode, c
     if (mode == 1) {
         return f64 ? pass_dispatch<double, true, 1>(kind, colour, p, st)
                    : pass_dispatch<float, true, 1>(kind, colour, p, st);
+    }
+    if (mode == 2) {
+        if (!p.dbg_dh || !p.dbg_acc) return hipErrorInvalidValue;
+        return f64 ? pass_dispatch<double, false, 2>(kind, colour, p, st)
+                   : pass_dispatch<float, false, 2>(kind, colour, p, st);
     }
     if (f64)
         return measure ? pass_dispatch<double, true, 0>(kind, colour, p, st)

@@ -24,7 +24,8 @@ struct PassLaunch {
     uint8_t *dbg_acc;         // debug: per-site decision (or null)
 };
 
-// mode: 0 = Metropolis update, 1 = observables of the current state only
+// mode: 0 = Metropolis update, 1 = observables of the current state only,
+//       2 = update writing per-site dH and decisions to p.dbg_dh / p.dbg_acc
 hipError_t launch_pass(int kind, bool f64, int colour, bool measure, int mode,
                        const PassLaunch &p, hipStream_t st);
 
