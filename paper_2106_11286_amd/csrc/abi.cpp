@@ -152,10 +152,10 @@ Tile default_tile(const mc_replica_desc *reps, int n)
     bool fits = true; // the strip kernel addresses each component array with 32-bit offsets
     for (int r = 0; r < n; ++r) fits &= box_sites(reps[r]) * sizeof(double) <= 0xFFFFFFFFull;
     if (reps[0].kind == MC_SC && Wmin >= 48 && fits) {
-        // row strips: whole rows per workgroup (up to 256 columns), 4 rows per thread
+        // row strips: whole rows per workgroup (up to 256 columns), 2 rows per thread
         t.kernel = KERNEL_STRIP;
         t.tx = std::min(256, (W + 63) / 64 * 64);
-        t.ty = 4;
+        t.ty = 2;
     } else {
         t.kernel = KERNEL_TILE;
         t.tx = std::min(64, pow2_at_least(W));
@@ -228,7 +228,7 @@ void make_work(const mc_replica_desc *reps, int n, const Tile &t, std::vector<Wo
 }
 
 struct ScratchLayout {
-    uint64_t off_ctr, off_reps, off_work, off_partials, off_records, total;
+    uint64_t off_ctr, off_reps, off_work, off_partials, off_records, off_stage, off_count, total;
 };
 
 ScratchLayout scratch_layout(int n_reps, uint64_t n_items, int n_colours)
@@ -246,6 +246,10 @@ ScratchLayout scratch_layout(int n_reps, uint64_t n_items, int n_colours)
     L.off_records = o;
     // ring of records plus one slot for from-scratch measurements
     o = align_up(o + sizeof(double) * NR * n_reps * (kRing + 1), 256);
+    L.off_stage = o;
+    o = align_up(o + sizeof(double) * NQ * FIN_BLOCKS * n_reps, 256);
+    L.off_count = o;
+    o = align_up(o + sizeof(uint32_t) * n_reps, 256);
     L.total = o;
     return L;
 }
@@ -299,6 +303,8 @@ struct mc_sim {
     WorkItem *work_dev = nullptr;
     double *partials = nullptr;
     double *records = nullptr;
+    double *stage = nullptr;    // finalise stage slots
+    uint32_t *fin_count = nullptr;
     double *host_rec = nullptr; // pinned, (kRing + 1) * n_reps * NR
     uint64_t t = 0;             // sweeps done
     uint64_t n_measured = 0;
@@ -343,7 +349,7 @@ mc_status enqueue_sweeps(mc_sim *h, uint32_t n, bool measure, uint32_t slot0)
             const uint32_t slot = (slot0 + i) % kRing;
             HIP_TRY(launch_finalize(h->reps_dev, h->n_reps, h->n_colours, h->partials, n_items,
                                     h->tctr, i, h->records + (size_t)slot * h->n_reps * NR,
-                                    h->stream));
+                                    h->stage, h->fin_count, h->stream));
         }
     }
     HIP_TRY(launch_advance(h->tctr, n, h->stream));
@@ -550,6 +556,8 @@ mc_status mc_init_lattice(const mc_replica_desc *reps, int32_t n_reps, mc_precis
     h->work_dev = (WorkItem *)(h->scratch + h->lay.off_work);
     h->partials = (double *)(h->scratch + h->lay.off_partials);
     h->records = (double *)(h->scratch + h->lay.off_records);
+    h->stage = (double *)(h->scratch + h->lay.off_stage);
+    h->fin_count = (uint32_t *)(h->scratch + h->lay.off_count);
 
     h->reps.resize(n_reps);
     h->n_occ.resize(n_reps);
@@ -590,7 +598,8 @@ mc_status mc_init_lattice(const mc_replica_desc *reps, int32_t n_reps, mc_precis
     if ((s = upload_reps(h)) != MC_OK) return cleanup(s);
     if (hipMemcpyAsync(h->work_dev, h->work.data(), sizeof(WorkItem) * h->work.size(),
                        hipMemcpyHostToDevice, h->stream) != hipSuccess ||
-        launch_set_counter(h->tctr, 0u, h->stream) != hipSuccess)
+        launch_set_counter(h->tctr, 0u, h->stream) != hipSuccess ||
+        launch_zero_u32(h->fin_count, (uint32_t)n_reps, h->stream) != hipSuccess)
         return cleanup(fail(MC_E_DEVICE, "upload failed: %s", hipGetErrorString(hipGetLastError())));
     if (init != MC_INIT_USER) {
         for (int r = 0; r < n_reps; ++r) {
@@ -657,7 +666,7 @@ mc_status mc_sweep_timed(mc_sim *h, uint32_t n_sweeps, uint32_t flags, double *p
             err = launch_finalize(h->reps_dev, h->n_reps, h->n_colours, h->partials, n_items,
                                   h->tctr, i,
                                   h->records + (size_t)((slot0 + i) % kRing) * h->n_reps * NR,
-                                  h->stream);
+                                  h->stage, h->fin_count, h->stream);
     }
     if (err == hipSuccess) err = launch_advance(h->tctr, n_sweeps, h->stream);
     if (err == hipSuccess) err = hipEventRecord(ev[2 * n_pass + 1], h->stream);
@@ -710,7 +719,7 @@ mc_status mc_measure_state(mc_sim *h, mc_obs *out, int32_t n_reps)
     for (int c = 0; c < h->n_colours; ++c) HIP_TRY(launch_pass(h->kind, f64, c, true, 1, p, h->stream));
     double *dst = h->records + (size_t)kRing * h->n_reps * NR;
     HIP_TRY(launch_finalize(h->reps_dev, h->n_reps, h->n_colours, h->partials, n_items, h->tctr,
-                            0, dst, h->stream));
+                            0, dst, h->stage, h->fin_count, h->stream));
     HIP_TRY(hipMemcpyAsync(h->host_rec, dst, sizeof(double) * NR * h->n_reps,
                            hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
@@ -854,7 +863,10 @@ mc_status mc_set_tile(mc_sim *h, int32_t kernel, int32_t tx, int32_t ty, int32_t
     h->work_dev = (WorkItem *)(h->scratch + lay.off_work);
     h->partials = (double *)(h->scratch + lay.off_partials);
     h->records = (double *)(h->scratch + lay.off_records);
+    h->stage = (double *)(h->scratch + lay.off_stage);
+    h->fin_count = (uint32_t *)(h->scratch + lay.off_count);
     h->last_slot = -1;
+    HIP_TRY(launch_zero_u32(h->fin_count, (uint32_t)h->n_reps, h->stream));
     for (int r = 0; r < h->n_reps; ++r) {
         h->reps[r].item_begin = b[r];
         h->reps[r].item_end = e[r];

@@ -444,14 +444,35 @@ k_sc_strip(PassLaunch P, int colour)
         }
     };
 
+    // In-row neighbours that the lane shift cannot supply (wave edges, the
+    // periodic wrap, open faces) are loaded one plane ahead by the lanes that
+    // need them, so the loads never stall the plane being updated.
+    auto load_edges = [&](int z, Vec3<T> *dst) {
+#pragma unroll
+        for (int k = 0; k < RY; ++k) {
+            const int yk = w.y0 + k;
+            const int yc = yk < Ly ? yk : Ly - 1;
+            const int p = (colour + yc + z) & 1;
+            const bool need = p ? right_mem : left_mem;
+            const int col = p ? xr : xl;
+            if (need && col >= 0)
+                dst[k] = load3(q, p ? b_r : b_l, oth_b + row_off(yc, z));
+            else
+                dst[k] = {T(0), T(0), T(0)};
+        }
+    };
+
     const int z0 = w.z0, z1 = min(w.z0 + P.tile.zc, Lz);
-    Vec3<T> om[RY], oc[RY + 2], op[RY + 2];
+    Vec3<T> om[RY], oc[RY + 2], op[RY + 2], ec[RY], en[RY];
     load_rows(z0 > 0 ? z0 - 1 : (pz ? Lz - 1 : -1), om, 1, RY);
     load_rows(z0, oc, 0, RY + 2);
+    load_edges(z0, ec);
     double acc[Q_N] = {0, 0, 0, 0, 0, 0};
     uint32_t n_acc = 0;
     for (int z = z0; z < z1; ++z) {
-        load_rows(z < Lz - 1 ? z + 1 : (pz ? 0 : -1), op, 0, RY + 2);
+        const int zn = z < Lz - 1 ? z + 1 : (pz ? 0 : -1);
+        load_rows(zn, op, 0, RY + 2);
+        if (z + 1 < z1) load_edges(zn, en);
 #pragma unroll
         for (int k = 0; k < RY; ++k) {
             const int yk = w.y0 + k;
@@ -459,19 +480,18 @@ k_sc_strip(PassLaunch P, int colour)
             const int yc = row_in ? yk : Ly - 1;
             const int p = (colour + yc + z) & 1; // uniform over the workgroup
             const uint32_t soff = row_off(yc, z);
-            const uint32_t s_own = own_b + soff, s_oth = oth_b + soff;
+            const uint32_t s_own = own_b + soff;
             T sx = buf_load(q.x, b_c, s_own, T()), sy = buf_load(q.y, b_c, s_own, T()),
               sz = buf_load(q.z, b_c, s_own, T());
             // in-row neighbour on the side given by the parity
             const Vec3<T> c = oc[k + 1];
+            const bool from_mem = p ? right_mem : left_mem;
             Vec3<T> nb;
-            if (p == 0) {
+            if (p == 0)
                 nb = {from_lower_lane(c.x), from_lower_lane(c.y), from_lower_lane(c.z)};
-                if (left_mem) nb = xl >= 0 ? load3(q, b_l, s_oth) : Vec3<T>{T(0), T(0), T(0)};
-            } else {
+            else
                 nb = {from_upper_lane(c.x), from_upper_lane(c.y), from_upper_lane(c.z)};
-                if (right_mem) nb = xr >= 0 ? load3(q, b_r, s_oth) : Vec3<T>{T(0), T(0), T(0)};
-            }
+            if (from_mem) nb = ec[k];
             // fixed order: -z, -y, -x, +x, +y, +z
             const Vec3<T> lo = p ? c : nb, hi = p ? nb : c;
             T hx = om[k].x + oc[k].x + lo.x + hi.x + oc[k + 2].x + op[k + 1].x;
@@ -514,6 +534,8 @@ k_sc_strip(PassLaunch P, int colour)
         for (int k = 0; k < RY; ++k) om[k] = oc[k + 1];
 #pragma unroll
         for (int k = 0; k < RY + 2; ++k) oc[k] = op[k];
+#pragma unroll
+        for (int k = 0; k < RY; ++k) ec[k] = en[k];
     }
     if (MEASURE) {
         acc[Q_NACC] = (double)n_acc;
@@ -716,35 +738,60 @@ k_layout(RepDev R, int kind, int to_natural, T *nx, T *ny, T *nz)
 }
 
 // ---------------------------------------------------------------------------
-// Finalise: one block per replica sums its partial slots of every pass in a
-// fixed order and writes one FP64 record.
+// Finalise: FIN_BLOCKS blocks per replica each sum a contiguous share of the
+// replica's partial slots (all passes) into a stage slot; the last block to
+// finish (counted with an agent-scope atomic) sums the stage slots in index
+// order and writes the FP64 record, then re-arms the counter.  The result
+// depends only on the work list, not on block timing.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256)
 k_finalize(const RepDev *__restrict__ reps, int n_colours, const double *__restrict__ partials,
            uint32_t n_items, const uint32_t *__restrict__ tctr, uint32_t t_off,
-           double *__restrict__ records)
+           double *__restrict__ records, double *__restrict__ stage, uint32_t *__restrict__ count)
 {
-    const RepDev &R = reps[blockIdx.x];
+    const uint32_t r = blockIdx.x / FIN_BLOCKS, j = blockIdx.x % FIN_BLOCKS;
+    const RepDev &R = reps[r];
+    const uint32_t n = R.item_end - R.item_begin;
+    const uint32_t b0 = R.item_begin + (uint32_t)(((uint64_t)n * j) / FIN_BLOCKS);
+    const uint32_t b1 = R.item_begin + (uint32_t)(((uint64_t)n * (j + 1)) / FIN_BLOCKS);
     double a[Q_N] = {0, 0, 0, 0, 0, 0};
     for (int c = 0; c < n_colours; ++c)
-        for (uint32_t it = R.item_begin + threadIdx.x; it < R.item_end; it += blockDim.x) {
+        for (uint32_t it = b0 + threadIdx.x; it < b1; it += blockDim.x) {
             const double *p = partials + ((size_t)c * n_items + it) * NQ;
 #pragma unroll
             for (int q = 0; q < Q_N; ++q) a[q] += p[q];
         }
-    __shared__ double out[NQ];
-    block_store_partials(a, out);
+    double *slot = stage + ((size_t)r * FIN_BLOCKS + j) * NQ;
+    block_store_partials(a, slot);
+    __shared__ uint32_t last;
+    __threadfence(); // the stage slot is visible device-wide before it is counted
     __syncthreads();
     if (threadIdx.x == 0) {
-        double *r = records + (size_t)blockIdx.x * NR;
-        r[R_MX] = out[Q_MX];
-        r[R_MY] = out[Q_MY];
-        r[R_MZ] = out[Q_MZ];
-        r[R_EEX] = -out[Q_SH];
-        r[R_EAN] = -R.K * out[Q_PE2];
-        r[R_NACC] = out[Q_NACC];
-        r[R_SWEEP] = (double)(*tctr + t_off) + 1.0;
-        r[7] = 0.0;
+        const uint32_t done = __hip_atomic_fetch_add(&count[r], 1u, __ATOMIC_ACQ_REL,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+        last = done == FIN_BLOCKS - 1;
+    }
+    __syncthreads();
+    if (!last) return;
+    if (threadIdx.x == 0) {
+        __atomic_thread_fence(__ATOMIC_ACQUIRE);
+        double out[Q_N] = {0, 0, 0, 0, 0, 0};
+        const double *st = stage + (size_t)r * FIN_BLOCKS * NQ;
+        for (uint32_t b = 0; b < FIN_BLOCKS; ++b)
+#pragma unroll
+            for (int q = 0; q < Q_N; ++q)
+                out[q] += __hip_atomic_load(&st[b * NQ + q], __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
+        double *rec = records + (size_t)r * NR;
+        rec[R_MX] = out[Q_MX];
+        rec[R_MY] = out[Q_MY];
+        rec[R_MZ] = out[Q_MZ];
+        rec[R_EEX] = -out[Q_SH];
+        rec[R_EAN] = -R.K * out[Q_PE2];
+        rec[R_NACC] = out[Q_NACC];
+        rec[R_SWEEP] = (double)(*tctr + t_off) + 1.0;
+        rec[7] = 0.0;
+        __hip_atomic_store(&count[r], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -875,10 +922,25 @@ hipError_t launch_layout(bool f64, int kind, const RepDev *rep_host, bool to_nat
 hipError_t launch_finalize(const RepDev *reps_dev, int n_reps, int n_colours,
                            const double *partials_dev, uint32_t n_items,
                            const uint32_t *tctr_dev, uint32_t t_off, double *records_dev,
-                           hipStream_t st)
+                           double *stage_dev, uint32_t *count_dev, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_finalize, dim3(n_reps), dim3(256), 0, st, reps_dev, n_colours,
-                       partials_dev, n_items, tctr_dev, t_off, records_dev);
+    hipLaunchKernelGGL(k_finalize, dim3(n_reps * FIN_BLOCKS), dim3(256), 0, st, reps_dev,
+                       n_colours, partials_dev, n_items, tctr_dev, t_off, records_dev, stage_dev,
+                       count_dev);
+    return hipGetLastError();
+}
+
+__global__ void k_zero_u32(uint32_t *p, uint32_t n)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+hipError_t launch_zero_u32(uint32_t *p, uint32_t n, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_u32, dim3((n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024), dim3(256),
+                       0, st, p, n);
     return hipGetLastError();
 }
 

@@ -37,6 +37,9 @@ struct alignas(16) WorkItem {
 enum : int { Q_MX = 0, Q_MY, Q_MZ, Q_PE2, Q_SH, Q_NACC, Q_N };
 constexpr int NQ = 8; // padded slot width (doubles)
 
+// Workgroups per replica in the first stage of the observable finalise.
+constexpr uint32_t FIN_BLOCKS = 32;
+
 // Record written by the finalise kernel (FP64), per replica per measured sweep.
 enum : int { R_MX = 0, R_MY, R_MZ, R_EEX, R_EAN, R_NACC, R_SWEEP, R_N };
 constexpr int NR = 8;
