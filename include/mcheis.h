@@ -53,8 +53,13 @@ typedef enum { MC_SC = 0, MC_BCC = 1, MC_FCC = 2 } mc_lattice_kind;
 typedef enum { MC_F32 = 0, MC_F64 = 1 } mc_precision;
 typedef enum { MC_INIT_RANDOM = 0, MC_INIT_ALIGNED = 1, MC_INIT_USER = 2 } mc_init_mode;
 
-/* mc_sweep flags */
-#define MC_MEASURE 1u /* reduce observables on every sweep of this call */
+/* mc_sweep / mc_schedule flags */
+#define MC_MEASURE 1u    /* reduce observables on every sweep of this call            */
+#define MC_PERSISTENT 2u /* run the sweeps as one persistent launch: work units       */
+                         /* (sweep, colour, tile) are claimed in order by the resident */
+                         /* workgroups, each replica advancing as soon as its previous */
+                         /* pass is complete (no grid-wide barrier).  Results are      */
+                         /* bitwise identical to the default launches.                */
 
 /* One replica: lattice geometry and model parameters (Eq. (1)).
  *  kind          sc / bcc / fcc conventional cubic cells.
@@ -114,6 +119,7 @@ typedef struct {
     int32_t n_T;
     const double *T; /* host array [n_T][n_reps] */
     uint32_t n_equil, n_meas, measure_every;
+    uint32_t flags;  /* 0 or MC_PERSISTENT */
 } mc_schedule;
 
 /* Summary statistics of one replica's series (equilibrium averages over the
@@ -216,7 +222,11 @@ mc_status mc_set_sweep(mc_sim *h, uint64_t t);
  *  kernel 0 (any lattice): tx*ty <= 256 threads, one column and row each;
  *  kernel 1 (sc only): tx threads along the row (64, 128, 192 or 256), each
  *    holding ty consecutive rows (1, 2, 4 or 8), with the other colour kept in
- *    registers across planes.
+ *    registers across planes;
+ *  kernel 2 (sc only, default): as kernel 1, but rows grouped in bands of ty
+ *    rows (2 or 4) and the (band, column) positions dealt to the tx threads
+ *    contiguously, so no lane idles whatever the row length; a tile is tx
+ *    positions x zc planes.
  * The spins do not depend on the choice (only the FP64 summation order of the
  * observables does).  A shape whose work list does not fit the handle's
  * scratch gives MC_E_BUFFER.  Discards the record of the last measured sweep.
@@ -233,6 +243,17 @@ mc_status mc_num_colours(const mc_sim *h, int32_t *n_colours);
  * output), at temperature T (used by C and chi). */
 mc_status mc_series_stats(const mc_obs *series, uint64_t n, uint64_t stride, double T,
                           mc_stats *out);
+
+/* Bounded wait of persistent launches: a work unit waiting for its replica's
+ * previous pass gives up after `spins` polls (about 0.1 us each; default
+ * 2^24).  A launch that gave up sets the handle's watchdog flag: the next
+ * synchronising call returns MC_E_DEVICE and the spins of that call are
+ * incomplete.  Every workgroup still exits normally. */
+mc_status mc_set_watchdog(mc_sim *h, uint32_t spins);
+
+/* Wait for all enqueued work of the handle and report deferred errors
+ * (device faults, a tripped persistent-launch watchdog). */
+mc_status mc_synchronize(mc_sim *h);
 
 /* Release the handle (never the caller's buffers, scratch or stream). */
 void mc_destroy(mc_sim *h);

@@ -126,14 +126,22 @@ int pow2_at_least(int v)
     return p;
 }
 
+// Workgroup tiles covering one z plane of a replica.
+uint64_t xy_tiles(const mc_replica_desc &d, const Tile &t)
+{
+    if (t.kernel == KERNEL_BAND) {
+        const uint64_t F = (uint64_t)((d.Ly + t.ty - 1) / t.ty) * row_len(d);
+        return (F + t.tx - 1) / t.tx;
+    }
+    return (uint64_t)((row_len(d) + t.tx - 1) / t.tx) * ((d.Ly + t.ty - 1) / t.ty);
+}
+
 // Planes per workgroup so that a pass has about kTargetItems workgroups.
 int z_chunk(const mc_replica_desc *reps, int n, const Tile &t)
 {
     uint64_t cols = 0, planes = 0;
     for (int r = 0; r < n; ++r) {
-        const uint64_t c = (uint64_t)((row_len(reps[r]) + t.tx - 1) / t.tx) *
-                           ((reps[r].Ly + t.ty - 1) / t.ty);
-        cols += c * reps[r].Lz;
+        cols += xy_tiles(reps[r], t) * reps[r].Lz;
         planes = std::max<uint64_t>(planes, reps[r].Lz);
     }
     const uint64_t zc = (cols + kTargetItems - 1) / kTargetItems;
@@ -151,10 +159,10 @@ Tile default_tile(const mc_replica_desc *reps, int n)
     Tile t;
     bool fits = true; // the strip kernel addresses each component array with 32-bit offsets
     for (int r = 0; r < n; ++r) fits &= box_sites(reps[r]) * sizeof(double) <= 0xFFFFFFFFull;
-    if (reps[0].kind == MC_SC && Wmin >= 48 && fits) {
-        // row strips: whole rows per workgroup (up to 256 columns), 2 rows per thread
-        t.kernel = KERNEL_STRIP;
-        t.tx = std::min(256, (W + 63) / 64 * 64);
+    if (reps[0].kind == MC_SC && fits) {
+        // bands of 2 rows, (band, column) positions dealt to 256 threads
+        t.kernel = KERNEL_BAND;
+        t.tx = 256;
         t.ty = 2;
     } else {
         t.kernel = KERNEL_TILE;
@@ -167,7 +175,15 @@ Tile default_tile(const mc_replica_desc *reps, int n)
 
 mc_status check_tile(const Tile &t, int kind, uint64_t max_component_bytes)
 {
-    if (t.kernel == KERNEL_STRIP) {
+    if (t.kernel == KERNEL_BAND) {
+        if (kind != MC_SC) return fail(MC_E_ARG, "the band kernel is for simple cubic lattices");
+        if (max_component_bytes > 0xFFFFFFFFull)
+            return fail(MC_E_UNSUPPORTED, "band kernel: a spin component array exceeds 4 GiB");
+        if (t.tx < 64 || t.tx > 256 || t.tx % 64)
+            return fail(MC_E_ARG, "band tile: tx must be 64, 128, 192 or 256 (got %d)", t.tx);
+        if (t.ty != 2 && t.ty != 4)
+            return fail(MC_E_ARG, "band tile: ty (rows per band) must be 2 or 4");
+    } else if (t.kernel == KERNEL_STRIP) {
         if (kind != MC_SC) return fail(MC_E_ARG, "the strip kernel is for simple cubic lattices");
         if (max_component_bytes > 0xFFFFFFFFull)
             return fail(MC_E_UNSUPPORTED, "strip kernel: a spin component array exceeds 4 GiB");
@@ -206,6 +222,25 @@ void make_work(const mc_replica_desc *reps, int n, const Tile &t, std::vector<Wo
         begin[r] = (uint32_t)work.size();
         const int W = row_len(d);
         const bool sc = d.kind == MC_SC;
+        if (t.kernel == KERNEL_BAND) {
+            const int rows = t.ty;
+            const int F = (d.Ly + rows - 1) / rows * W;
+            for (int z0 = 0; z0 < d.Lz; z0 += t.zc)
+                for (int f0 = 0; f0 < F; f0 += t.tx) {
+                    if (d.sphere_radius > 0.0) {
+                        const int y0 = f0 / W * rows;
+                        const int y1 = std::min(d.Ly, ((f0 + t.tx - 1) / W + 1) * rows) - 1;
+                        const int cz1 = std::min(d.Lz, z0 + t.zc) - 1;
+                        const int64_t m = min_sq(-d.Lx, d.Lx - 1) +
+                                          min_sq(2 * y0 - d.Ly, 2 * y1 + 1 - d.Ly) +
+                                          min_sq(2 * z0 - d.Lz, 2 * cz1 + 1 - d.Lz);
+                        if ((double)m > 4.0 * d.sphere_radius * d.sphere_radius) continue;
+                    }
+                    work.push_back(WorkItem{(uint32_t)r, f0, 0, z0});
+                }
+            end[r] = (uint32_t)work.size();
+            continue;
+        }
         for (int z0 = 0; z0 < d.Lz; z0 += t.zc)
             for (int x0 = 0; x0 < W; x0 += t.tx)
                 for (int y0 = 0; y0 < d.Ly; y0 += t.ty) {
@@ -228,7 +263,8 @@ void make_work(const mc_replica_desc *reps, int n, const Tile &t, std::vector<Wo
 }
 
 struct ScratchLayout {
-    uint64_t off_ctr, off_reps, off_work, off_partials, off_records, off_stage, off_count, total;
+    uint64_t off_ctr, off_reps, off_work, off_partials, off_records, off_stage, off_count,
+        off_persist, total;
 };
 
 ScratchLayout scratch_layout(int n_reps, uint64_t n_items, int n_colours)
@@ -250,6 +286,8 @@ ScratchLayout scratch_layout(int n_reps, uint64_t n_items, int n_colours)
     o = align_up(o + sizeof(double) * NQ * FIN_BLOCKS * n_reps, 256);
     L.off_count = o;
     o = align_up(o + sizeof(uint32_t) * n_reps, 256);
+    L.off_persist = o;
+    o = align_up(o + sizeof(uint32_t) * persist_state_words(n_reps), 256);
     L.total = o;
     return L;
 }
@@ -305,6 +343,9 @@ struct mc_sim {
     double *records = nullptr;
     double *stage = nullptr;    // finalise stage slots
     uint32_t *fin_count = nullptr;
+    uint32_t *pstate = nullptr; // persistent-launch counters
+    uint32_t spin_limit = 1u << 24;
+    bool persist_used = false;
     double *host_rec = nullptr; // pinned, (kRing + 1) * n_reps * NR
     uint64_t t = 0;             // sweeps done
     uint64_t n_measured = 0;
@@ -356,6 +397,45 @@ mc_status enqueue_sweeps(mc_sim *h, uint32_t n, bool measure, uint32_t slot0)
     return MC_OK;
 }
 
+// n sweeps as one persistent launch (preceded by a counter reset, followed by
+// the counter advance).  Pure launches: safe inside stream capture.
+mc_status enqueue_persistent(mc_sim *h, uint32_t n, bool measure, uint32_t slot0)
+{
+    const uint32_t n_items = (uint32_t)h->work.size();
+    if ((uint64_t)n * h->n_colours * n_items >= 0xFFFFFFFFull)
+        return fail(MC_E_ARG, "persistent launch of %u sweeps exceeds 2^32 work units", n);
+    PersistLaunch a;
+    a.state = h->pstate;
+    a.n_sweeps = n;
+    a.n_colours = (uint32_t)h->n_colours;
+    a.n_reps = (uint32_t)h->n_reps;
+    a.spin_limit = h->spin_limit;
+    a.records = h->records;
+    a.ring = kRing;
+    a.slot0 = slot0;
+    HIP_TRY(launch_zero_u32(h->pstate, persist_state_words(h->n_reps), h->stream));
+    HIP_TRY(launch_persistent(h->kind, h->prec == MC_F64, measure, pass_args(h, 0, n_items, 0), a,
+                              h->stream));
+    HIP_TRY(launch_advance(h->tctr, n, h->stream));
+    h->persist_used = true;
+    return MC_OK;
+}
+
+// After a synchronisation: report a persistent launch whose bounded wait gave
+// up (the spins of that call are then incomplete).
+mc_status check_persistent(mc_sim *h)
+{
+    if (!h->persist_used) return MC_OK;
+    uint32_t hdr[4] = {0, 0, 0, 0};
+    HIP_TRY(hipMemcpy(hdr, h->pstate, sizeof hdr, hipMemcpyDeviceToHost));
+    h->persist_used = false;
+    if (hdr[2])
+        return fail(MC_E_DEVICE, "persistent sweep: a wait for a replica's previous pass exceeded "
+                                 "%u spins; the state of that call is incomplete",
+                    h->spin_limit);
+    return MC_OK;
+}
+
 void record_to_obs(const mc_sim *h, const double *rec, int r, mc_obs *o)
 {
     const double N = (double)h->n_occ[r];
@@ -383,17 +463,21 @@ void set_temperature(RepDev &R, double T)
     R.beta = (T > 0.0 && std::isfinite(T)) ? 1.0 / T : 0.0;
 }
 
-mc_status run_chunk(mc_sim *h, uint32_t n, bool measure, uint32_t slot0)
+mc_status run_chunk(mc_sim *h, uint32_t n, bool measure, uint32_t slot0, bool persistent)
 {
     if (n == 0) return MC_OK;
-    if (!h->stream) return enqueue_sweeps(h, n, measure, slot0);
+    if (!h->stream)
+        return persistent ? enqueue_persistent(h, n, measure, slot0)
+                          : enqueue_sweeps(h, n, measure, slot0);
     // replay a captured graph of n sweeps; graphs bake the ring slots, so a
     // measured graph is keyed by its first slot too (callers use slot 0)
-    const std::pair<uint32_t, uint32_t> key(n, measure ? 1u + slot0 : 0u);
+    const std::pair<uint32_t, uint32_t> key(n | (persistent ? 0x80000000u : 0u),
+                                            measure ? 1u + slot0 : 0u);
     auto it = h->graphs.find(key);
     if (it == h->graphs.end()) {
         HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-        mc_status s = enqueue_sweeps(h, n, measure, slot0);
+        mc_status s = persistent ? enqueue_persistent(h, n, measure, slot0)
+                                 : enqueue_sweeps(h, n, measure, slot0);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(h->stream, &g);
         if (s != MC_OK) {
@@ -408,6 +492,7 @@ mc_status run_chunk(mc_sim *h, uint32_t n, bool measure, uint32_t slot0)
         it = h->graphs.emplace(key, ex).first;
     }
     HIP_TRY(hipGraphLaunch(it->second, h->stream));
+    if (persistent) h->persist_used = true;
     return MC_OK;
 }
 
@@ -558,6 +643,7 @@ mc_status mc_init_lattice(const mc_replica_desc *reps, int32_t n_reps, mc_precis
     h->records = (double *)(h->scratch + h->lay.off_records);
     h->stage = (double *)(h->scratch + h->lay.off_stage);
     h->fin_count = (uint32_t *)(h->scratch + h->lay.off_count);
+    h->pstate = (uint32_t *)(h->scratch + h->lay.off_persist);
 
     h->reps.resize(n_reps);
     h->n_occ.resize(n_reps);
@@ -619,12 +705,13 @@ mc_status mc_init_lattice(const mc_replica_desc *reps, int32_t n_reps, mc_precis
 mc_status mc_sweep(mc_sim *h, uint32_t n_sweeps, uint32_t flags)
 {
     if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
-    if (flags & ~MC_MEASURE) return fail(MC_E_ARG, "unknown flags 0x%x", flags);
+    if (flags & ~(MC_MEASURE | MC_PERSISTENT)) return fail(MC_E_ARG, "unknown flags 0x%x", flags);
     if (n_sweeps == 0) return MC_OK;
     if (h->t + n_sweeps > 0xFFFFFFFFull) return fail(MC_E_STATE, "sweep counter would exceed 2^32-1");
     const bool measure = flags & MC_MEASURE;
     const uint32_t slot0 = (uint32_t)(h->n_measured % kRing);
-    mc_status s = enqueue_sweeps(h, n_sweeps, measure, slot0);
+    mc_status s = (flags & MC_PERSISTENT) ? enqueue_persistent(h, n_sweeps, measure, slot0)
+                                          : enqueue_sweeps(h, n_sweeps, measure, slot0);
     if (s != MC_OK) return s;
     h->t += n_sweeps;
     if (measure) {
@@ -700,6 +787,9 @@ mc_status mc_observables(mc_sim *h, mc_obs *out, int32_t n_reps)
     if (!out) return fail(MC_E_ARG, "out is NULL");
     if (n_reps != h->n_reps) return fail(MC_E_ARG, "n_reps %d != handle's %d", n_reps, h->n_reps);
     if (h->last_slot < 0) return fail(MC_E_STATE, "no measured sweep yet");
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    mc_status ps = check_persistent(h);
+    if (ps != MC_OK) return ps;
     const size_t sz = sizeof(double) * NR * h->n_reps;
     HIP_TRY(hipMemcpyAsync(h->host_rec, h->records + (size_t)h->last_slot * h->n_reps * NR, sz,
                            hipMemcpyDeviceToHost, h->stream));
@@ -713,6 +803,9 @@ mc_status mc_measure_state(mc_sim *h, mc_obs *out, int32_t n_reps)
     if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
     if (!out) return fail(MC_E_ARG, "out is NULL");
     if (n_reps != h->n_reps) return fail(MC_E_ARG, "n_reps %d != handle's %d", n_reps, h->n_reps);
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    mc_status ps = check_persistent(h);
+    if (ps != MC_OK) return ps;
     const bool f64 = h->prec == MC_F64;
     const uint32_t n_items = (uint32_t)h->work.size();
     const PassLaunch p = pass_args(h, 0, n_items, 0);
@@ -751,6 +844,8 @@ mc_status mc_run_schedule(mc_sim *h, const mc_schedule *s, mc_obs *series, uint6
     if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
     if (!s || !s->T) return fail(MC_E_ARG, "schedule or its T is NULL");
     if (s->n_T < 1 || s->measure_every < 1) return fail(MC_E_ARG, "n_T and measure_every must be >= 1");
+    if (s->flags & ~MC_PERSISTENT) return fail(MC_E_ARG, "unknown schedule flags 0x%x", s->flags);
+    const bool persistent = (s->flags & MC_PERSISTENT) != 0;
     const uint64_t per_step = s->n_meas / s->measure_every;
     const uint64_t need = (uint64_t)s->n_T * per_step * h->n_reps;
     if (need > 0 && !series) return fail(MC_E_ARG, "series is NULL");
@@ -767,20 +862,21 @@ mc_status mc_run_schedule(mc_sim *h, const mc_schedule *s, mc_obs *series, uint6
         if (st != MC_OK) return st;
         for (uint32_t done = 0; done < s->n_equil;) {
             const uint32_t k = std::min(kGraphChunk, s->n_equil - done);
-            if ((st = run_chunk(h, k, false, 0)) != MC_OK) return st;
+            if ((st = run_chunk(h, k, false, 0, persistent)) != MC_OK) return st;
             done += k;
             h->t += k;
         }
         uint32_t meas_idx = 0;
         for (uint32_t done = 0; done < s->n_meas;) {
             const uint32_t k = std::min(kGraphChunk, s->n_meas - done);
-            if ((st = run_chunk(h, k, true, 0)) != MC_OK) return st;
+            if ((st = run_chunk(h, k, true, 0, persistent)) != MC_OK) return st;
             h->t += k;
             h->n_measured += k;
             h->last_slot = k - 1;
             const size_t sz = sizeof(double) * NR * h->n_reps * k;
             HIP_TRY(hipMemcpyAsync(h->host_rec, h->records, sz, hipMemcpyDeviceToHost, h->stream));
             HIP_TRY(hipStreamSynchronize(h->stream));
+            if ((st = check_persistent(h)) != MC_OK) return st;
             for (uint32_t j = 0; j < k; ++j, ++meas_idx) {
                 if ((meas_idx + 1) % s->measure_every) continue;
                 for (int r = 0; r < h->n_reps; ++r)
@@ -791,8 +887,26 @@ mc_status mc_run_schedule(mc_sim *h, const mc_schedule *s, mc_obs *series, uint6
         }
     }
     HIP_TRY(hipStreamSynchronize(h->stream));
+    mc_status fin = check_persistent(h);
+    if (fin != MC_OK) return fin;
     if (n_written) *n_written = written;
     return MC_OK;
+}
+
+mc_status mc_set_watchdog(mc_sim *h, uint32_t spins)
+{
+    if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
+    h->spin_limit = spins;
+    for (auto &kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+    h->graphs.clear();
+    return MC_OK;
+}
+
+mc_status mc_synchronize(mc_sim *h)
+{
+    if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return check_persistent(h);
 }
 
 mc_status mc_debug_pass(mc_sim *h, int32_t colour, void *const *dh, void *const *accepted)
@@ -865,6 +979,7 @@ mc_status mc_set_tile(mc_sim *h, int32_t kernel, int32_t tx, int32_t ty, int32_t
     h->records = (double *)(h->scratch + lay.off_records);
     h->stage = (double *)(h->scratch + lay.off_stage);
     h->fin_count = (uint32_t *)(h->scratch + lay.off_count);
+    h->pstate = (uint32_t *)(h->scratch + lay.off_persist);
     h->last_slot = -1;
     HIP_TRY(launch_zero_u32(h->fin_count, (uint32_t)h->n_reps, h->stream));
     for (int r = 0; r < h->n_reps; ++r) {

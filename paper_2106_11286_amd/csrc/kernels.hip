@@ -240,18 +240,15 @@ __device__ __forceinline__ void accumulate(double (&acc)[Q_N], T sx, T sy, T sz,
 // short rows.
 // ---------------------------------------------------------------------------
 template <typename T, bool MEASURE, int MODE>
-__global__ void __launch_bounds__(256)
-k_sc_tile(PassLaunch P, int colour)
+__device__ __forceinline__ void sc_tile_body(const PassLaunch &P, int colour, uint32_t item,
+                                             uint32_t t)
 {
-    uint32_t item;
-    if (!logical_item(P, item)) return;
     const WorkItem w = P.work_dev[item];
     const RepDev &R = P.reps_dev[w.rep];
     const int Ly = R.Ly, Lz = R.Lz, Lxh = R.Lxh;
     const int lx = threadIdx.x % P.tile.tx, ly = threadIdx.x / P.tile.tx;
     const int xh = w.x0 + lx, y = w.y0 + ly;
     const bool active = xh < Lxh && y < Ly && ly < P.tile.ty;
-    const uint32_t t = *P.tctr_dev + P.t_off;
     const uint32_t plane = R.plane;
     const gptr<T> gx = as_global<T>(R.sx), gy = as_global<T>(R.sy), gz = as_global<T>(R.sz);
     const uint32_t own = colour ? plane : 0u, oth = colour ? 0u : plane;
@@ -376,11 +373,9 @@ template <typename T> struct PlaneRs {
 };
 
 template <typename T, bool MEASURE, int MODE, int RY>
-__global__ void __launch_bounds__(256)
-k_sc_strip(PassLaunch P, int colour)
+__device__ __forceinline__ void sc_strip_body(const PassLaunch &P, int colour, uint32_t item,
+                                              uint32_t t)
 {
-    uint32_t item;
-    if (!logical_item(P, item)) return;
     // every descriptor field is read into registers before the first store, so
     // the loads stay scalar (memory that the kernel may write cannot be)
     const WorkItem w = P.work_dev[item];
@@ -392,7 +387,6 @@ k_sc_strip(PassLaunch P, int colour)
     const int xraw = w.x0 + (int)threadIdx.x;
     const bool xin = xraw < Lxh && (int)threadIdx.x < P.tile.tx;
     const int xh = xin ? xraw : Lxh - 1;
-    const uint32_t t = *P.tctr_dev + P.t_off;
     const uint32_t plane = R.plane;
     const uint32_t own = colour ? plane : 0u, oth = colour ? 0u : plane;
     const T J = (T)R.J, K = (T)R.K, ex = (T)R.e[0], ey = (T)R.e[1], ez = (T)R.e[2];
@@ -433,21 +427,23 @@ k_sc_strip(PassLaunch P, int colour)
         }
         yrow[k + 1] = y;
     }
+    // Loads are issued unconditionally (rows and planes outside an open face
+    // read row / plane 0) and zeroed afterwards by a uniform branch that
+    // periodic lattices never take.
     auto load_rows = [&](int z, Vec3<T> *dst, int k0, int n) {
-        if (z < 0) {
-            for (int k = 0; k < n; ++k) dst[k] = {T(0), T(0), T(0)};
-            return;
-        }
+        const bool z_ok = z >= 0;
+        const int zc = z_ok ? z : 0;
         for (int k = 0; k < n; ++k) {
             const int y = yrow[k0 + k];
-            dst[k] = y < 0 ? Vec3<T>{T(0), T(0), T(0)} : load3(q, b_c, oth_b + row_off(y, z));
+            dst[k] = load3(q, b_c, oth_b + row_off(y < 0 ? 0 : y, zc));
+            if (!z_ok || y < 0) dst[k] = {T(0), T(0), T(0)};
         }
     };
 
     // In-row neighbours that the lane shift cannot supply (wave edges, the
     // periodic wrap, open faces) are loaded one plane ahead by the lanes that
     // need them, so the loads never stall the plane being updated.
-    auto load_edges = [&](int z, Vec3<T> *dst) {
+    auto load_edges = [&](int z, Vec3<T> (&dst)[RY]) {
 #pragma unroll
         for (int k = 0; k < RY; ++k) {
             const int yk = w.y0 + k;
@@ -463,15 +459,16 @@ k_sc_strip(PassLaunch P, int colour)
     };
 
     const int z0 = w.z0, z1 = min(w.z0 + P.tile.zc, Lz);
-    Vec3<T> om[RY], oc[RY + 2], op[RY + 2], ec[RY], en[RY];
-    load_rows(z0 > 0 ? z0 - 1 : (pz ? Lz - 1 : -1), om, 1, RY);
-    load_rows(z0, oc, 0, RY + 2);
-    load_edges(z0, ec);
     double acc[Q_N] = {0, 0, 0, 0, 0, 0};
     uint32_t n_acc = 0;
-    for (int z = z0; z < z1; ++z) {
+    // One plane: rows of the other colour at z-1 (pm), z (pc) and z+1 (pn,
+    // loaded here), in-row edge values of plane z (ec) and z+1 (en, loaded
+    // here).  The plane sets form a ring of three; the loop is unrolled by
+    // three so that the ring turns without moving registers.
+    auto step = [&](const Vec3<T> (&pm)[RY + 2], const Vec3<T> (&pc)[RY + 2],
+                    Vec3<T> (&pn)[RY + 2], const Vec3<T> (&ec)[RY], Vec3<T> (&en)[RY], int z) {
         const int zn = z < Lz - 1 ? z + 1 : (pz ? 0 : -1);
-        load_rows(zn, op, 0, RY + 2);
+        load_rows(zn, pn, 0, RY + 2);
         if (z + 1 < z1) load_edges(zn, en);
 #pragma unroll
         for (int k = 0; k < RY; ++k) {
@@ -484,7 +481,7 @@ k_sc_strip(PassLaunch P, int colour)
             T sx = buf_load(q.x, b_c, s_own, T()), sy = buf_load(q.y, b_c, s_own, T()),
               sz = buf_load(q.z, b_c, s_own, T());
             // in-row neighbour on the side given by the parity
-            const Vec3<T> c = oc[k + 1];
+            const Vec3<T> c = pc[k + 1];
             const bool from_mem = p ? right_mem : left_mem;
             Vec3<T> nb;
             if (p == 0)
@@ -494,9 +491,9 @@ k_sc_strip(PassLaunch P, int colour)
             if (from_mem) nb = ec[k];
             // fixed order: -z, -y, -x, +x, +y, +z
             const Vec3<T> lo = p ? c : nb, hi = p ? nb : c;
-            T hx = om[k].x + oc[k].x + lo.x + hi.x + oc[k + 2].x + op[k + 1].x;
-            T hy = om[k].y + oc[k].y + lo.y + hi.y + oc[k + 2].y + op[k + 1].y;
-            T hz = om[k].z + oc[k].z + lo.z + hi.z + oc[k + 2].z + op[k + 1].z;
+            T hx = pm[k + 1].x + pc[k].x + lo.x + hi.x + pc[k + 2].x + pn[k + 1].x;
+            T hy = pm[k + 1].y + pc[k].y + lo.y + hi.y + pc[k + 2].y + pn[k + 1].y;
+            T hz = pm[k + 1].z + pc[k].z + lo.z + hi.z + pc[k + 2].z + pn[k + 1].z;
             hx *= J;
             hy *= J;
             hz *= J;
@@ -530,8 +527,196 @@ k_sc_strip(PassLaunch P, int colour)
                 n_acc += a ? 1u : 0u;
             }
         }
+    };
+    Vec3<T> ra[RY + 2], rb[RY + 2], rc[RY + 2], ea[RY], eb[RY], ee[RY];
+    load_rows(z0 > 0 ? z0 - 1 : (pz ? Lz - 1 : -1), ra, 0, RY + 2);
+    load_rows(z0, rb, 0, RY + 2);
+    load_edges(z0, eb);
+    int z = z0;
+    for (; z + 2 < z1; z += 3) {
+        step(ra, rb, rc, eb, ee, z);
+        step(rb, rc, ra, ee, ea, z + 1);
+        step(rc, ra, rb, ea, eb, z + 2);
+    }
+    if (z < z1) step(ra, rb, rc, eb, ee, z);
+    if (z + 1 < z1) step(rb, rc, ra, ee, ea, z + 1);
+    if (MEASURE) {
+        acc[Q_NACC] = (double)n_acc;
+        block_store_partials(acc, P.partials_dev + ((size_t)colour * P.n_items + item) * NQ);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Band kernel (simple cubic): the row-strip scheme without idle lanes.  Rows
+// are grouped into bands of RY rows; the positions (band, xh) are numbered
+// band-major and dealt to the lanes contiguously, so a wave may run from the
+// end of one band into the next and every lane has work whatever the row
+// length.  With RY even, the parity of a site depends only on (k, z), so it
+// stays uniform over the wave; each lane keeps per-row byte offsets of its
+// own band in registers, and every access is one buffer instruction with the
+// plane offset in a scalar register.
+// ---------------------------------------------------------------------------
+template <typename T, bool MEASURE, int MODE, int RY>
+__device__ __forceinline__ void sc_band_body(const PassLaunch &P, int colour, uint32_t item,
+                                             uint32_t t)
+{
+    static_assert(RY % 2 == 0, "band rows must be even");
+    // every descriptor field is read into registers before the first store, so
+    // the loads stay scalar (memory that the kernel may write cannot be)
+    const WorkItem w = P.work_dev[item];
+    const RepDev &R = P.reps_dev[w.rep];
+    const int Ly = R.Ly, Lz = R.Lz, Lxh = R.Lxh, Lx = R.Lx;
+    void *const base_x = R.sx, *const base_y = R.sy, *const base_z = R.sz;
+    const uint32_t rid = R.rid;
+    const int lane = threadIdx.x & 63;
+    const int n_bands = (Ly + RY - 1) / RY;
+    const int F = n_bands * Lxh; // positions (band, xh)
+    const int fraw = w.x0 + (int)threadIdx.x;
+    const bool fin = fraw < F && (int)threadIdx.x < P.tile.tx;
+    const int f = fin ? fraw : F - 1;
+    const int band = f / Lxh;
+    const int xh = f - band * Lxh;
+    const int yb = band * RY; // first row of the band
+    const uint32_t plane = R.plane;
+    const uint32_t own = colour ? plane : 0u, oth = colour ? 0u : plane;
+    const T J = (T)R.J, K = (T)R.K, ex = (T)R.e[0], ey = (T)R.e[1], ez = (T)R.e[2];
+    const T beta = (T)R.beta;
+    const bool greedy = R.greedy != 0;
+    const bool px = R.pmask & 1u, py = R.pmask & 2u, pz = R.pmask & 4u;
+    const int xl = xh > 0 ? xh - 1 : (px ? Lxh - 1 : -1);
+    const int xr = xh < Lxh - 1 ? xh + 1 : (px ? 0 : -1);
+    const bool left_mem = lane == 0 || xh == 0;           // x-1 not held by lane-1
+    const bool right_mem = lane == 63 || xh >= Lxh - 1;   // x+1 not held by lane+1
+    const uint32_t row_bytes = (uint32_t)Lxh * (uint32_t)sizeof(T);
+    const uint32_t b_c = (uint32_t)xh * (uint32_t)sizeof(T);
+    const uint32_t b_l = (uint32_t)(xl < 0 ? 0 : xl) * (uint32_t)sizeof(T);
+    const uint32_t b_r = (uint32_t)(xr < 0 ? 0 : xr) * (uint32_t)sizeof(T);
+    const PlaneRs<T> q = {plane_rsrc<T>(base_x, 0, R.n_box), plane_rsrc<T>(base_y, 0, R.n_box),
+                          plane_rsrc<T>(base_z, 0, R.n_box)};
+    const uint32_t own_b = own * (uint32_t)sizeof(T), oth_b = oth * (uint32_t)sizeof(T);
+    const uint32_t zplane_b = (uint32_t)Ly * row_bytes;
+    auto load3 = [&](uint32_t voff, uint32_t soff) -> Vec3<T> {
+        return {buf_load(q.x, voff, soff, T()), buf_load(q.y, voff, soff, T()),
+                buf_load(q.z, voff, soff, T())};
+    };
+
+    // this lane's rows yb-1 .. yb+RY (wrapped on periodic faces) as byte
+    // offsets within a z plane, and which of them exist (open faces)
+    uint32_t roff[RY + 2];
+    uint32_t row_ok = 0;
 #pragma unroll
-        for (int k = 0; k < RY; ++k) om[k] = oc[k + 1];
+    for (int k = -1; k <= RY; ++k) {
+        int y = yb + k;
+        bool ok = true;
+        if (y < 0 || y >= Ly) {
+            if (py) {
+                while (y < 0) y += Ly;
+                while (y >= Ly) y -= Ly;
+            } else {
+                ok = false;
+                y = y < 0 ? 0 : Ly - 1;
+            }
+        }
+        roff[k + 1] = (uint32_t)y * row_bytes + b_c;
+        row_ok |= (ok ? 1u : 0u) << (k + 1);
+    }
+    auto load_rows = [&](int z, Vec3<T> *dst) {
+        if (z < 0) {
+#pragma unroll
+            for (int k = 0; k < RY + 2; ++k) dst[k] = {T(0), T(0), T(0)};
+            return;
+        }
+        const uint32_t soff = oth_b + (uint32_t)z * zplane_b;
+#pragma unroll
+        for (int k = 0; k < RY + 2; ++k) {
+            dst[k] = load3(roff[k], soff);
+            if (!py && !((row_ok >> k) & 1u)) dst[k] = {T(0), T(0), T(0)};
+        }
+    };
+    // In-row neighbours that the lane shift cannot supply (wave edges, band
+    // seams, the periodic wrap, open faces) are loaded one plane ahead by the
+    // lanes that need them, so the loads never stall the plane being updated.
+    auto load_edges = [&](int z, Vec3<T> *dst) {
+        const uint32_t soff = oth_b + (uint32_t)z * zplane_b;
+#pragma unroll
+        for (int k = 0; k < RY; ++k) {
+            const int p = (colour + k + z) & 1;
+            const bool need = p ? right_mem : left_mem;
+            const int col = p ? xr : xl;
+            if (need && col >= 0)
+                dst[k] = load3(roff[k + 1] - b_c + (p ? b_r : b_l), soff);
+            else
+                dst[k] = {T(0), T(0), T(0)};
+        }
+    };
+
+    const int z0 = w.z0, z1 = min(w.z0 + P.tile.zc, Lz);
+    Vec3<T> om[RY + 2], oc[RY + 2], op[RY + 2], ec[RY], en[RY];
+    load_rows(z0 > 0 ? z0 - 1 : (pz ? Lz - 1 : -1), om);
+    load_rows(z0, oc);
+    load_edges(z0, ec);
+    double acc[Q_N] = {0, 0, 0, 0, 0, 0};
+    uint32_t n_acc = 0;
+    for (int z = z0; z < z1; ++z) {
+        const int zn = z < Lz - 1 ? z + 1 : (pz ? 0 : -1);
+        load_rows(zn, op);
+        if (z + 1 < z1) load_edges(zn, en);
+        const uint32_t s_own = own_b + (uint32_t)z * zplane_b;
+#pragma unroll
+        for (int k = 0; k < RY; ++k) {
+            const int y = yb + k;
+            const bool live = fin && y < Ly;
+            const int p = (colour + k + z) & 1; // uniform over the wave (RY even)
+            T sx = buf_load(q.x, roff[k + 1], s_own, T()), sy = buf_load(q.y, roff[k + 1], s_own, T()),
+              sz = buf_load(q.z, roff[k + 1], s_own, T());
+            // in-row neighbour on the side given by the parity
+            const Vec3<T> c = oc[k + 1];
+            const bool from_mem = p ? right_mem : left_mem;
+            Vec3<T> nb;
+            if (p == 0)
+                nb = {from_lower_lane(c.x), from_lower_lane(c.y), from_lower_lane(c.z)};
+            else
+                nb = {from_upper_lane(c.x), from_upper_lane(c.y), from_upper_lane(c.z)};
+            if (from_mem) nb = ec[k];
+            // fixed order: -z, -y, -x, +x, +y, +z
+            const Vec3<T> lo = p ? c : nb, hi = p ? nb : c;
+            T hx = om[k + 1].x + oc[k].x + lo.x + hi.x + oc[k + 2].x + op[k + 1].x;
+            T hy = om[k + 1].y + oc[k].y + lo.y + hi.y + oc[k + 2].y + op[k + 1].y;
+            T hz = om[k + 1].z + oc[k].z + lo.z + hi.z + oc[k + 2].z + op[k + 1].z;
+            hx *= J;
+            hy *= J;
+            hz *= J;
+            bool a = false;
+            if (MODE != 1) {
+                const uint32_t s = (uint32_t)(z * Ly + y) * (uint32_t)Lx + 2u * xh + p;
+                T dH;
+                a = metropolis<T>(sx, sy, sz, hx, hy, hz, s, rid, t, P.seed_lo, P.seed_hi, K,
+                                  ex, ey, ez, beta, greedy, dH);
+                if (live) {
+                    const uint32_t i = own + (uint32_t)(z * Ly + y) * Lxh + xh;
+                    if (MODE == 2) {
+                        ((T *)P.dbg_dh)[i] = dH;
+                        P.dbg_acc[i] = a ? 1 : 0;
+                    }
+                    if (a) {
+                        buf_store(sx, q.x, roff[k + 1], s_own);
+                        buf_store(sy, q.y, roff[k + 1], s_own);
+                        buf_store(sz, q.z, roff[k + 1], s_own);
+                    }
+                }
+            }
+            if (MEASURE && live) {
+                acc[Q_MX] += (double)sx;
+                acc[Q_MY] += (double)sy;
+                acc[Q_MZ] += (double)sz;
+                const double pe = (double)(sx * ex + sy * ey + sz * ez);
+                acc[Q_PE2] += pe * pe;
+                if (colour == 1) acc[Q_SH] += (double)(sx * hx + sy * hy + sz * hz);
+                n_acc += a ? 1u : 0u;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < RY + 2; ++k) om[k] = oc[k];
 #pragma unroll
         for (int k = 0; k < RY + 2; ++k) oc[k] = op[k];
 #pragma unroll
@@ -552,19 +737,15 @@ k_sc_strip(PassLaunch P, int colour)
 // branch-free inside the box.
 // ---------------------------------------------------------------------------
 template <int KIND, int B, typename T, bool MEASURE, int MODE>
-__global__ void __launch_bounds__(256)
-k_basis_pass(PassLaunch P)
+__device__ __forceinline__ void basis_body(const PassLaunch &P, uint32_t item, uint32_t t)
 {
     constexpr int NB = basis_count(KIND);
-    uint32_t item;
-    if (!logical_item(P, item)) return;
     const WorkItem w = P.work_dev[item];
     const RepDev &R = P.reps_dev[w.rep];
     const int Lx = R.Lx, Ly = R.Ly, Lz = R.Lz;
     const int lx = threadIdx.x % P.tile.tx, ly = threadIdx.x / P.tile.tx;
     const int x = w.x0 + lx, y = w.y0 + ly;
     const bool active = x < Lx && y < Ly && ly < P.tile.ty;
-    const uint32_t t = *P.tctr_dev + P.t_off;
     const uint32_t plane = R.plane;
     const gptr<T> gx = as_global<T>(R.sx), gy = as_global<T>(R.sy), gz = as_global<T>(R.sz);
     const T J = (T)R.J, K = (T)R.K, ex = (T)R.e[0], ey = (T)R.e[1], ez = (T)R.e[2];
@@ -649,6 +830,159 @@ k_basis_pass(PassLaunch P)
     }
     if (MEASURE)
         block_store_partials(acc, P.partials_dev + ((size_t)B * P.n_items + item) * NQ);
+}
+
+// ---------------------------------------------------------------------------
+// Pass kernels: one workgroup per work item, sweep counter from the device.
+// ---------------------------------------------------------------------------
+template <typename T, bool MEASURE, int MODE>
+__global__ void __launch_bounds__(256) k_sc_tile(PassLaunch P, int colour)
+{
+    uint32_t item;
+    if (!logical_item(P, item)) return;
+    sc_tile_body<T, MEASURE, MODE>(P, colour, item, *P.tctr_dev + P.t_off);
+}
+
+template <typename T, bool MEASURE, int MODE, int RY>
+__global__ void __launch_bounds__(256) k_sc_strip(PassLaunch P, int colour)
+{
+    uint32_t item;
+    if (!logical_item(P, item)) return;
+    sc_strip_body<T, MEASURE, MODE, RY>(P, colour, item, *P.tctr_dev + P.t_off);
+}
+
+template <typename T, bool MEASURE, int MODE, int RY>
+__global__ void __launch_bounds__(256) k_sc_band(PassLaunch P, int colour)
+{
+    uint32_t item;
+    if (!logical_item(P, item)) return;
+    sc_band_body<T, MEASURE, MODE, RY>(P, colour, item, *P.tctr_dev + P.t_off);
+}
+
+template <int KIND, int B, typename T, bool MEASURE, int MODE>
+__global__ void __launch_bounds__(256) k_basis_pass(PassLaunch P)
+{
+    uint32_t item;
+    if (!logical_item(P, item)) return;
+    basis_body<KIND, B, T, MEASURE, MODE>(P, item, *P.tctr_dev + P.t_off);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent batched sweeps (see PersistLaunch).  Memory ordering: a unit's
+// stores are released (agent scope) before its completion is counted; the
+// workgroup that completes a replica's pass acquires, reduces the pass's
+// partial sums if the sweep is measured, then releases the next phase; a
+// waiting unit acquires before reading spins.
+// ---------------------------------------------------------------------------
+template <typename T, bool MEASURE, int KIND, int KERNEL, int RY>
+__device__ __forceinline__ void unit_body(const PassLaunch &P, int c, uint32_t item, uint32_t t)
+{
+    if constexpr (KIND == SC) {
+        if constexpr (KERNEL == KERNEL_STRIP) sc_strip_body<T, MEASURE, 0, RY>(P, c, item, t);
+        else if constexpr (KERNEL == KERNEL_BAND) sc_band_body<T, MEASURE, 0, RY>(P, c, item, t);
+        else sc_tile_body<T, MEASURE, 0>(P, c, item, t);
+    } else {
+        switch (c) {
+        case 0: basis_body<KIND, 0, T, MEASURE, 0>(P, item, t); break;
+        case 1: basis_body<KIND, 1, T, MEASURE, 0>(P, item, t); break;
+        case 2:
+            if constexpr (KIND == FCC) basis_body<KIND, 2, T, MEASURE, 0>(P, item, t);
+            break;
+        default:
+            if constexpr (KIND == FCC) basis_body<KIND, 3, T, MEASURE, 0>(P, item, t);
+            break;
+        }
+    }
+}
+
+template <typename T, bool MEASURE, int KIND, int KERNEL, int RY>
+__global__ void __launch_bounds__(256) k_persistent(PassLaunch P, PersistLaunch A)
+{
+    __shared__ uint32_t s_unit, s_flag;
+    __shared__ double s_rec[NQ];
+    uint32_t *const hdr = A.state, *const done = A.state + 4, *const ready = A.state + 4 + A.n_reps;
+    const uint32_t n_items = P.n_items;
+    const uint32_t per_sweep = A.n_colours * n_items;
+    const uint32_t total = A.n_sweeps * per_sweep;
+    const uint32_t t0 = *P.tctr_dev + P.t_off;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            uint32_t u = __hip_atomic_fetch_add(&hdr[0], 1u, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+            if (__hip_atomic_load(&hdr[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) u = total;
+            s_unit = u;
+        }
+        __syncthreads();
+        const uint32_t u = s_unit;
+        if (u >= total) break;
+        const uint32_t sw = u / per_sweep, rem = u - sw * per_sweep;
+        const uint32_t c = rem / n_items, item = rem - c * n_items;
+        const uint32_t r = P.work_dev[item].rep;
+        const uint32_t phase = sw * A.n_colours + c;
+        if (threadIdx.x == 0) {
+            uint32_t ok = 1;
+            for (uint32_t spins = 0;
+                 __hip_atomic_load(&ready[r], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < phase;
+                 ++spins) {
+                if (spins >= A.spin_limit ||
+                    __hip_atomic_load(&hdr[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+            if (!ok) {
+                __hip_atomic_store(&hdr[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&hdr[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            s_flag = ok;
+        }
+        __syncthreads();
+        if (!s_flag) break;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        unit_body<T, MEASURE, KIND, KERNEL, RY>(P, (int)c, item, t0 + sw);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const RepDev &R = P.reps_dev[r];
+            const uint32_t n_r = R.item_end - R.item_begin;
+            const uint32_t old = __hip_atomic_fetch_add(&done[r], 1u, __ATOMIC_ACQ_REL,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
+            s_flag = (old + 1u == (phase + 1u) * n_r);
+        }
+        __syncthreads();
+        if (s_flag) { // this unit completed replica r's phase
+            if (MEASURE && c == A.n_colours - 1) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                const RepDev &R = P.reps_dev[r];
+                double a[Q_N] = {0, 0, 0, 0, 0, 0};
+                for (uint32_t cc = 0; cc < A.n_colours; ++cc)
+                    for (uint32_t it = R.item_begin + threadIdx.x; it < R.item_end; it += blockDim.x) {
+                        const double *p = P.partials_dev + ((size_t)cc * n_items + it) * NQ;
+#pragma unroll
+                        for (int q = 0; q < Q_N; ++q) a[q] += p[q];
+                    }
+                block_store_partials(a, s_rec);
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    double *rec = A.records + ((size_t)((A.slot0 + sw) % A.ring) * A.n_reps + r) * NR;
+                    rec[R_MX] = s_rec[Q_MX];
+                    rec[R_MY] = s_rec[Q_MY];
+                    rec[R_MZ] = s_rec[Q_MZ];
+                    rec[R_EEX] = -s_rec[Q_SH];
+                    rec[R_EAN] = -R.K * s_rec[Q_PE2];
+                    rec[R_NACC] = s_rec[Q_NACC];
+                    rec[R_SWEEP] = (double)(t0 + sw) + 1.0;
+                    rec[7] = 0.0;
+                }
+            }
+            if (threadIdx.x == 0) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                __hip_atomic_store(&ready[r], phase + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        __syncthreads();
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -820,6 +1154,15 @@ static dim3 pass_grid(const PassLaunch &p) { return dim3(((p.n_blocks + 7u) >> 3
 template <typename T, bool MEASURE, int MODE>
 static hipError_t sc_launch(int colour, const PassLaunch &p, hipStream_t st)
 {
+    if (p.tile.kernel == KERNEL_BAND) {
+        const dim3 g = pass_grid(p), b(p.tile.tx);
+        switch (p.tile.ty) {
+        case 2: hipLaunchKernelGGL((k_sc_band<T, MEASURE, MODE, 2>), g, b, 0, st, p, colour); break;
+        case 4: hipLaunchKernelGGL((k_sc_band<T, MEASURE, MODE, 4>), g, b, 0, st, p, colour); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     if (p.tile.kernel == KERNEL_STRIP) {
         const dim3 g = pass_grid(p), b(p.tile.tx);
         switch (p.tile.ty) {
@@ -942,6 +1285,47 @@ hipError_t launch_zero_u32(uint32_t *p, uint32_t n, hipStream_t st)
     hipLaunchKernelGGL(k_zero_u32, dim3((n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024), dim3(256),
                        0, st, p, n);
     return hipGetLastError();
+}
+
+template <typename T, bool MEASURE>
+static hipError_t persist_dispatch(int kind, const PassLaunch &p, const PersistLaunch &a,
+                                   hipStream_t st)
+{
+    const uint64_t total = (uint64_t)a.n_sweeps * a.n_colours * p.n_items;
+    const unsigned grid = (unsigned)(total < 2048 ? total : 2048);
+    if (grid == 0) return hipSuccess;
+    const int threads = p.tile.kernel == KERNEL_TILE ? ((p.tile.tx * p.tile.ty + 63) / 64) * 64
+                                                     : p.tile.tx;
+    const dim3 g(grid), b(threads);
+    if (kind == BCC) {
+        hipLaunchKernelGGL((k_persistent<T, MEASURE, BCC, KERNEL_TILE, 1>), g, b, 0, st, p, a);
+    } else if (kind == FCC) {
+        hipLaunchKernelGGL((k_persistent<T, MEASURE, FCC, KERNEL_TILE, 1>), g, b, 0, st, p, a);
+    } else if (p.tile.kernel == KERNEL_TILE) {
+        hipLaunchKernelGGL((k_persistent<T, MEASURE, SC, KERNEL_TILE, 1>), g, b, 0, st, p, a);
+    } else if (p.tile.kernel == KERNEL_STRIP && p.tile.ty == 2) {
+        hipLaunchKernelGGL((k_persistent<T, MEASURE, SC, KERNEL_STRIP, 2>), g, b, 0, st, p, a);
+    } else if (p.tile.kernel == KERNEL_STRIP && p.tile.ty == 4) {
+        hipLaunchKernelGGL((k_persistent<T, MEASURE, SC, KERNEL_STRIP, 4>), g, b, 0, st, p, a);
+    } else if (p.tile.kernel == KERNEL_BAND && p.tile.ty == 2) {
+        hipLaunchKernelGGL((k_persistent<T, MEASURE, SC, KERNEL_BAND, 2>), g, b, 0, st, p, a);
+    } else if (p.tile.kernel == KERNEL_BAND && p.tile.ty == 4) {
+        hipLaunchKernelGGL((k_persistent<T, MEASURE, SC, KERNEL_BAND, 4>), g, b, 0, st, p, a);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_persistent(int kind, bool f64, bool measure, const PassLaunch &p,
+                             const PersistLaunch &a, hipStream_t st)
+{
+    if ((uint64_t)a.n_sweeps * a.n_colours * p.n_items >= 0xFFFFFFFFull) return hipErrorInvalidValue;
+    if (f64)
+        return measure ? persist_dispatch<double, true>(kind, p, a, st)
+                       : persist_dispatch<double, false>(kind, p, a, st);
+    return measure ? persist_dispatch<float, true>(kind, p, a, st)
+                   : persist_dispatch<float, false>(kind, p, a, st);
 }
 
 hipError_t launch_advance(uint32_t *tctr_dev, uint32_t n, hipStream_t st)

@@ -44,6 +44,25 @@ hipError_t launch_finalize(const RepDev *reps_dev, int n_reps, int n_colours,
                            double *stage_dev, uint32_t *count_dev, hipStream_t st);
 hipError_t launch_zero_u32(uint32_t *p, uint32_t n, hipStream_t st);
 
+// One persistent launch that runs n_sweeps sweeps of every replica.  Work units
+// (sweep, colour, item) are handed out in that order by an atomic counter; a
+// unit waits until its replica has finished the previous colour pass (or
+// sweep), so replicas advance independently and no grid-wide barrier is
+// needed.  State layout (uint32, zeroed before every launch):
+//   [0] next unit, [1] abort, [2] watchdog tripped, [3] unused,
+//   [4 .. 4+n_reps) items done per replica, [4+n_reps .. 4+2 n_reps) phases released.
+struct PersistLaunch {
+    uint32_t *state;
+    uint32_t n_sweeps, n_colours, n_reps;
+    uint32_t spin_limit;  // bounded wait: spins of ~0.1 us before the watchdog trips
+    double *records;      // ring [ring][n_reps][NR]
+    uint32_t ring, slot0; // record slot of sweep s = (slot0 + s) % ring
+};
+inline uint32_t persist_state_words(int n_reps) { return 4u + 2u * (uint32_t)n_reps; }
+
+hipError_t launch_persistent(int kind, bool f64, bool measure, const PassLaunch &p,
+                             const PersistLaunch &a, hipStream_t st);
+
 hipError_t launch_advance(uint32_t *tctr_dev, uint32_t n, hipStream_t st);
 hipError_t launch_set_counter(uint32_t *tctr_dev, uint32_t v, hipStream_t st);
 hipError_t launch_fill_zero(double *p, uint64_t n, hipStream_t st);

@@ -26,6 +26,7 @@ SC, BCC, FCC = 0, 1, 2
 F32, F64 = 0, 1
 INIT_RANDOM, INIT_ALIGNED, INIT_USER = 0, 1, 2
 MEASURE = 1
+PERSISTENT = 2
 STATUS = {0: "MC_OK", -1: "MC_E_ARG", -2: "MC_E_UNSUPPORTED", -3: "MC_E_BUFFER",
           -4: "MC_E_DEVICE", -5: "MC_E_STATE"}
 KINDS = {"sc": SC, "bcc": BCC, "fcc": FCC}
@@ -60,7 +61,7 @@ class Obs(ctypes.Structure):
 class Schedule(ctypes.Structure):
     _fields_ = [("n_T", ctypes.c_int32), ("T", ctypes.POINTER(ctypes.c_double)),
                 ("n_equil", ctypes.c_uint32), ("n_meas", ctypes.c_uint32),
-                ("measure_every", ctypes.c_uint32)]
+                ("measure_every", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
 
 
 class Stats(ctypes.Structure):
@@ -103,6 +104,8 @@ _SIGNATURES = {
     "mc_num_colours": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
     "mc_series_stats": (ctypes.c_int, [ctypes.POINTER(Obs), ctypes.c_uint64, ctypes.c_uint64,
                                        ctypes.c_double, ctypes.POINTER(Stats)]),
+    "mc_set_watchdog": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32]),
+    "mc_synchronize": (ctypes.c_int, [ctypes.c_void_p]),
     "mc_destroy": (None, [ctypes.c_void_p]),
     "mc_last_error": (ctypes.c_char_p, []),
     "mc_version": (ctypes.c_char_p, []),
@@ -267,9 +270,18 @@ class Simulation:
         return self._h
 
     # -- the four entry points --------------------------------------------
-    def sweep(self, n: int = 1, measure: bool = False):
-        """``mc_sweep``: enqueue n sweeps (asynchronous)."""
-        _check("mc_sweep", LIB.mc_sweep(self.handle, int(n), MEASURE if measure else 0))
+    def sweep(self, n: int = 1, measure: bool = False, persistent: bool = False):
+        """``mc_sweep``: enqueue n sweeps (asynchronous); ``persistent`` runs them
+        as one persistent launch."""
+        flags = (MEASURE if measure else 0) | (PERSISTENT if persistent else 0)
+        _check("mc_sweep", LIB.mc_sweep(self.handle, int(n), flags))
+
+    def synchronize_checked(self):
+        """``mc_synchronize``: wait and report deferred errors."""
+        _check("mc_synchronize", LIB.mc_synchronize(self.handle))
+
+    def set_watchdog(self, spins: int):
+        _check("mc_set_watchdog", LIB.mc_set_watchdog(self.handle, int(spins)))
 
     def sweep_timed(self, n: int, measure: bool = False):
         """``mc_sweep_timed``: (mean ms per colour-pass launch, total ms)."""
@@ -289,7 +301,8 @@ class Simulation:
         _check("mc_measure_state", LIB.mc_measure_state(self.handle, out, self.n_reps))
         return [obs_to_dict(o) for o in out]
 
-    def run_schedule(self, T, n_equil: int, n_meas: int, measure_every: int = 1) -> np.ndarray:
+    def run_schedule(self, T, n_equil: int, n_meas: int, measure_every: int = 1,
+                     persistent: bool = False) -> np.ndarray:
         """``mc_run_schedule``: T is (n_T,) or (n_T, n_reps).  Returns an array
         (n_T, n_rec, n_reps, 10) of records (see ``obs_array_to_numpy``)."""
         T = np.asarray(T, dtype=np.float64)
@@ -304,6 +317,7 @@ class Simulation:
         s.n_T = n_T
         s.T = T.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         s.n_equil, s.n_meas, s.measure_every = int(n_equil), int(n_meas), int(measure_every)
+        s.flags = PERSISTENT if persistent else 0
         nw = ctypes.c_uint64()
         _check("mc_run_schedule", LIB.mc_run_schedule(self.handle, ctypes.byref(s), series, cap,
                                                       ctypes.byref(nw)))

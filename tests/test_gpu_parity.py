@@ -198,7 +198,8 @@ def test_fp32_single_pass_edge_temperatures(M):
 
 
 TILES = [None, (0, 8, 8, 3), (0, 64, 4, 34), (0, 16, 2, 1), (1, 64, 1, 5), (1, 64, 4, 34),
-         (1, 128, 8, 3), (1, 256, 2, 7), (1, 192, 4, 1)]
+         (1, 128, 8, 3), (1, 256, 2, 7), (1, 192, 4, 1), (2, 256, 2, 7), (2, 64, 4, 3),
+         (2, 128, 2, 1), (2, 192, 4, 34)]
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
@@ -234,10 +235,17 @@ def test_strip_kernel_rejects_other_lattices(M):
     sim = M.Simulation([M.Replica(kind="fcc", L=(6, 6, 6))])
     with pytest.raises(M.MCError):
         sim.set_tile(64, 4, 2, kernel=1)
+    with pytest.raises(M.MCError):
+        sim.set_tile(64, 2, 2, kernel=2)
     sim = M.Simulation([M.Replica(kind="sc", L=(16, 16, 16))])
     for bad in ((96, 4, 2), (64, 3, 2), (64, 4, 0), (512, 1, 1)):
         with pytest.raises(M.MCError):
             sim.set_tile(*bad, kernel=1)
+    for bad in ((256, 1, 2), (256, 3, 2), (256, 8, 2), (100, 2, 2)):
+        with pytest.raises(M.MCError):
+            sim.set_tile(*bad, kernel=2)
+    with pytest.raises(M.MCError):
+        sim.set_tile(8, 8, 1, kernel=3)
 
 
 def test_checkpoint_resume_is_bitwise(M):
@@ -375,7 +383,7 @@ def test_full_size_sc464_sampled(M):
     w = W.C5_SC464_ROOFLINE
     rep = M.Replica(**W.replica_fields(w))
     sim = M.Simulation([rep], precision="f32", seed=w["seed"])
-    assert sim.get_tile()[0] == 1  # the row-strip kernel the benchmark times
+    assert sim.get_tile()[0] == 2  # the band kernel the benchmark times
     sim.sweep(99)
     sim.sweep(1, measure=True)
     fused = sim.observables()[0]
@@ -451,3 +459,73 @@ def test_full_size_fcc_particle_sampled(M):
             if checked >= 1500:
                 break
         assert checked >= 1500
+
+
+# --------------------------------------------------------------------------
+# Persistent batched launches (many replicas, uneven sizes, one launch)
+# --------------------------------------------------------------------------
+def _batch(M, kind="sc"):
+    if kind == "sc":
+        Ls = [(16, 16, 16), (24, 24, 24), (32, 32, 32), (48, 48, 48), (20, 18, 22)]
+    else:
+        Ls = [(6, 6, 6), (9, 7, 8), (10, 10, 10)]
+    return [M.Replica(kind=kind, L=L, J=1.0, K=0.1, e=(0.0, 0.0, 1.0), T=0.8 + 0.3 * r,
+                      replica_id=r) for r, L in enumerate(Ls)]
+
+
+@pytest.mark.parametrize("kind,prec", [("sc", "f32"), ("sc", "f64"), ("fcc", "f32")])
+def test_persistent_matches_eager(M, kind, prec):
+    reps = _batch(M, kind)
+    a = M.Simulation(reps, precision=prec, seed=12)
+    b = M.Simulation(reps, precision=prec, seed=12)
+    for rnd in range(3):
+        a.sweep(4, measure=True, persistent=True)
+        b.sweep(4, measure=True)
+        oa, ob = a.observables(), b.observables()
+        for x, y in zip(oa, ob):
+            assert x["sweep"] == y["sweep"] and x["n_accepted"] == y["n_accepted"]
+            assert abs(x["E"] - y["E"]) <= 1e-12 * abs(y["E"])
+            assert np.max(np.abs(x["M"] - y["M"])) <= 1e-14
+    for r in range(len(reps)):
+        for x, y in zip(natural(a, r), natural(b, r)):
+            assert np.array_equal(x, y)
+
+
+def test_persistent_schedule_and_oracle(M):
+    """A persistent, graph-replayed schedule over uneven replicas equals the
+    oracle's FP64 chain replica by replica."""
+    reps = _batch(M)[:3]
+    sim = M.Simulation(reps, precision="f64", seed=31)
+    T = np.array([[0.9, 1.2, 1.5], [1.1, 1.3, 2.0]])
+    rec = sim.run_schedule(T, n_equil=5, n_meas=9, persistent=True)
+    for r, rep in enumerate(reps):
+        lat = oracle_lattice(rep)
+        s = O.init(lat, oracle_params(rep, 31))
+        t = 0
+        for step in range(2):
+            p = oracle_params(M.Replica(**{**rep.__dict__, "T": T[step, r]}), 31)
+            O.run(lat, p, t, 5, s, record=False)
+            ref = O.run(lat, p, t + 5, 9, s)
+            t += 14
+            got = rec[step, :, r, :]
+            assert np.array_equal(got[:, 1], ref[:, 5])
+            assert np.max(np.abs(got[:, 2:5] - ref[:, 0:3] / lat.n_occ)) <= 1e-12
+        for x, y in zip(natural(sim, r), s):
+            assert np.max(np.abs(x - y)) <= 1e-12
+
+
+def test_persistent_watchdog_exits_cleanly(M):
+    """A zero wait budget makes the persistent launch give up at its first
+    unmet dependency: every workgroup exits, the next synchronising call
+    reports MC_E_DEVICE, and the handle keeps working afterwards."""
+    reps = _batch(M)[:2]
+    sim = M.Simulation(reps, precision="f32", seed=5)
+    sim.set_watchdog(0)
+    sim.sweep(40, persistent=True)
+    with pytest.raises(M.MCError) as ei:
+        sim.synchronize_checked()
+    assert ei.value.status == -4 and "persistent" in str(ei.value)
+    sim.set_watchdog(1 << 24)
+    sim.sweep(3, measure=True, persistent=True)
+    o = sim.observables()
+    assert all(x["n_sites"] > 0 for x in o)
