@@ -56,9 +56,13 @@ def time_precision(M, W, prec, steps, warmup):
 
     w = W.C5_SC464_ROOFLINE
     rep = M.Replica(**W.replica_fields(w))
-    sim = M.Simulation([rep], precision=prec, seed=w["seed"])
+    scratch = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
+    sim = M.Simulation([rep], precision=prec, seed=w["seed"], scratch=scratch)
     n = sim.n_occ[0]
-    log(f"[bench] {prec}: {n} spins, tile {sim.get_tile()}, warmup {warmup}")
+    # kernel / tile shape chosen by the library's autotuner (its trial sweeps
+    # are ordinary sweeps of the chain and count as warm-up)
+    tile = sim.autotune(trial_sweeps=6, measure=True)
+    log(f"[bench] {prec}: {n} spins, autotuned tile {sim.get_tile()}, warmup {warmup}")
     if warmup:
         sim.sweep(warmup, measure=True)
     sim.synchronize()
@@ -80,6 +84,8 @@ def time_precision(M, W, prec, steps, warmup):
         "absM": obs["absM"],
         "e_per_spin": obs["E"] / n,
         "n_spins": n,
+        "tile": {"kernel": ["tile", "strip", "band"][tile[0]], "tx": tile[1], "ty": tile[2],
+                 "zc": tile[3]},
     }
     sim.close()
     del sim
@@ -182,7 +188,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": r32["achieved_GBps"], "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": r32["achieved_GBps"] / HBM_PEAK_GBPS,
                      "traffic": traffic,
-                     "kernel": "k_sc_pass<float, MEASURE> (one colour pass)",
+                     "kernel": "sc colour pass, FP32, measured (%s %dx%dx%d)" % (
+                         r32["tile"]["kernel"], r32["tile"]["tx"], r32["tile"]["ty"],
+                         r32["tile"]["zc"]),
                      "algorithmic_bytes_per_launch": BYTES_PER_UPDATE["f32"] * r32["n_spins"] / 2,
                      "pass_ms": r32["pass_ms"]},
         "cpu_baseline": cpu,

@@ -59,7 +59,8 @@ typedef enum { MC_INIT_RANDOM = 0, MC_INIT_ALIGNED = 1, MC_INIT_USER = 2 } mc_in
                          /* (sweep, colour, tile) are claimed in order by the resident */
                          /* workgroups, each replica advancing as soon as its previous */
                          /* pass is complete (no grid-wide barrier).  Results are      */
-                         /* bitwise identical to the default launches.                */
+                         /* bitwise identical to the default launches.  Strip tiles  */
+                         /* of 1 or 8 rows have no persistent kernel: MC_E_UNSUPPORTED.*/
 
 /* One replica: lattice geometry and model parameters (Eq. (1)).
  *  kind          sc / bcc / fcc conventional cubic cells.
@@ -234,6 +235,17 @@ mc_status mc_set_sweep(mc_sim *h, uint64_t t);
 mc_status mc_set_tile(mc_sim *h, int32_t kernel, int32_t tx, int32_t ty, int32_t zc);
 mc_status mc_get_tile(const mc_sim *h, int32_t *kernel, int32_t *tx, int32_t *ty, int32_t *zc,
                       uint64_t *n_items);
+
+/* Autotuner: time candidate kernels and tile shapes on the handle's own
+ * lattices (trial_sweeps sweeps each, with `flags` as for mc_sweep) and keep
+ * the fastest.  The trial sweeps are ordinary sweeps of the chain: they
+ * advance the state and the sweep counter (results stay bitwise independent
+ * of the shape).  cache_path (may be NULL) names a text file of earlier
+ * choices keyed by device, lattices, precision and flags; a matching entry
+ * skips the trials, a new choice is appended.  The chosen shape is returned
+ * through the out pointers (each may be NULL).  Synchronises. */
+mc_status mc_autotune(mc_sim *h, uint32_t trial_sweeps, uint32_t flags, const char *cache_path,
+                      int32_t *kernel, int32_t *tx, int32_t *ty, int32_t *zc);
 
 /* Number of colours (passes per sweep) of the handle's lattice kind. */
 mc_status mc_num_colours(const mc_sim *h, int32_t *n_colours);

@@ -105,6 +105,9 @@ _SIGNATURES = {
     "mc_series_stats": (ctypes.c_int, [ctypes.POINTER(Obs), ctypes.c_uint64, ctypes.c_uint64,
                                        ctypes.c_double, ctypes.POINTER(Stats)]),
     "mc_set_watchdog": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32]),
+    "mc_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_char_p,
+                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "mc_synchronize": (ctypes.c_int, [ctypes.c_void_p]),
     "mc_destroy": (None, [ctypes.c_void_p]),
     "mc_last_error": (ctypes.c_char_p, []),
@@ -346,6 +349,18 @@ class Simulation:
         """``mc_set_tile``: kernel 0 = tile (tx x ty threads), 1 = sc row strip
         (tx threads along the row, ty rows per thread); zc planes per tile."""
         _check("mc_set_tile", LIB.mc_set_tile(self.handle, int(kernel), int(tx), int(ty), int(zc)))
+
+    def autotune(self, trial_sweeps: int = 5, measure: bool = True, persistent: bool = False,
+                 cache_path: Optional[str] = None):
+        """``mc_autotune``: pick the fastest kernel / tile shape (the trial
+        sweeps advance the chain).  Returns (kernel, tx, ty, zc)."""
+        flags = (MEASURE if measure else 0) | (PERSISTENT if persistent else 0)
+        k, a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        path = cache_path.encode() if cache_path else None
+        _check("mc_autotune", LIB.mc_autotune(self.handle, int(trial_sweeps), flags, path,
+                                              ctypes.byref(k), ctypes.byref(a), ctypes.byref(b),
+                                              ctypes.byref(c)))
+        return int(k.value), int(a.value), int(b.value), int(c.value)
 
     def get_tile(self):
         """(kernel, tx, ty, zc, n_work_items)."""

@@ -231,6 +231,46 @@ def test_tile_shape_and_batching_are_bitwise(M, prec):
             assert abs(o["E"] - obs_b[r]["E"]) <= 1e-9 * abs(o["E"])
 
 
+MEASURE_CASES = [("sc", (64, 40, 30), None), ("sc", (64, 40, 30), (0, 16, 16, 1)),
+                 ("sc", (64, 40, 30), (1, 64, 1, 1)), ("sc", (64, 40, 30), (1, 64, 4, 2)),
+                 ("sc", (64, 40, 30), (2, 256, 4, 1)), ("sc", (150, 14, 12), (1, 128, 2, 3)),
+                 ("bcc", (9, 8, 7), None), ("fcc", (7, 6, 5), None)]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("case", range(len(MEASURE_CASES)))
+def test_measuring_does_not_change_the_chain(M, case, prec):
+    """Sweeps with the fused observable reduction leave bitwise the same spins
+    as sweeps without it, eager, graph-replayed and persistent alike."""
+    import torch
+
+    kind, L, tile = MEASURE_CASES[case]
+    rep = M.Replica(kind=kind, L=L, K=0.1, T=1.3, e=(0.0, 0.6, 0.8))
+    sims = []
+    # the persistent kernel has no instantiation for strips of 1 or 8 rows
+    modes = ("plain", "measured") if tile and tile[0] == 1 and tile[2] in (1, 8) else \
+        ("plain", "measured", "persistent")
+    for mode in modes:
+        s = M.Simulation([rep], precision=prec, seed=8,
+                         scratch=torch.empty(32 << 20, dtype=torch.uint8, device="cuda"))
+        if tile:
+            s.set_tile(tile[1], tile[2], tile[3], kernel=tile[0])
+        if mode == "plain":
+            s.sweep(3)
+            s.sweep(2)
+        else:
+            s.sweep(3, measure=True, persistent=mode == "persistent")
+            s.sweep(2, measure=True, persistent=mode == "persistent")
+        sims.append(natural(s))
+    for other in sims[1:]:
+        for a, b in zip(sims[0], other):
+            assert np.array_equal(a, b)
+    if len(modes) == 2:
+        with pytest.raises(M.MCError) as ei:
+            s.sweep(1, persistent=True)
+        assert ei.value.status == -2
+
+
 def test_strip_kernel_rejects_other_lattices(M):
     sim = M.Simulation([M.Replica(kind="fcc", L=(6, 6, 6))])
     with pytest.raises(M.MCError):
@@ -529,3 +569,27 @@ def test_persistent_watchdog_exits_cleanly(M):
     sim.sweep(3, measure=True, persistent=True)
     o = sim.observables()
     assert all(x["n_sites"] > 0 for x in o)
+
+
+def test_autotune_keeps_chain_and_caches(M, tmp_path):
+    """The autotuner's trials are ordinary sweeps: after it, the state equals a
+    plain run of the same number of sweeps; a second call hits the cache."""
+    rep = M.Replica(kind="sc", L=(64, 40, 30), K=0.1, T=1.3)
+    import torch
+
+    scratch = torch.empty(32 << 20, dtype=torch.uint8, device="cuda")
+    a = M.Simulation([rep], precision="f32", seed=8, scratch=scratch)
+    cache = str(tmp_path / "tune.txt")
+    tile = a.autotune(trial_sweeps=2, measure=True, cache_path=cache)
+    t = a.get_sweep()
+    assert t >= 3 and tile == a.get_tile()[:4]
+    b = M.Simulation([rep], precision="f32", seed=8)
+    b.sweep(t)
+    for x, y in zip(natural(a), natural(b)):
+        assert np.array_equal(x, y)
+    lines = open(cache).read().splitlines()
+    assert len(lines) == 1
+    c = M.Simulation([rep], precision="f32", seed=8, scratch=torch.empty(32 << 20, dtype=torch.uint8, device="cuda"))
+    assert c.autotune(trial_sweeps=2, measure=True, cache_path=cache) == tile
+    assert c.get_sweep() == 0  # cache hit: no trial sweeps
+    assert len(open(cache).read().splitlines()) == 1
