@@ -26,7 +26,9 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0           # MI355X HBM3E
 BYTES_PER_UPDATE = {"f32": 36, "f64": 72}  # two-pass colour-packed: read own + other, write own
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sc_pass_f32_L464_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2106_11286_amd", "csrc", "kernels.hip")
+# sources whose change invalidates the committed counter readings
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2106_11286_amd", "csrc", "kernels.hip"),
+               os.path.join(ROOT, "paper_2106_11286_amd", "build.py")]
 
 
 def log(msg):
@@ -34,24 +36,28 @@ def log(msg):
 
 
 def kernel_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per pass launch from committed counter summaries, if they were
-    taken on the current kernel source."""
+def measured_traffic(tile):
+    """HBM bytes per pass launch (FETCH_SIZE and WRITE_SIZE, scaled by a copy
+    of known size) from the committed counter summary, if it was taken on the
+    current kernel source and the same tile shape; else None."""
     try:
         with open(TRAFFIC_FILE) as f:
             d = json.load(f)
     except (OSError, ValueError):
         return None
-    if d.get("kernel_sha256_16") != kernel_hash():
+    if d.get("kernel_sha256_16") != kernel_hash() or list(d.get("tile", [])) != list(tile):
         return None
     return d.get("bytes_per_pass_launch")
 
 
-def time_precision(M, W, prec, steps, warmup):
+def time_precision(M, W, prec, steps, warmup, tile=None):
     import torch
 
     w = W.C5_SC464_ROOFLINE
@@ -59,10 +65,15 @@ def time_precision(M, W, prec, steps, warmup):
     scratch = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
     sim = M.Simulation([rep], precision=prec, seed=w["seed"], scratch=scratch)
     n = sim.n_occ[0]
-    # kernel / tile shape chosen by the library's autotuner (its trial sweeps
-    # are ordinary sweeps of the chain and count as warm-up)
-    tile = sim.autotune(trial_sweeps=6, measure=True)
-    log(f"[bench] {prec}: {n} spins, autotuned tile {sim.get_tile()}, warmup {warmup}")
+    if tile is None:
+        # kernel / tile shape chosen by the library's autotuner (its trial
+        # sweeps are ordinary sweeps of the chain and count as warm-up)
+        tile = sim.autotune(trial_sweeps=6, measure=True)
+        how = "autotuned"
+    else:
+        sim.set_tile(tile[1], tile[2], tile[3], kernel=tile[0])
+        how = "fixed"
+    log(f"[bench] {prec}: {n} spins, {how} tile {sim.get_tile()}, warmup {warmup}")
     if warmup:
         sim.sweep(warmup, measure=True)
     sim.synchronize()
@@ -115,7 +126,8 @@ def cpu_baseline(W, sweeps):
                       f"colour), {dt:.1f} s; table build and initial state not timed"}
 
 
-def copy_probe(gib=2.0, reps=20):
+def copy_probe(gib=2.0, reps=20, emit=True):
+    """Device-to-device copy of `gib` GiB (read + write of that size each)."""
     import torch
 
     n = int(gib * 2**30) // 4
@@ -132,8 +144,13 @@ def copy_probe(gib=2.0, reps=20):
     e.synchronize()
     ms = s.elapsed_time(e) / reps
     gbps = 2 * n * 4 / (ms * 1e-3) / 1e9
-    print(json.dumps({"probe": "device copy", "bytes_read": n * 4, "bytes_written": n * 4,
-                      "ms": ms, "GBps": gbps}), flush=True)
+    res = {"probe": "device copy", "bytes_read": n * 4, "bytes_written": n * 4, "ms": ms,
+           "GBps": gbps}
+    del a, b
+    torch.cuda.empty_cache()
+    if emit:
+        print(json.dumps(res), flush=True)
+    return res
 
 
 def main():
@@ -146,7 +163,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--tile", default=None,
+                    help="kernel,tx,ty,zc for the FP32 leg instead of autotuning "
+                         "(kernel 0 tile, 1 strip, 2 band)")
     args = ap.parse_args()
+    tile = None
+    if args.tile:
+        tile = tuple(int(v) for v in args.tile.split(","))
+        if len(tile) != 4:
+            ap.error("--tile takes kernel,tx,ty,zc")
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported: this build runs the sweep on one "
               "GPU (multi-GPU slab decomposition is a design note only)", file=sys.stderr)
@@ -161,13 +186,18 @@ def main():
     from paper_2106_11286_amd import workloads as W
 
     w = W.C5_SC464_ROOFLINE
-    r32 = time_precision(M, W, "f32", args.steps, args.warmup)
+    r32 = time_precision(M, W, "f32", args.steps, args.warmup, tile)
     r64 = None if args.no_fp64 else time_precision(M, W, "f64", min(args.steps, args.fp64_steps),
                                                   min(args.warmup, 5))
     cpu = None
     if rank == 0 and not args.no_cpu_baseline:
         cpu = cpu_baseline(W, args.cpu_sweeps)
-    traffic = measured_traffic()
+    t32 = r32["tile"]
+    traffic = measured_traffic([["tile", "strip", "band"].index(t32["kernel"]), t32["tx"],
+                                t32["ty"], t32["zc"]])
+    copy = copy_probe(emit=False)
+    log(f"[bench] device copy {copy['GBps']:.0f} GB/s")
+    ach = r32["achieved_GBps"]
     out = {
         "metric": "spin-update attempts/ns (G updates/s) + % HBM roofline, FP32 vs FP64, 10^8 spins",
         "value": r32["value"],
@@ -185,9 +215,13 @@ def main():
                    "spins": r32["n_spins"], "J": w["J"], "K": w["K"], "e": list(w["e"]),
                    "T": w["T"], "seed": w["seed"], "step": "one measured sweep (2 colour passes "
                    "+ fused FP64 observables)", "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": r32["achieved_GBps"], "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": r32["achieved_GBps"] / HBM_PEAK_GBPS,
+        "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": ach / HBM_PEAK_GBPS,
                      "traffic": traffic,
+                     "copy_GBps": copy["GBps"], "frac_of_copy": ach / copy["GBps"],
+                     # the same updates priced at the 24 B/update minimum (each
+                     # spin read and written once per sweep)
+                     "frac_at_24B_per_update": r32["value"] * 24.0 / HBM_PEAK_GBPS,
                      "kernel": "sc colour pass, FP32, measured (%s %dx%dx%d)" % (
                          r32["tile"]["kernel"], r32["tile"]["tx"], r32["tile"]["ty"],
                          r32["tile"]["zc"]),
