@@ -132,6 +132,8 @@ typedef struct {
     double C;   /* specific heat per spin, (<E^2> - <E>^2)/(N T^2) */
     double chi; /* susceptibility per spin, N (<m^2> - <|m|>^2)/T */
     double acceptance;
+    double U4_err; /* jackknife over 32 contiguous blocks (record i in block
+                    * floor(32 i / n); n blocks of one record when n < 32) */
 } mc_stats;
 
 typedef struct mc_sim mc_sim; /* opaque handle */

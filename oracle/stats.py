@@ -31,6 +31,26 @@ def blocking_error(x) -> float:
     return float(best)
 
 
+def binder_jackknife_error(m2, m4, n_blocks: int = 32) -> float:
+    """Error of U4 = 1 - <m^4>/(3 <m^2>^2) by the delete-one-block jackknife
+    (Efron 1982; blocks long compared with the autocorrelation time):
+    B = min(n_blocks, n) contiguous blocks, record i in block floor(B i / n);
+    U4 re-evaluated with each block left out; error^2 = (B-1)/B * sum of
+    squared deviations of those values from their mean."""
+    m2 = np.asarray(m2, dtype=np.float64)
+    m4 = np.asarray(m4, dtype=np.float64)
+    n = m2.size
+    B = min(n_blocks, n)
+    if B < 2:
+        return 0.0
+    block = (np.arange(n, dtype=np.int64) * B) // n
+    u = np.empty(B)
+    for b in range(B):
+        keep = block != b
+        u[b] = 1.0 - m4[keep].mean() / (3.0 * m2[keep].mean() ** 2)
+    return float(np.sqrt((B - 1) / B * np.sum((u - u.mean()) ** 2)))
+
+
 def series_summary(records, n_sites: int, T: float):
     """From per-sweep records (rows {Mx, My, Mz (sums), E_exch, E_anis, ...})
     compute means and blocked errors of |m|, m^2, m^4, E/N and the derived
@@ -48,6 +68,7 @@ def series_summary(records, n_sites: int, T: float):
         out[name] = float(s.mean())
         out[name + "_err"] = blocking_error(s)
     out["U4"] = 1.0 - out["m4"] / (3.0 * out["m2"] ** 2)
+    out["U4_err"] = binder_jackknife_error(m2, m4)
     if T > 0 and np.isfinite(T):
         out["C"] = float((np.mean(E * E) - np.mean(E) ** 2) / (n_sites * T * T))
         out["chi"] = float(n_sites * (out["m2"] - out["abs_m"] ** 2) / T)

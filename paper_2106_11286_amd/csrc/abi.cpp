@@ -539,6 +539,38 @@ double blocked_error(std::vector<double> x)
     return best;
 }
 
+// Error of the Binder cumulant U4 = 1 - <m^4>/(3 <m^2>^2): delete-one-block
+// jackknife over B = min(32, n) contiguous blocks, record i in block
+// floor(B i / n).
+double binder_jackknife(const std::vector<double> &m2, const std::vector<double> &m4)
+{
+    const size_t n = m2.size();
+    const size_t B = std::min<size_t>(32, n);
+    if (B < 2) return 0.0;
+    std::vector<double> s2(B, 0.0), s4(B, 0.0), cnt(B, 0.0);
+    double t2 = 0.0, t4 = 0.0;
+    for (size_t i = 0; i < n; ++i) {
+        const size_t b = (size_t)(((unsigned __int128)i * B) / n);
+        s2[b] += m2[i];
+        s4[b] += m4[i];
+        cnt[b] += 1.0;
+        t2 += m2[i];
+        t4 += m4[i];
+    }
+    std::vector<double> u(B);
+    double mu = 0.0;
+    for (size_t b = 0; b < B; ++b) {
+        const double rest = (double)n - cnt[b];
+        const double q2 = (t2 - s2[b]) / rest, q4 = (t4 - s4[b]) / rest;
+        u[b] = 1.0 - q4 / (3.0 * q2 * q2);
+        mu += u[b];
+    }
+    mu /= (double)B;
+    double v = 0.0;
+    for (double x : u) v += (x - mu) * (x - mu);
+    return std::sqrt(v * (double)(B - 1) / (double)B);
+}
+
 } // namespace
 
 extern "C" {
@@ -1218,6 +1250,7 @@ mc_status mc_series_stats(const mc_obs *series, uint64_t n, uint64_t stride, dou
     out->e = mean_of(e);
     out->e_err = blocked_error(e);
     out->U4 = 1.0 - out->m4 / (3.0 * out->m2 * out->m2);
+    out->U4_err = binder_jackknife(m2, m4);
     out->acceptance = acc / (double)n;
     if (T > 0.0 && std::isfinite(T)) {
         const double mE = mean_of(E);

@@ -67,7 +67,7 @@ class Schedule(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("n", ctypes.c_uint64)] + [(k, ctypes.c_double) for k in (
         "abs_m", "abs_m_err", "m2", "m2_err", "m4", "m4_err", "e", "e_err", "U4", "C", "chi",
-        "acceptance")]
+        "acceptance", "U4_err")]
 
 
 # Every exported symbol with its argument types (checked against the header in

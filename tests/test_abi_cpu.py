@@ -89,7 +89,7 @@ def test_series_stats_against_oracle(M):
     ref = OS.series_summary(np.column_stack([m * N, E, np.zeros(n)]), N, T)
     for k in ("abs_m", "m2", "m4", "e", "U4"):
         assert st[k] == pytest.approx(ref[k], rel=1e-10), k
-    for k in ("abs_m_err", "m2_err", "m4_err", "e_err"):
+    for k in ("abs_m_err", "m2_err", "m4_err", "e_err", "U4_err"):
         assert st[k] == pytest.approx(ref[k], rel=1e-10), k
     assert st["C"] == pytest.approx(ref["C"], rel=1e-10)
     assert st["chi"] == pytest.approx(ref["chi"], rel=1e-10)

@@ -1,0 +1,150 @@
+"""GPU statistics: distribution parity of long runs and the batched-replica
+workload.
+
+Long-run bar (independent seeds, so the two runs are independent samples of
+the same Boltzmann distribution of Eq. (1)): for each observable
+z = (a - b) / sqrt(err_a^2 + err_b^2), errors by blocking (jackknife for the
+Binder cumulant).  The reported bar is |z| <= 3.  Over n comparisons about
+0.27 % x n exceed 3 by chance, so a family of comparisons passes when every
+|z| <= 4 and no more than max(1, n/20) exceed 3; a systematic bias of the
+FP32 path would push many z the same way.
+
+Batched workload: 64 replicas of uneven size and temperature in one
+persistent launch give bitwise the spins of each replica run alone, and the
+FP64 batch follows the oracle's chain.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from oracle import stats as OS
+from paper_2106_11286_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+OBS = ("abs_m", "m2", "e", "U4")
+
+
+@pytest.fixture(scope="module")
+def M():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    from paper_2106_11286_amd import mcheis
+
+    return mcheis
+
+
+def natural(sim, r=0):
+    return [t.double().cpu().numpy() for t in sim.to_natural(r)]
+
+
+def zscore(a, b, k):
+    return (a[k] - b[k]) / np.hypot(a[k + "_err"], b[k + "_err"])
+
+
+def check_family(z, label):
+    z = np.asarray(z, dtype=np.float64)
+    print(f"{label}: max |z| {np.max(np.abs(z)):.2f}, |z| > 3: {int(np.sum(np.abs(z) > 3))} "
+          f"of {z.size}, mean z {z.mean():+.2f}")
+    assert np.all(np.isfinite(z)), label
+    assert np.max(np.abs(z)) <= 4.0, (label, z)
+    assert np.sum(np.abs(z) > 3.0) <= max(1, z.size // 20), (label, z)
+
+
+def test_fp32_batched_long_run_matches_oracle(M):
+    """Five sc L=10 replicas (T from 0.9 to 2.5, through T_c) advanced together
+    in persistent FP32 launches; 2000 + 20000 sweeps from the aligned state.
+    <|m|>, <m^2>, <e> and U4 agree with FP64 oracle runs of other seeds."""
+    Ts = (0.9, 1.3, 1.45, 1.7, 2.5)
+    L, K, n_eq, n_meas = 10, 0.1, 2000, 20000
+    reps = [M.Replica(kind="sc", L=(L, L, L), K=K, T=T, replica_id=r) for r, T in enumerate(Ts)]
+    sim = M.Simulation(reps, precision="f32", seed=101, init="aligned")
+    rec = sim.run_schedule([list(Ts)], n_equil=n_eq, n_meas=n_meas, persistent=True)[0]
+    N = L ** 3
+    z = []
+    for r, T in enumerate(Ts):
+        g = M.series_stats(rec[:, r, :], N, T)
+        lat = O.Lattice(O.SC, L, L, L)
+        p = O.Params(J=1.0, K=K, e=(0.0, 0.0, 1.0), T=T, seed=202, replica_id=r)
+        s = O.init(lat, p, O.INIT_ALIGNED)
+        O.run(lat, p, 0, n_eq, s, record=False)
+        o = OS.series_summary(O.run(lat, p, n_eq, n_meas, s), N, T)
+        zs = [zscore(g, o, k) for k in OBS]
+        print(f"T={T}: " + ", ".join(f"{k} {g[k]:.5f}/{o[k]:.5f} z={v:+.2f}"
+                                      for k, v in zip(OBS, zs)))
+        z += zs
+    check_family(z, "FP32 batch vs FP64 oracle")
+
+
+def test_c2_ladder_fp32_vs_fp64(M):
+    """The temperature-sweep schedule (17 T from 0.4 to 2.0, 2000 + 2000
+    sweeps each, state carried up the ladder, K = 0.05) at L = 24 from the
+    aligned state: FP32 and FP64 GPU runs with independent seeds agree on
+    <|m|>, <m^2>, <e> and U4 at every temperature."""
+    w = W.C2_SC256_TSWEEP
+    L = 24
+    Ts = np.asarray(w["T_ladder"])
+    rep = M.Replica(**W.replica_fields(w, L=(L, L, L)))
+    out = {}
+    for prec, seed in (("f32", 11), ("f64", 12)):
+        sim = M.Simulation([rep], precision=prec, seed=seed, init="aligned")
+        rec = sim.run_schedule(Ts, n_equil=w["n_equil"], n_meas=w["n_meas"])
+        out[prec] = [M.series_stats(rec[i, :, 0, :], L ** 3, T) for i, T in enumerate(Ts)]
+    z = []
+    for i, T in enumerate(Ts):
+        a, b = out["f32"][i], out["f64"][i]
+        zs = [zscore(a, b, k) for k in OBS]
+        print(f"T={T:.2f}: " + ", ".join(f"{k} z={v:+.2f}" for k, v in zip(OBS, zs)))
+        z += zs
+    check_family(z, "FP32 vs FP64 ladder")
+
+
+def test_c3_batched_equals_unbatched_and_oracle(M):
+    """The 64-replica workload (L in {32, 48, 64, 96}, T from 0.8 to 2.0): one
+    persistent FP32 batch equals every replica run alone, bitwise; the FP64
+    batch follows the oracle over 10 sweeps for the L = 32 replicas."""
+    import torch
+
+    w = W.C3_BATCHED
+    fields = W.c3_replicas(w)
+    reps = [M.Replica(**f) for f in fields]
+    scratch = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+    batch = M.Simulation(reps, precision="f32", seed=w["seed"], scratch=scratch)
+    batch.autotune(trial_sweeps=1, measure=True, persistent=True)
+    batch.sweep(4, measure=True, persistent=True)
+    t = batch.get_sweep()
+    obs_b = batch.observables()
+    for r, rep in enumerate(reps):
+        one = M.Simulation([rep], precision="f32", seed=w["seed"])
+        one.sweep(t - 1)
+        one.sweep(1, measure=True)
+        for a, b in zip(natural(one), natural(batch, r)):
+            assert np.array_equal(a, b), r
+        o = one.observables()[0]
+        assert o["n_accepted"] == obs_b[r]["n_accepted"], r
+        assert abs(o["E"] - obs_b[r]["E"]) <= 1e-9 * abs(o["E"]), r
+        one.close()
+    batch.close()
+    del scratch
+
+    b64 = M.Simulation(reps, precision="f64", seed=w["seed"])
+    b64.sweep(10, measure=True, persistent=True)
+    obs = b64.observables()
+    n_checked = 0
+    for r, f in enumerate(fields):
+        if f["L"][0] != 32:
+            continue
+        lat = O.Lattice(O.SC, *f["L"], periodic_mask=f["periodic_mask"])
+        p = O.Params(J=f["J"], K=f["K"], e=f["e"], T=f["T"], seed=w["seed"], replica_id=r)
+        s = O.init(lat, p)
+        ref = O.run(lat, p, 0, 10, s)
+        for a, b in zip(natural(b64, r), s):
+            assert np.max(np.abs(a - b)) <= 1e-12, r
+        N = lat.n_occ
+        assert obs[r]["n_accepted"] == int(ref[-1, 5]), r
+        assert np.max(np.abs(np.array(obs[r]["M"]) - ref[-1, 0:3] / N)) <= 1e-12, r
+        E = ref[-1, 3] + ref[-1, 4]
+        assert abs(obs[r]["E"] - E) <= 1e-10 * abs(E), r
+        n_checked += 1
+    assert n_checked >= 4
