@@ -153,6 +153,125 @@ def copy_probe(gib=2.0, reps=20, emit=True):
     return res
 
 
+# ---------------------------------------------------------------------------
+# The other workloads (``--workload``): throughput lines for the trajectory,
+# temperature-ladder, batched-replica and nanoparticle configurations.
+# ---------------------------------------------------------------------------
+def _timed(fn):
+    import torch
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t0
+
+
+def run_c1(M, W, cpu):
+    """sc L=16 FP64, 1000 measured sweeps (per-sweep records), graph-replayed
+    and persistent; the oracle's full 1000 sweeps on one and on all threads."""
+    w = W.C1_SC16_TRAJECTORY
+    rep = M.Replica(**W.replica_fields(w))
+    n = w["sweeps"]
+    res = {"workload": w["name"], "spins": 4096, "sweeps": n, "dtype": "f64"}
+    for mode in ("graph", "persistent"):
+        sim = M.Simulation([rep], precision="f64", seed=w["seed"])
+        # the first call captures the graphs; the second (continuing the
+        # chain) is timed
+        sim.run_schedule([rep.T], 0, n, persistent=mode == "persistent")
+        _, dt = _timed(lambda: sim.run_schedule([rep.T], 0, n, persistent=mode == "persistent"))
+        res[mode] = {"s": dt, "updates_per_ns": 4096 * n / dt / 1e9, "us_per_sweep": dt / n * 1e6}
+    if cpu:
+        from oracle import oracle as O
+
+        lat = O.Lattice(O.SC, *w["L"], periodic_mask=w["periodic_mask"])
+        p = O.Params(J=w["J"], K=w["K"], e=w["e"], T=w["T"], seed=w["seed"])
+        all_threads = O.num_threads()
+        for nt in (1, all_threads):
+            O.set_num_threads(nt)
+            s = O.init(lat, p)
+            t0 = time.perf_counter()
+            O.run(lat, p, 0, n, s)
+            dt = time.perf_counter() - t0
+            res[f"oracle_{nt}_threads"] = {"s": dt, "ns_per_update": dt / (4096 * n) * 1e9}
+        O.set_num_threads(all_threads)
+    return res
+
+
+def run_c2(M, W):
+    """sc L=256 temperature ladder (17 T, 2000 + 2000 sweeps each, random
+    start, state carried up the ladder), FP32 and FP64 with independent seeds:
+    throughput and per-temperature averages with blocked errors."""
+    w = W.C2_SC256_TSWEEP
+    rep = M.Replica(**W.replica_fields(w))
+    Ts = list(w["T_ladder"])
+    N = 256 ** 3
+    res = {"workload": w["name"], "spins": N, "T": Ts, "n_equil": w["n_equil"],
+           "n_meas": w["n_meas"]}
+    stats = {}
+    for prec, seed in (("f32", w["seed"]), ("f64", w["seed"] + 100)):
+        sim = M.Simulation([rep], precision=prec, seed=seed)
+        tile = sim.autotune(trial_sweeps=4, measure=True)
+        sim.set_sweep(0)
+        sim.close()
+        sim = M.Simulation([rep], precision=prec, seed=seed)
+        sim.set_tile(tile[1], tile[2], tile[3], kernel=tile[0])
+        rec, dt = _timed(lambda: sim.run_schedule(Ts, w["n_equil"], w["n_meas"]))
+        n_upd = N * len(Ts) * (w["n_equil"] + w["n_meas"])
+        stats[prec] = [M.series_stats(rec[i, :, 0, :], N, T) for i, T in enumerate(Ts)]
+        res[prec] = {"s": dt, "updates_per_ns": n_upd / dt / 1e9, "tile": list(tile), "seed": seed}
+        log(f"[bench] c2 {prec}: {res[prec]['updates_per_ns']:.1f} updates/ns")
+        sim.close()
+    rows = []
+    for i, T in enumerate(Ts):
+        a, b = stats["f32"][i], stats["f64"][i]
+        row = {"T": T}
+        for k in ("abs_m", "m2", "e", "U4"):
+            row[k] = [a[k], b[k]]
+            row["z_" + k] = (a[k] - b[k]) / max(1e-300, (a[k + "_err"] ** 2 + b[k + "_err"] ** 2) ** 0.5)
+        rows.append(row)
+    res["ladder"] = rows
+    return res
+
+
+def run_c3(M, W, sweeps):
+    """64 sc replicas (L in {32, 48, 64, 96}, T 0.8 .. 2.0), FP32, all advanced
+    by one persistent launch per call; autotuned tile; also the same sweeps as
+    per-pass launches."""
+    import torch
+
+    w = W.C3_BATCHED
+    reps = [M.Replica(**f) for f in W.c3_replicas(w)]
+    scratch = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+    sim = M.Simulation(reps, precision="f32", seed=w["seed"], scratch=scratch)
+    N = sum(sim.n_occ)
+    tile = sim.autotune(trial_sweeps=3, measure=True, persistent=True)
+    res = {"workload": w["name"], "replicas": len(reps), "spins": N, "sweeps": sweeps,
+           "tile": list(tile)}
+    sim.sweep(20, measure=True, persistent=True)
+    _, dt = _timed(lambda: sim.sweep(sweeps, measure=True, persistent=True))
+    res["persistent"] = {"s": dt, "updates_per_ns": N * sweeps / dt / 1e9}
+    _, dt = _timed(lambda: sim.sweep(sweeps, measure=True))
+    res["per_pass_launches"] = {"s": dt, "updates_per_ns": N * sweeps / dt / 1e9}
+    return res
+
+
+def run_c4(M, W, sweeps):
+    """FCC nanoparticle (128^3 cells, sphere R = 60, open surface), FP32, four
+    colour passes; rate per occupied site."""
+    w = W.C4_FCC_PARTICLE
+    rep = M.Replica(**W.replica_fields(w))
+    sim = M.Simulation([rep], precision="f32", seed=w["seed"])
+    N = sim.n_occ[0]
+    tile = sim.autotune(trial_sweeps=3, measure=True)
+    sim.sweep(20, measure=True)
+    _, dt = _timed(lambda: sim.sweep(sweeps, measure=True))
+    box = 4 * 128 ** 3
+    return {"workload": w["name"], "spins": N, "box_sites": box, "sweeps": sweeps,
+            "tile": list(tile), "s": dt, "updates_per_ns": N * sweeps / dt / 1e9,
+            "box_sites_per_ns": box * sweeps / dt / 1e9}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -163,6 +282,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--workload", default="c5", choices=["c5", "c1", "c2", "c3", "c4"],
+                    help="c5 (default): the 10^8-spin headline; others print their own line")
     ap.add_argument("--tile", default=None,
                     help="kernel,tx,ty,zc for the FP32 leg instead of autotuning "
                          "(kernel 0 tile, 1 strip, 2 band)")
@@ -184,6 +305,18 @@ def main():
         return
     from paper_2106_11286_amd import mcheis as M
     from paper_2106_11286_amd import workloads as W
+
+    if args.workload != "c5":
+        if args.workload == "c1":
+            out = run_c1(M, W, cpu=not args.no_cpu_baseline)
+        elif args.workload == "c2":
+            out = run_c2(M, W)
+        elif args.workload == "c3":
+            out = run_c3(M, W, W.C3_BATCHED["sweeps"])
+        else:
+            out = run_c4(M, W, 1000)
+        print(json.dumps(out), flush=True)
+        return
 
     w = W.C5_SC464_ROOFLINE
     r32 = time_precision(M, W, "f32", args.steps, args.warmup, tile)

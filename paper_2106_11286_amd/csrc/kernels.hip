@@ -920,9 +920,11 @@ __global__ void __launch_bounds__(256) k_persistent(PassLaunch P, PersistLaunch 
         const uint32_t r = P.work_dev[item].rep;
         const uint32_t phase = sw * A.n_colours + c;
         if (threadIdx.x == 0) {
+            // poll with plain (relaxed) loads; the acquire fence below, once
+            // the phase is released, orders the unit's reads after it
             uint32_t ok = 1;
             for (uint32_t spins = 0;
-                 __hip_atomic_load(&ready[r], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < phase;
+                 __hip_atomic_load(&ready[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < phase;
                  ++spins) {
                 if (spins >= A.spin_limit ||
                     __hip_atomic_load(&hdr[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
@@ -946,7 +948,9 @@ __global__ void __launch_bounds__(256) k_persistent(PassLaunch P, PersistLaunch 
         if (threadIdx.x == 0) {
             const RepDev &R = P.reps_dev[r];
             const uint32_t n_r = R.item_end - R.item_begin;
-            const uint32_t old = __hip_atomic_fetch_add(&done[r], 1u, __ATOMIC_ACQ_REL,
+            // every wave released its stores above; the count itself needs
+            // no ordering of its own
+            const uint32_t old = __hip_atomic_fetch_add(&done[r], 1u, __ATOMIC_RELAXED,
                                                         __HIP_MEMORY_SCOPE_AGENT);
             s_flag = (old + 1u == (phase + 1u) * n_r);
         }
@@ -977,8 +981,10 @@ __global__ void __launch_bounds__(256) k_persistent(PassLaunch P, PersistLaunch 
                 }
             }
             if (threadIdx.x == 0) {
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-                __hip_atomic_store(&ready[r], phase + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                // the other units of this phase released their stores before
+                // counting; acquire them, then release the next phase
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+                __hip_atomic_store(&ready[r], phase + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
         __syncthreads();
@@ -1291,8 +1297,12 @@ template <typename T, bool MEASURE>
 static hipError_t persist_dispatch(int kind, const PassLaunch &p, const PersistLaunch &a,
                                    hipStream_t st)
 {
+    // at most one phase of every replica (n_items units in all) can run at a
+    // time; workgroups beyond twice that would only wait
     const uint64_t total = (uint64_t)a.n_sweeps * a.n_colours * p.n_items;
-    const unsigned grid = (unsigned)(total < 2048 ? total : 2048);
+    uint64_t cap = 2ull * p.n_items;
+    if (cap > 2048) cap = 2048;
+    const unsigned grid = (unsigned)(total < cap ? total : cap);
     if (grid == 0) return hipSuccess;
     const int threads = p.tile.kernel == KERNEL_TILE ? ((p.tile.tx * p.tile.ty + 63) / 64) * 64
                                                      : p.tile.tx;
