@@ -229,11 +229,17 @@ mc_status mc_set_sweep(mc_sim *h, uint64_t t);
  *  kernel 2 (sc only, default): as kernel 1, but rows grouped in bands of ty
  *    rows (2 or 4) and the (band, column) positions dealt to the tx threads
  *    contiguously, so no lane idles whatever the row length; a tile is tx
- *    positions x zc planes.
+ *    positions x zc planes;
+ *  kernel 3 (any lattice whose three component planes fit one workgroup's
+ *    LDS; the default then): whole sweeps in LDS, one workgroup of tx threads
+ *    (64 .. 1024, multiple of 64) per replica, colour passes separated by
+ *    workgroup barriers; ty and zc are ignored.  Single passes (mc_debug_pass,
+ *    mc_measure_state) keep using the previous pass kernel.  A replica too
+ *    large gives MC_E_UNSUPPORTED.
  * The spins do not depend on the choice (only the FP64 summation order of the
  * observables does).  A shape whose work list does not fit the handle's
- * scratch gives MC_E_BUFFER.  Discards the record of the last measured sweep.
- * Synchronises. */
+ * scratch gives MC_E_BUFFER.  Choosing kernel 0-2 discards the record of the
+ * last measured sweep.  Synchronises. */
 mc_status mc_set_tile(mc_sim *h, int32_t kernel, int32_t tx, int32_t ty, int32_t zc);
 mc_status mc_get_tile(const mc_sim *h, int32_t *kernel, int32_t *tx, int32_t *ty, int32_t *zc,
                       uint64_t *n_items);

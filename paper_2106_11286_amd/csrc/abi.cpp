@@ -49,6 +49,9 @@ mc_status fail(mc_status s, const char *fmt, ...)
     } while (0)
 
 constexpr uint32_t kRing = 256;       // observable records kept per replica
+// LDS kept back from the dynamic allocation of the LDS kernel for its static
+// arrays (reduction slots).
+constexpr uint32_t kLdsReserve = 2048;
 constexpr uint32_t kTargetItems = 8192; // work items aimed for per pass
 constexpr uint32_t kGraphChunk = 64;  // sweeps per captured graph
 
@@ -333,7 +336,9 @@ struct mc_sim {
     std::vector<RepDev> reps;
     std::vector<uint64_t> n_occ;
     std::vector<WorkItem> work;
-    Tile tile{};
+    Tile tile{};      // kernel of whole sweeps
+    Tile pass_tile{}; // kernel of single passes (= tile unless tile is the LDS kernel)
+    uint32_t lds_max = 0; // dynamic LDS a workgroup may use on this device (bytes)
     hipStream_t stream = nullptr;
     char *scratch = nullptr;
     uint64_t scratch_bytes = 0;
@@ -372,17 +377,56 @@ PassLaunch pass_args(mc_sim *h, uint32_t item_base, uint32_t n_blocks, uint32_t 
     p.t_off = t_off;
     p.seed_lo = (uint32_t)h->seed;
     p.seed_hi = (uint32_t)(h->seed >> 32);
-    p.tile = h->tile;
+    p.tile = h->pass_tile;
     p.partials_dev = h->partials;
     p.dbg_dh = nullptr;
     p.dbg_acc = nullptr;
     return p;
 }
 
+// LDS bytes the LDS kernel needs: three component planes of the largest replica.
+uint64_t lds_need(const mc_sim *h)
+{
+    const uint64_t esz = h->prec == MC_F64 ? sizeof(double) : sizeof(float);
+    uint64_t m = 0;
+    for (const RepDev &R : h->reps) m = std::max<uint64_t>(m, 3ull * R.n_box * esz);
+    return m;
+}
+
+bool lds_fits(const mc_sim *h) { return h->lds_max > 0 && lds_need(h) <= h->lds_max; }
+
+// Threads of the default LDS tile: one per site of a colour, 64 .. 1024.
+int lds_threads(const mc_sim *h)
+{
+    uint32_t m = 64;
+    for (const RepDev &R : h->reps) m = std::max<uint32_t>(m, R.plane);
+    return (int)std::min<uint32_t>(1024, (m + 63) / 64 * 64);
+}
+
+// n whole sweeps of every replica by the LDS kernel, then the counter advance.
+mc_status enqueue_lds(mc_sim *h, uint32_t n, bool measure, uint32_t slot0)
+{
+    LdsLaunch L;
+    L.reps_dev = h->reps_dev;
+    L.n_reps = (uint32_t)h->n_reps;
+    L.n_sweeps = n;
+    L.tctr_dev = h->tctr;
+    L.seed_lo = (uint32_t)h->seed;
+    L.seed_hi = (uint32_t)(h->seed >> 32);
+    L.records = h->records;
+    L.ring = kRing;
+    L.slot0 = slot0;
+    L.lds_bytes = (uint32_t)lds_need(h);
+    HIP_TRY(launch_lds(h->kind, h->prec == MC_F64, measure, L, h->tile.tx, h->stream));
+    HIP_TRY(launch_advance(h->tctr, n, h->stream));
+    return MC_OK;
+}
+
 // Enqueue n sweeps (passes, optional finalise into ring slots slot0.., then
 // the counter advance).  Pure launches: safe inside stream capture.
 mc_status enqueue_sweeps(mc_sim *h, uint32_t n, bool measure, uint32_t slot0)
 {
+    if (h->tile.kernel == KERNEL_LDS) return enqueue_lds(h, n, measure, slot0);
     const bool f64 = h->prec == MC_F64;
     const uint32_t n_items = (uint32_t)h->work.size();
     for (uint32_t i = 0; i < n; ++i) {
@@ -405,10 +449,14 @@ bool persistent_supported(const Tile &t)
     return t.kernel != KERNEL_STRIP || t.ty == 2 || t.ty == 4;
 }
 
+// A persistent call with the LDS kernel is an LDS launch (already one launch
+// for all n sweeps, with no device-scope synchronisation).
+
 // n sweeps as one persistent launch (preceded by a counter reset, followed by
 // the counter advance).  Pure launches: safe inside stream capture.
 mc_status enqueue_persistent(mc_sim *h, uint32_t n, bool measure, uint32_t slot0)
 {
+    if (h->tile.kernel == KERNEL_LDS) return enqueue_lds(h, n, measure, slot0);
     if (!persistent_supported(h->tile))
         return fail(MC_E_UNSUPPORTED, "persistent sweeps: no kernel for strips of %d rows "
                                       "(use 2 or 4, or another kernel)", h->tile.ty);
@@ -503,7 +551,8 @@ mc_status run_chunk(mc_sim *h, uint32_t n, bool measure, uint32_t slot0, bool pe
         it = h->graphs.emplace(key, ex).first;
     }
     HIP_TRY(hipGraphLaunch(it->second, h->stream));
-    if (persistent) h->persist_used = true;
+    // the LDS kernel keeps no counters that a watchdog could trip
+    if (persistent && h->tile.kernel != KERNEL_LDS) h->persist_used = true;
     return MC_OK;
 }
 
@@ -660,8 +709,9 @@ mc_status mc_init_lattice(const mc_replica_desc *reps, int32_t n_reps, mc_precis
     h->stream = (hipStream_t)hip_stream;
     h->desc.assign(reps, reps + n_reps);
     h->tile = default_tile(reps, n_reps);
+    h->pass_tile = h->tile;
     std::vector<uint32_t> b, e;
-    make_work(reps, n_reps, h->tile, h->work, b, e);
+    make_work(reps, n_reps, h->pass_tile, h->work, b, e);
     h->lay = scratch_layout(n_reps, h->work.size(), h->n_colours);
     auto cleanup = [&](mc_status s) {
         mc_destroy(h);
@@ -728,7 +778,8 @@ mc_status mc_init_lattice(const mc_replica_desc *reps, int32_t n_reps, mc_precis
     if (hipMemcpyAsync(h->work_dev, h->work.data(), sizeof(WorkItem) * h->work.size(),
                        hipMemcpyHostToDevice, h->stream) != hipSuccess ||
         launch_set_counter(h->tctr, 0u, h->stream) != hipSuccess ||
-        launch_zero_u32(h->fin_count, (uint32_t)n_reps, h->stream) != hipSuccess)
+        launch_zero_u32(h->fin_count, (uint32_t)n_reps, h->stream) != hipSuccess ||
+        launch_zero_u32(h->pstate, persist_state_words(n_reps), h->stream) != hipSuccess)
         return cleanup(fail(MC_E_DEVICE, "upload failed: %s", hipGetErrorString(hipGetLastError())));
     if (init != MC_INIT_USER) {
         for (int r = 0; r < n_reps; ++r) {
@@ -741,6 +792,19 @@ mc_status mc_init_lattice(const mc_replica_desc *reps, int32_t n_reps, mc_precis
     }
     if (hipStreamSynchronize(h->stream) != hipSuccess)
         return cleanup(fail(MC_E_DEVICE, "init: %s", hipGetErrorString(hipGetLastError())));
+    // lattices whose state fits one workgroup's LDS run whole sweeps there
+    {
+        int dev = 0, lds = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) ==
+                hipSuccess &&
+            lds > (int)kLdsReserve)
+            h->lds_max = (uint32_t)lds - kLdsReserve;
+        (void)hipGetLastError();
+        if (lds_fits(h) && lds_allow(h->kind, prec == MC_F64, (uint32_t)lds_need(h)) == hipSuccess)
+            h->tile = Tile{KERNEL_LDS, lds_threads(h), 1, 1};
+        (void)hipGetLastError();
+    }
     *out = h;
     return MC_OK;
 }
@@ -773,6 +837,32 @@ mc_status mc_sweep_timed(mc_sim *h, uint32_t n_sweeps, uint32_t flags, double *p
     if (n_sweeps == 0) return fail(MC_E_ARG, "n_sweeps must be >= 1");
     if (h->t + n_sweeps > 0xFFFFFFFFull) return fail(MC_E_STATE, "sweep counter would exceed 2^32-1");
     const bool measure = flags & MC_MEASURE;
+    if (h->tile.kernel == KERNEL_LDS) {
+        // whole sweeps in one launch: the pass time reported is the average
+        // share of a colour pass
+        hipEvent_t e0, e1;
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        const uint32_t slot0 = (uint32_t)(h->n_measured % kRing);
+        hipError_t err = hipEventRecord(e0, h->stream);
+        mc_status st = err == hipSuccess ? enqueue_lds(h, n_sweeps, measure, slot0) : MC_OK;
+        if (err == hipSuccess && st == MC_OK) err = hipEventRecord(e1, h->stream);
+        if (err == hipSuccess && st == MC_OK) err = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (err == hipSuccess && st == MC_OK) err = hipEventElapsedTime(&ms, e0, e1);
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (st != MC_OK) return st;
+        if (err != hipSuccess) return fail(MC_E_DEVICE, "timed sweeps: %s", hipGetErrorString(err));
+        h->t += n_sweeps;
+        if (measure) {
+            h->n_measured += n_sweeps;
+            h->last_slot = (int64_t)((slot0 + n_sweeps - 1) % kRing);
+        }
+        *total_ms = ms;
+        *pass_ms_avg = ms / (double)(n_sweeps * (uint32_t)h->n_colours);
+        return MC_OK;
+    }
     const bool f64 = h->prec == MC_F64;
     const uint32_t n_items = (uint32_t)h->work.size();
     const uint32_t n_pass = n_sweeps * (uint32_t)h->n_colours;
@@ -996,6 +1086,21 @@ mc_status mc_layout_copy(mc_sim *h, int32_t replica, int32_t to_natural, void *n
 mc_status mc_set_tile(mc_sim *h, int32_t kernel, int32_t tx, int32_t ty, int32_t zc)
 {
     if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
+    if (kernel == KERNEL_LDS) {
+        if (tx < 64 || tx > 1024 || tx % 64)
+            return fail(MC_E_ARG, "LDS tile: tx (threads per replica) must be a multiple of 64 "
+                                  "in [64, 1024] (got %d)", tx);
+        if (!lds_fits(h))
+            return fail(MC_E_UNSUPPORTED, "LDS kernel: a replica needs %llu bytes of LDS, a "
+                                          "workgroup may use %u",
+                        (unsigned long long)lds_need(h), h->lds_max);
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        HIP_TRY(lds_allow(h->kind, h->prec == MC_F64, (uint32_t)lds_need(h)));
+        for (auto &kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+        h->graphs.clear();
+        h->tile = Tile{KERNEL_LDS, tx, 1, 1};
+        return MC_OK;
+    }
     Tile t{kernel, tx, ty, zc};
     uint64_t max_bytes = 0;
     for (const RepDev &R : h->reps)
@@ -1014,6 +1119,7 @@ mc_status mc_set_tile(mc_sim *h, int32_t kernel, int32_t tx, int32_t ty, int32_t
     for (auto &kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
     h->graphs.clear();
     h->tile = t;
+    h->pass_tile = t;
     h->work.swap(work);
     h->lay = lay;
     h->reps_dev = (RepDev *)(h->scratch + lay.off_reps);
@@ -1062,6 +1168,8 @@ std::vector<Tile> tile_candidates(const mc_sim *h)
         base.push_back(Tile{KERNEL_TILE, tx, ty, 1});
     }
     std::vector<Tile> out;
+    if (lds_fits(h))
+        for (int threads : {256, 512, 1024}) out.push_back(Tile{KERNEL_LDS, threads, 1, 1});
     for (Tile t : base) {
         uint64_t cols = 0;
         int planes = 1;

@@ -239,6 +239,42 @@ __device__ __forceinline__ void accumulate(double (&acc)[Q_N], T sx, T sy, T sz,
 // the tile's z range; neighbours are loaded directly (cache hits).  Used for
 // short rows.
 // ---------------------------------------------------------------------------
+// Field of the six neighbours of a simple-cubic site (J not applied), summed
+// in the fixed order -z, -y, -x, +x, +y, +z over the other colour's plane at
+// element offset oth.  P is a global or an LDS pointer; missing neighbours
+// across open faces contribute nothing.
+template <typename T, typename P>
+__device__ __forceinline__ void sc_site_field(P gx, P gy, P gz, uint32_t oth, int Lxh, int Ly,
+                                              int Lz, bool px, bool py, bool pz, int xh, int y,
+                                              int z, int p, T &hx, T &hy, T &hz)
+{
+    const int ym = y > 0 ? y - 1 : (py ? Ly - 1 : -1);
+    const int yp = y < Ly - 1 ? y + 1 : (py ? 0 : -1);
+    const int xm = xh > 0 ? xh - 1 : (px ? Lxh - 1 : -1);
+    const int xp = xh < Lxh - 1 ? xh + 1 : (px ? 0 : -1);
+    const int zm = z > 0 ? z - 1 : (pz ? Lz - 1 : -1);
+    const int zp = z < Lz - 1 ? z + 1 : (pz ? 0 : -1);
+    hx = 0;
+    hy = 0;
+    hz = 0;
+    auto add = [&](int valid, uint32_t j) {
+        if (valid) {
+            hx += gx[oth + j];
+            hy += gy[oth + j];
+            hz += gz[oth + j];
+        }
+    };
+    add(zm >= 0, (uint32_t)(zm * Ly + y) * Lxh + xh);
+    add(ym >= 0, (uint32_t)(z * Ly + ym) * Lxh + xh);
+    const int xl = p ? xh : xm; // x-1
+    const int xr = p ? xp : xh; // x+1
+    const uint32_t row = (uint32_t)(z * Ly + y) * Lxh;
+    add(xl >= 0, row + xl);
+    add(xr >= 0, row + xr);
+    add(yp >= 0, (uint32_t)(z * Ly + yp) * Lxh + xh);
+    add(zp >= 0, (uint32_t)(zp * Ly + y) * Lxh + xh);
+}
+
 template <typename T, bool MEASURE, int MODE>
 __device__ __forceinline__ void sc_tile_body(const PassLaunch &P, int colour, uint32_t item,
                                              uint32_t t)
@@ -259,36 +295,12 @@ __device__ __forceinline__ void sc_tile_body(const PassLaunch &P, int colour, ui
 
     double acc[Q_N] = {0, 0, 0, 0, 0, 0};
     if (active) {
-        const int ym = y > 0 ? y - 1 : (py ? Ly - 1 : -1);
-        const int yp = y < Ly - 1 ? y + 1 : (py ? 0 : -1);
-        const int xm = xh > 0 ? xh - 1 : (px ? Lxh - 1 : -1);
-        const int xp = xh < Lxh - 1 ? xh + 1 : (px ? 0 : -1);
         const int z1 = min(w.z0 + P.tile.zc, Lz);
         for (int z = w.z0; z < z1; ++z) {
             const int p = (colour + y + z) & 1;
-            const int zm = z > 0 ? z - 1 : (pz ? Lz - 1 : -1);
-            const int zp = z < Lz - 1 ? z + 1 : (pz ? 0 : -1);
             const uint32_t i = (uint32_t)(z * Ly + y) * Lxh + xh;
-            T hx = 0, hy = 0, hz = 0;
-            auto add = [&](int valid, uint32_t j) {
-                if (valid) {
-                    hx += gx[oth + j];
-                    hy += gy[oth + j];
-                    hz += gz[oth + j];
-                }
-            };
-            // fixed order: -z, -y, -x, +x, +y, +z
-            add(zm >= 0, (uint32_t)(zm * Ly + y) * Lxh + xh);
-            add(ym >= 0, (uint32_t)(z * Ly + ym) * Lxh + xh);
-            {
-                const int xl = p ? xh : xm; // x-1
-                const int xr = p ? xp : xh; // x+1
-                const uint32_t row = (uint32_t)(z * Ly + y) * Lxh;
-                add(xl >= 0, row + xl);
-                add(xr >= 0, row + xr);
-            }
-            add(yp >= 0, (uint32_t)(z * Ly + yp) * Lxh + xh);
-            add(zp >= 0, (uint32_t)(zp * Ly + y) * Lxh + xh);
+            T hx, hy, hz;
+            sc_site_field<T>(gx, gy, gz, oth, Lxh, Ly, Lz, px, py, pz, xh, y, z, p, hx, hy, hz);
             hx *= J;
             hy *= J;
             hz *= J;
@@ -736,6 +748,65 @@ __device__ __forceinline__ void sc_band_body(const PassLaunch &P, int colour, ui
 // basis for fcc, 8 for bcc.  Unoccupied sites hold zero, so the field sum is
 // branch-free inside the box.
 // ---------------------------------------------------------------------------
+// Field at basis site B of cell (x, y, z) (J not applied): hx.. over all
+// neighbours, lx_.. over the neighbours of lower colour (basis index < B).
+// Other basis sites b2 ascending; per b2 the 2 to 8 candidate cells in the
+// fixed (iz, iy, ix) order, summed first, then added.  P is a global or an
+// LDS pointer; plane = cells per basis plane.
+template <int KIND, int B, typename T, typename P>
+__device__ __forceinline__ void basis_site_field(P gx, P gy, P gz, uint32_t plane, int Lx, int Ly,
+                                                 int Lz, bool pxm, bool pym, bool pzm, int x,
+                                                 int y, int z, T &hx, T &hy, T &hz, T &lx_,
+                                                 T &ly_, T &lz_)
+{
+    constexpr int NB = basis_count(KIND);
+    constexpr int bx = basis2(KIND, B, 0), by = basis2(KIND, B, 1), bz = basis2(KIND, B, 2);
+    hx = 0;
+    hy = 0;
+    hz = 0;
+    lx_ = 0;
+    ly_ = 0;
+    lz_ = 0;
+#pragma unroll
+    for (int b2 = 0; b2 < NB; ++b2) {
+        if (b2 == B) continue;
+        const int dx = basis2(KIND, b2, 0) - bx;
+        const int dy = basis2(KIND, b2, 1) - by;
+        const int dz = basis2(KIND, b2, 2) - bz;
+        const int nox = dx ? 2 : 1, noy = dy ? 2 : 1, noz = dz ? 2 : 1;
+        T ax = 0, ay = 0, az = 0;
+#pragma unroll
+        for (int iz = 0; iz < noz; ++iz)
+#pragma unroll
+            for (int iy = 0; iy < noy; ++iy)
+#pragma unroll
+                for (int ix = 0; ix < nox; ++ix) {
+                    int cx = x - ix * dx, cy = y - iy * dy, cz = z - iz * dz;
+                    bool ok = true;
+                    if (cx < 0) { cx += Lx; ok &= pxm; }
+                    if (cx >= Lx) { cx -= Lx; ok &= pxm; }
+                    if (cy < 0) { cy += Ly; ok &= pym; }
+                    if (cy >= Ly) { cy -= Ly; ok &= pym; }
+                    if (cz < 0) { cz += Lz; ok &= pzm; }
+                    if (cz >= Lz) { cz -= Lz; ok &= pzm; }
+                    if (ok) {
+                        const uint32_t j = (uint32_t)b2 * plane + (uint32_t)(cz * Ly + cy) * Lx + cx;
+                        ax += gx[j];
+                        ay += gy[j];
+                        az += gz[j];
+                    }
+                }
+        hx += ax;
+        hy += ay;
+        hz += az;
+        if (b2 < B) {
+            lx_ += ax;
+            ly_ += ay;
+            lz_ += az;
+        }
+    }
+}
+
 template <int KIND, int B, typename T, bool MEASURE, int MODE>
 __device__ __forceinline__ void basis_body(const PassLaunch &P, uint32_t item, uint32_t t)
 {
@@ -760,47 +831,9 @@ __device__ __forceinline__ void basis_body(const PassLaunch &P, uint32_t item, u
         for (int z = w.z0; z < z1; ++z) {
             if (!occupied(R, x, y, z, bx, by, bz)) continue;
             const uint32_t cell = (uint32_t)(z * Ly + y) * Lx + x;
-            T hx = 0, hy = 0, hz = 0;    // all neighbours
-            T lx_ = 0, ly_ = 0, lz_ = 0; // neighbours of lower colour (final)
-#pragma unroll
-            for (int b2 = 0; b2 < NB; ++b2) {
-                if (b2 == B) continue;
-                const int dx = basis2(KIND, b2, 0) - bx;
-                const int dy = basis2(KIND, b2, 1) - by;
-                const int dz = basis2(KIND, b2, 2) - bz;
-                const int nox = dx ? 2 : 1, noy = dy ? 2 : 1, noz = dz ? 2 : 1;
-                T ax = 0, ay = 0, az = 0;
-#pragma unroll
-                for (int iz = 0; iz < noz; ++iz)
-#pragma unroll
-                    for (int iy = 0; iy < noy; ++iy)
-#pragma unroll
-                        for (int ix = 0; ix < nox; ++ix) {
-                            int cx = x - ix * dx, cy = y - iy * dy, cz = z - iz * dz;
-                            bool ok = true;
-                            if (cx < 0) { cx += Lx; ok &= pxm; }
-                            if (cx >= Lx) { cx -= Lx; ok &= pxm; }
-                            if (cy < 0) { cy += Ly; ok &= pym; }
-                            if (cy >= Ly) { cy -= Ly; ok &= pym; }
-                            if (cz < 0) { cz += Lz; ok &= pzm; }
-                            if (cz >= Lz) { cz -= Lz; ok &= pzm; }
-                            if (ok) {
-                                const uint32_t j = (uint32_t)b2 * plane +
-                                                   (uint32_t)(cz * Ly + cy) * Lx + cx;
-                                ax += gx[j];
-                                ay += gy[j];
-                                az += gz[j];
-                            }
-                        }
-                hx += ax;
-                hy += ay;
-                hz += az;
-                if (b2 < B) {
-                    lx_ += ax;
-                    ly_ += ay;
-                    lz_ += az;
-                }
-            }
+            T hx, hy, hz, lx_, ly_, lz_;
+            basis_site_field<KIND, B, T>(gx, gy, gz, plane, Lx, Ly, Lz, pxm, pym, pzm, x, y, z,
+                                         hx, hy, hz, lx_, ly_, lz_);
             hx *= J;
             hy *= J;
             hz *= J;
@@ -988,6 +1021,159 @@ __global__ void __launch_bounds__(256) k_persistent(PassLaunch P, PersistLaunch 
             }
         }
         __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Small lattices held in LDS: one workgroup per replica copies the replica's
+// three component planes into LDS, runs n whole sweeps there (colour passes
+// separated by workgroup barriers, so no other workgroup is involved and no
+// device-scope synchronisation is needed), optionally writes one record per
+// sweep, and copies the planes back.  The site updates are the same
+// arithmetic, in the same order, as the pass kernels, so the chain is
+// bitwise the same.
+// ---------------------------------------------------------------------------
+template <typename T> using lptr = __attribute__((address_space(3))) T *;
+
+// Block reduction for up to 1024 threads into out[0..Q_N) (LDS); fixed order.
+__device__ __forceinline__ void block_reduce_1024(double (&a)[Q_N], double *out)
+{
+    __shared__ double red[16][Q_N];
+#pragma unroll
+    for (int q = 0; q < Q_N; ++q) {
+        double v = a[q];
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+        a[q] = v;
+    }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int n_waves = (blockDim.x + 63) >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < Q_N; ++q) red[wave][q] = a[q];
+    }
+    __syncthreads();
+    if (threadIdx.x < Q_N) {
+        double v = 0.0;
+        for (int w = 0; w < n_waves; ++w) v += red[w][threadIdx.x];
+        out[threadIdx.x] = v;
+    }
+    __syncthreads();
+}
+
+template <typename T, int KIND, bool MEASURE>
+__global__ void __launch_bounds__(1024) k_lds_sweeps(LdsLaunch L)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+    __shared__ double s_rec[Q_N];
+    constexpr int NB = basis_count(KIND);
+    constexpr int NC = KIND == SC ? 2 : NB;
+    const RepDev &R = L.reps_dev[blockIdx.x];
+    const int Lx = R.Lx, Ly = R.Ly, Lz = R.Lz, Lxh = R.Lxh;
+    const uint32_t n_box = R.n_box, plane = R.plane, rid = R.rid;
+    const gptr<T> gx = as_global<T>(R.sx), gy = as_global<T>(R.sy), gz = as_global<T>(R.sz);
+    const T J = (T)R.J, K = (T)R.K, ex = (T)R.e[0], ey = (T)R.e[1], ez = (T)R.e[2];
+    const T beta = (T)R.beta;
+    const bool greedy = R.greedy != 0;
+    const bool px = R.pmask & 1u, py = R.pmask & 2u, pz = R.pmask & 4u;
+    const double Kd = R.K;
+    const uint32_t t0 = *L.tctr_dev;
+    const lptr<T> lx = (lptr<T>)(lptr<unsigned char>)lds_raw;
+    const lptr<T> ly = lx + n_box, lz = ly + n_box;
+    for (uint32_t i = threadIdx.x; i < n_box; i += blockDim.x) {
+        lx[i] = gx[i];
+        ly[i] = gy[i];
+        lz[i] = gz[i];
+    }
+    __syncthreads();
+    for (uint32_t sw = 0; sw < L.n_sweeps; ++sw) {
+        const uint32_t t = t0 + sw;
+        double acc[Q_N] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            for (uint32_t k = threadIdx.x; k < plane; k += blockDim.x) {
+                T hx, hy, hz, sh_x, sh_y, sh_z;
+                uint32_t i, s;
+                if constexpr (KIND == SC) {
+                    const int xh = (int)(k % (uint32_t)Lxh);
+                    const uint32_t row = k / (uint32_t)Lxh;
+                    const int y = (int)(row % (uint32_t)Ly), z = (int)(row / (uint32_t)Ly);
+                    const int p = (c + y + z) & 1;
+                    sc_site_field<T>(lx, ly, lz, c ? 0u : plane, Lxh, Ly, Lz, px, py, pz, xh, y,
+                                     z, p, hx, hy, hz);
+                    i = (c ? plane : 0u) + k;
+                    s = row * (uint32_t)Lx + 2u * (uint32_t)xh + (uint32_t)p;
+                } else {
+                    const int x = (int)(k % (uint32_t)Lx);
+                    const uint32_t r2 = k / (uint32_t)Lx;
+                    const int y = (int)(r2 % (uint32_t)Ly), z = (int)(r2 / (uint32_t)Ly);
+                    if (!occupied(R, x, y, z, basis2(KIND, c, 0), basis2(KIND, c, 1),
+                                  basis2(KIND, c, 2)))
+                        continue;
+                    switch (c) {
+                    case 0:
+                        basis_site_field<KIND, 0, T>(lx, ly, lz, plane, Lx, Ly, Lz, px, py, pz, x,
+                                                     y, z, hx, hy, hz, sh_x, sh_y, sh_z);
+                        break;
+                    case 1:
+                        basis_site_field<KIND, 1, T>(lx, ly, lz, plane, Lx, Ly, Lz, px, py, pz, x,
+                                                     y, z, hx, hy, hz, sh_x, sh_y, sh_z);
+                        break;
+                    case 2:
+                        basis_site_field<KIND, (NB > 2 ? 2 : 0), T>(lx, ly, lz, plane, Lx, Ly, Lz,
+                                                                    px, py, pz, x, y, z, hx, hy,
+                                                                    hz, sh_x, sh_y, sh_z);
+                        break;
+                    default:
+                        basis_site_field<KIND, (NB > 3 ? 3 : 0), T>(lx, ly, lz, plane, Lx, Ly, Lz,
+                                                                    px, py, pz, x, y, z, hx, hy,
+                                                                    hz, sh_x, sh_y, sh_z);
+                        break;
+                    }
+                    i = (uint32_t)c * plane + k;
+                    s = k * NB + (uint32_t)c;
+                }
+                hx *= J;
+                hy *= J;
+                hz *= J;
+                T sx = lx[i], sy = ly[i], sz = lz[i];
+                T dH;
+                const bool a = metropolis<T>(sx, sy, sz, hx, hy, hz, s, rid, t, L.seed_lo,
+                                             L.seed_hi, K, ex, ey, ez, beta, greedy, dH);
+                if (a) {
+                    lx[i] = sx;
+                    ly[i] = sy;
+                    lz[i] = sz;
+                }
+                if (MEASURE) {
+                    T sh;
+                    if constexpr (KIND == SC) sh = c == 1 ? sx * hx + sy * hy + sz * hz : T(0);
+                    else sh = J * (sx * sh_x + sy * sh_y + sz * sh_z);
+                    accumulate<T>(acc, sx, sy, sz, ex, ey, ez, sh, a);
+                }
+            }
+            __syncthreads();
+        }
+        if (MEASURE) {
+            block_reduce_1024(acc, s_rec);
+            if (threadIdx.x == 0) {
+                double *rec = L.records +
+                              ((size_t)((L.slot0 + sw) % L.ring) * L.n_reps + blockIdx.x) * NR;
+                rec[R_MX] = s_rec[Q_MX];
+                rec[R_MY] = s_rec[Q_MY];
+                rec[R_MZ] = s_rec[Q_MZ];
+                rec[R_EEX] = -s_rec[Q_SH];
+                rec[R_EAN] = -Kd * s_rec[Q_PE2];
+                rec[R_NACC] = s_rec[Q_NACC];
+                rec[R_SWEEP] = (double)t + 1.0;
+                rec[7] = 0.0;
+            }
+        }
+    }
+    for (uint32_t i = threadIdx.x; i < n_box; i += blockDim.x) {
+        gx[i] = lx[i];
+        gy[i] = ly[i];
+        gz[i] = lz[i];
     }
 }
 
@@ -1325,6 +1511,57 @@ static hipError_t persist_dispatch(int kind, const PassLaunch &p, const PersistL
         return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <typename T, bool MEASURE>
+static hipError_t lds_dispatch(int kind, const LdsLaunch &L, int threads, hipStream_t st)
+{
+    const dim3 g(L.n_reps), b(threads);
+    if (kind == SC)
+        hipLaunchKernelGGL((k_lds_sweeps<T, SC, MEASURE>), g, b, L.lds_bytes, st, L);
+    else if (kind == BCC)
+        hipLaunchKernelGGL((k_lds_sweeps<T, BCC, MEASURE>), g, b, L.lds_bytes, st, L);
+    else
+        hipLaunchKernelGGL((k_lds_sweeps<T, FCC, MEASURE>), g, b, L.lds_bytes, st, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_lds(int kind, bool f64, bool measure, const LdsLaunch &L, int threads,
+                      hipStream_t st)
+{
+    if (L.n_reps == 0 || L.n_sweeps == 0) return hipSuccess;
+    if (threads < 64 || threads > 1024 || threads % 64) return hipErrorInvalidValue;
+    if (f64)
+        return measure ? lds_dispatch<double, true>(kind, L, threads, st)
+                       : lds_dispatch<double, false>(kind, L, threads, st);
+    return measure ? lds_dispatch<float, true>(kind, L, threads, st)
+                   : lds_dispatch<float, false>(kind, L, threads, st);
+}
+
+template <typename T> static hipError_t lds_allow_kind(int kind, uint32_t bytes)
+{
+    const void *f[2];
+    if (kind == SC) {
+        f[0] = (const void *)&k_lds_sweeps<T, SC, false>;
+        f[1] = (const void *)&k_lds_sweeps<T, SC, true>;
+    } else if (kind == BCC) {
+        f[0] = (const void *)&k_lds_sweeps<T, BCC, false>;
+        f[1] = (const void *)&k_lds_sweeps<T, BCC, true>;
+    } else {
+        f[0] = (const void *)&k_lds_sweeps<T, FCC, false>;
+        f[1] = (const void *)&k_lds_sweeps<T, FCC, true>;
+    }
+    for (const void *fn : f) {
+        const hipError_t e =
+            hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t lds_allow(int kind, bool f64, uint32_t bytes)
+{
+    return f64 ? lds_allow_kind<double>(kind, bytes) : lds_allow_kind<float>(kind, bytes);
 }
 
 hipError_t launch_persistent(int kind, bool f64, bool measure, const PassLaunch &p,

@@ -63,6 +63,22 @@ inline uint32_t persist_state_words(int n_reps) { return 4u + 2u * (uint32_t)n_r
 hipError_t launch_persistent(int kind, bool f64, bool measure, const PassLaunch &p,
                              const PersistLaunch &a, hipStream_t st);
 
+// Whole sweeps of small replicas in LDS: one workgroup per replica (every
+// replica's three planes, lds_bytes in all, fit one workgroup's LDS).
+struct LdsLaunch {
+    const RepDev *reps_dev;
+    uint32_t n_reps, n_sweeps;
+    const uint32_t *tctr_dev; // sweep counter t of the first sweep
+    uint32_t seed_lo, seed_hi;
+    double *records;          // ring [ring][n_reps][NR] (measured launches)
+    uint32_t ring, slot0;
+    uint32_t lds_bytes;       // dynamic LDS per workgroup
+};
+hipError_t launch_lds(int kind, bool f64, bool measure, const LdsLaunch &L, int threads,
+                      hipStream_t st);
+// Allow the LDS kernels of one lattice kind and precision `bytes` of dynamic LDS.
+hipError_t lds_allow(int kind, bool f64, uint32_t bytes);
+
 hipError_t launch_advance(uint32_t *tctr_dev, uint32_t n, hipStream_t st);
 hipError_t launch_set_counter(uint32_t *tctr_dev, uint32_t v, hipStream_t st);
 hipError_t launch_fill_zero(double *p, uint64_t n, hipStream_t st);

@@ -49,6 +49,7 @@ enum : int32_t {
     KERNEL_TILE = 0,  // one site per thread per plane, tx x ty threads (any lattice kind)
     KERNEL_STRIP = 1, // sc only: tx threads along a row (multiple of 64), ty rows per thread
     KERNEL_BAND = 2,  // sc only: tx threads over (band, column) positions, ty (even) rows per band
+    KERNEL_LDS = 3,   // whole sweeps in LDS, one workgroup of tx threads per replica (small lattices)
 };
 
 // Tile of one workgroup: tx row columns x ty rows x zc planes, and the kernel

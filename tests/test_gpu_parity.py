@@ -234,7 +234,9 @@ def test_tile_shape_and_batching_are_bitwise(M, prec):
 MEASURE_CASES = [("sc", (64, 40, 30), None), ("sc", (64, 40, 30), (0, 16, 16, 1)),
                  ("sc", (64, 40, 30), (1, 64, 1, 1)), ("sc", (64, 40, 30), (1, 64, 4, 2)),
                  ("sc", (64, 40, 30), (2, 256, 4, 1)), ("sc", (150, 14, 12), (1, 128, 2, 3)),
-                 ("bcc", (9, 8, 7), None), ("fcc", (7, 6, 5), None)]
+                 ("bcc", (9, 8, 7), None), ("fcc", (7, 6, 5), None),
+                 ("bcc", (9, 8, 7), (0, 8, 8, 2)), ("fcc", (7, 6, 5), (0, 8, 8, 1)),
+                 ("sc", (16, 12, 10), (3, 256, 1, 1))]
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
@@ -269,6 +271,63 @@ def test_measuring_does_not_change_the_chain(M, case, prec):
         with pytest.raises(M.MCError) as ei:
             s.sweep(1, persistent=True)
         assert ei.value.status == -2
+
+
+LDS_CASES = [("sc", (16, 16, 16), 7, 0.0, "f64"), ("sc", (16, 16, 16), 7, 0.0, "f32"),
+             ("sc", (12, 10, 8), 5, 0.0, "f32"), ("bcc", (8, 8, 8), 7, 0.0, "f64"),
+             ("bcc", (7, 9, 5), 3, 0.0, "f32"), ("fcc", (6, 6, 6), 0, 2.6, "f32"),
+             ("fcc", (7, 6, 5), 7, 0.0, "f64")]
+
+
+@pytest.mark.parametrize("case", range(len(LDS_CASES)))
+def test_lds_kernel_matches_pass_kernels(M, case):
+    """Lattices whose state fits one workgroup's LDS run whole sweeps there by
+    default; spins equal the pass kernels' bitwise, records agree."""
+    kind, L, mask, R, prec = LDS_CASES[case]
+    rep = M.Replica(kind=kind, L=L, periodic_mask=mask, sphere_radius=R, K=0.2, T=1.1,
+                    e=(0.3, 0.0, 0.95), replica_id=3)
+    a = M.Simulation([rep, M.Replica(kind=kind, L=L, periodic_mask=mask, sphere_radius=R,
+                                     K=0.05, T=2.0, replica_id=4)], precision=prec, seed=21)
+    b = M.Simulation([rep, M.Replica(kind=kind, L=L, periodic_mask=mask, sphere_radius=R,
+                                     K=0.05, T=2.0, replica_id=4)], precision=prec, seed=21)
+    assert a.get_tile()[0] == 3
+    b.set_tile(16, 16, 1, kernel=0)
+    ra = a.run_schedule([[1.1, 2.0], [0.9, 1.5]], n_equil=3, n_meas=6)
+    rb = b.run_schedule([[1.1, 2.0], [0.9, 1.5]], n_equil=3, n_meas=6)
+    assert np.array_equal(ra[..., 0:2], rb[..., 0:2])  # sweep, accepted
+    assert np.max(np.abs(ra[..., 2:5] - rb[..., 2:5])) <= 1e-12
+    assert np.max(np.abs(ra[..., 6] - rb[..., 6]) / np.abs(rb[..., 6])) <= 1e-10
+    a.sweep(5, persistent=True)
+    b.sweep(5)
+    a.set_tile(64, 1, 1, kernel=3)
+    a.sweep(2, measure=True)
+    b.sweep(2, measure=True)
+    for r in range(2):
+        for x, y in zip(natural(a, r), natural(b, r)):
+            assert np.array_equal(x, y)
+        oa, ob = a.observables()[r], b.observables()[r]
+        assert oa["n_accepted"] == ob["n_accepted"] and oa["sweep"] == ob["sweep"]
+    # single passes still run (on the pass kernel)
+    st = a.measure_state()
+    assert st[0]["n_sites"] == a.n_occ[0]
+
+
+def test_lds_kernel_limits(M):
+    big = M.Simulation([M.Replica(kind="sc", L=(64, 64, 64))], precision="f32")
+    assert big.get_tile()[0] != 3
+    with pytest.raises(M.MCError) as ei:
+        big.set_tile(256, 1, 1, kernel=3)
+    assert ei.value.status == -2
+    small = M.Simulation([M.Replica(kind="sc", L=(8, 8, 8))], precision="f32")
+    assert small.get_tile()[0] == 3
+    for bad in (32, 100, 2048):
+        with pytest.raises(M.MCError) as ei:
+            small.set_tile(bad, 1, 1, kernel=3)
+        assert ei.value.status == -1
+    pm, tot = small.sweep_timed(4, measure=True)
+    assert tot > 0 and pm > 0
+    o = small.observables()[0]
+    assert o["sweep"] == 4
 
 
 def test_strip_kernel_rejects_other_lattices(M):
@@ -513,11 +572,15 @@ def _batch(M, kind="sc"):
                       replica_id=r) for r, L in enumerate(Ls)]
 
 
-@pytest.mark.parametrize("kind,prec", [("sc", "f32"), ("sc", "f64"), ("fcc", "f32")])
+@pytest.mark.parametrize("kind,prec", [("sc", "f32"), ("sc", "f64"), ("fcc", "f32"),
+                                       ("fcc", "f64")])
 def test_persistent_matches_eager(M, kind, prec):
     reps = _batch(M, kind)
     a = M.Simulation(reps, precision=prec, seed=12)
     b = M.Simulation(reps, precision=prec, seed=12)
+    if kind == "fcc":  # small enough for the LDS kernel: pin the pass kernel
+        for s in (a, b):
+            s.set_tile(16, 16, 1, kernel=0)
     for rnd in range(3):
         a.sweep(4, measure=True, persistent=True)
         b.sweep(4, measure=True)
