@@ -24,6 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0           # MI355X HBM3E
+KERNEL_NAMES = ["tile", "strip", "band", "lds", "pair"]  # mc_set_tile kernel ids
 BYTES_PER_UPDATE = {"f32": 36, "f64": 72}  # two-pass colour-packed: read own + other, write own
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sc_pass_f32_L464_traffic.json")
 # sources whose change invalidates the committed counter readings
@@ -95,7 +96,7 @@ def time_precision(M, W, prec, steps, warmup, tile=None):
         "absM": obs["absM"],
         "e_per_spin": obs["E"] / n,
         "n_spins": n,
-        "tile": {"kernel": ["tile", "strip", "band"][tile[0]], "tx": tile[1], "ty": tile[2],
+        "tile": {"kernel": KERNEL_NAMES[tile[0]], "tx": tile[1], "ty": tile[2],
                  "zc": tile[3]},
     }
     sim.close()
@@ -326,8 +327,8 @@ def main():
     if rank == 0 and not args.no_cpu_baseline:
         cpu = cpu_baseline(W, args.cpu_sweeps)
     t32 = r32["tile"]
-    traffic = measured_traffic([["tile", "strip", "band"].index(t32["kernel"]), t32["tx"],
-                                t32["ty"], t32["zc"]])
+    traffic = measured_traffic([KERNEL_NAMES.index(t32["kernel"]), t32["tx"], t32["ty"],
+                                t32["zc"]])
     copy = copy_probe(emit=False)
     log(f"[bench] device copy {copy['GBps']:.0f} GB/s")
     ach = r32["achieved_GBps"]

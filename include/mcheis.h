@@ -60,7 +60,8 @@ typedef enum { MC_INIT_RANDOM = 0, MC_INIT_ALIGNED = 1, MC_INIT_USER = 2 } mc_in
                          /* workgroups, each replica advancing as soon as its previous */
                          /* pass is complete (no grid-wide barrier).  Results are      */
                          /* bitwise identical to the default launches.  Strip tiles  */
-                         /* of 1 or 8 rows have no persistent kernel: MC_E_UNSUPPORTED.*/
+                         /* of 1 or 8 rows and pair tiles of 4 rows have no          */
+                         /* persistent kernel: MC_E_UNSUPPORTED.                      */
 
 /* One replica: lattice geometry and model parameters (Eq. (1)).
  *  kind          sc / bcc / fcc conventional cubic cells.
@@ -226,8 +227,9 @@ mc_status mc_set_sweep(mc_sim *h, uint64_t t);
  *  kernel 1 (sc only): tx threads along the row (64, 128, 192 or 256), each
  *    holding ty consecutive rows (1, 2, 4 or 8), with the other colour kept in
  *    registers across planes;
- *  kernel 2 (sc only, default): as kernel 1, but rows grouped in bands of ty
- *    rows (2 or 4) and the (band, column) positions dealt to the tx threads
+ *  kernel 2 (sc only; the default for short or odd rows): as kernel 1, but
+ *    rows grouped in bands of ty rows (2 or 4) and the (band, column)
+ *    positions dealt to the tx threads
  *    contiguously, so no lane idles whatever the row length; a tile is tx
  *    positions x zc planes;
  *  kernel 3 (any lattice whose three component planes fit one workgroup's
@@ -235,7 +237,12 @@ mc_status mc_set_sweep(mc_sim *h, uint64_t t);
  *    (64 .. 1024, multiple of 64) per replica, colour passes separated by
  *    workgroup barriers; ty and zc are ignored.  Single passes (mc_debug_pass,
  *    mc_measure_state) keep using the previous pass kernel.  A replica too
- *    large gives MC_E_UNSUPPORTED.
+ *    large gives MC_E_UNSUPPORTED;
+ *  kernel 4 (sc only, every row of an even number of packed columns; the
+ *    default when every row also has at least 96 packed columns): as
+ *    kernel 1 with two adjacent columns per thread, read and written as one
+ *    8-byte (FP32) or 16-byte (FP64) access; tx threads (64 .. 256) cover 2 tx
+ *    columns, ty rows per thread (1, 2 or 4; persistent sweeps: 1 or 2).
  * The spins do not depend on the choice (only the FP64 summation order of the
  * observables does).  A shape whose work list does not fit the handle's
  * scratch gives MC_E_BUFFER.  Choosing kernel 0-2 discards the record of the

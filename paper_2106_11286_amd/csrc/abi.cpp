@@ -138,7 +138,8 @@ uint64_t xy_tiles(const mc_replica_desc &d, const Tile &t)
         const uint64_t F = (uint64_t)((d.Ly + t.ty - 1) / t.ty) * row_len(d);
         return (F + t.tx - 1) / t.tx;
     }
-    return (uint64_t)((row_len(d) + t.tx - 1) / t.tx) * ((d.Ly + t.ty - 1) / t.ty);
+    const int wx = t.kernel == KERNEL_PAIR ? 2 * t.tx : t.tx; // packed columns per tile
+    return (uint64_t)((row_len(d) + wx - 1) / wx) * ((d.Ly + t.ty - 1) / t.ty);
 }
 
 // Planes per workgroup so that a pass has about kTargetItems workgroups.
@@ -164,7 +165,15 @@ Tile default_tile(const mc_replica_desc *reps, int n)
     Tile t;
     bool fits = true; // the strip kernel addresses each component array with 32-bit offsets
     for (int r = 0; r < n; ++r) fits &= box_sites(reps[r]) * sizeof(double) <= 0xFFFFFFFFull;
-    if (reps[0].kind == MC_SC && fits) {
+    bool even = true; // every row holds an even number of packed columns
+    for (int r = 0; r < n; ++r) even &= row_len(reps[r]) % 2 == 0;
+    if (reps[0].kind == MC_SC && fits && even && Wmin >= 96) {
+        // long rows: two columns per thread, 2 rows per thread, whole rows
+        // (up to 512 columns) per workgroup
+        t.kernel = KERNEL_PAIR;
+        t.tx = std::min(256, ((W + 1) / 2 + 63) / 64 * 64);
+        t.ty = 2;
+    } else if (reps[0].kind == MC_SC && fits) {
         // bands of 2 rows, (band, column) positions dealt to 256 threads
         t.kernel = KERNEL_BAND;
         t.tx = 256;
@@ -188,6 +197,14 @@ mc_status check_tile(const Tile &t, int kind, uint64_t max_component_bytes)
             return fail(MC_E_ARG, "band tile: tx must be 64, 128, 192 or 256 (got %d)", t.tx);
         if (t.ty != 2 && t.ty != 4)
             return fail(MC_E_ARG, "band tile: ty (rows per band) must be 2 or 4");
+    } else if (t.kernel == KERNEL_PAIR) {
+        if (kind != MC_SC) return fail(MC_E_ARG, "the pair kernel is for simple cubic lattices");
+        if (max_component_bytes > 0xFFFFFFFFull)
+            return fail(MC_E_UNSUPPORTED, "pair kernel: a spin component array exceeds 4 GiB");
+        if (t.tx < 64 || t.tx > 256 || t.tx % 64)
+            return fail(MC_E_ARG, "pair tile: tx must be 64, 128, 192 or 256 (got %d)", t.tx);
+        if (t.ty != 1 && t.ty != 2 && t.ty != 4)
+            return fail(MC_E_ARG, "pair tile: ty (rows per thread) must be 1, 2 or 4");
     } else if (t.kernel == KERNEL_STRIP) {
         if (kind != MC_SC) return fail(MC_E_ARG, "the strip kernel is for simple cubic lattices");
         if (max_component_bytes > 0xFFFFFFFFull)
@@ -246,14 +263,15 @@ void make_work(const mc_replica_desc *reps, int n, const Tile &t, std::vector<Wo
             end[r] = (uint32_t)work.size();
             continue;
         }
+        const int wx = t.kernel == KERNEL_PAIR ? 2 * t.tx : t.tx; // packed columns per tile
         for (int z0 = 0; z0 < d.Lz; z0 += t.zc)
-            for (int x0 = 0; x0 < W; x0 += t.tx)
+            for (int x0 = 0; x0 < W; x0 += wx)
                 for (int y0 = 0; y0 < d.Ly; y0 += t.ty) {
                     if (d.sphere_radius > 0.0) {
                         // cells covered, then half-unit site positions relative to the centre
                         const int cx0 = sc ? 2 * x0 : x0;
-                        const int cx1 = sc ? std::min(d.Lx, 2 * (x0 + t.tx)) - 1
-                                           : std::min(d.Lx, x0 + t.tx) - 1;
+                        const int cx1 = sc ? std::min(d.Lx, 2 * (x0 + wx)) - 1
+                                           : std::min(d.Lx, x0 + wx) - 1;
                         const int cy1 = std::min(d.Ly, y0 + t.ty) - 1;
                         const int cz1 = std::min(d.Lz, z0 + t.zc) - 1;
                         const int64_t m = min_sq(2 * cx0 - d.Lx, 2 * cx1 + 1 - d.Lx) +
@@ -446,6 +464,7 @@ mc_status enqueue_sweeps(mc_sim *h, uint32_t n, bool measure, uint32_t slot0)
 // Tile shapes the persistent kernel is instantiated for.
 bool persistent_supported(const Tile &t)
 {
+    if (t.kernel == KERNEL_PAIR) return t.ty == 1 || t.ty == 2;
     return t.kernel != KERNEL_STRIP || t.ty == 2 || t.ty == 4;
 }
 
@@ -458,8 +477,9 @@ mc_status enqueue_persistent(mc_sim *h, uint32_t n, bool measure, uint32_t slot0
 {
     if (h->tile.kernel == KERNEL_LDS) return enqueue_lds(h, n, measure, slot0);
     if (!persistent_supported(h->tile))
-        return fail(MC_E_UNSUPPORTED, "persistent sweeps: no kernel for strips of %d rows "
-                                      "(use 2 or 4, or another kernel)", h->tile.ty);
+        return fail(MC_E_UNSUPPORTED, "persistent sweeps: no kernel for this tile (%d rows "
+                                      "per thread); use strips of 2 or 4 rows, pairs of 1 or "
+                                      "2 rows, or another kernel", h->tile.ty);
     const uint32_t n_items = (uint32_t)h->work.size();
     if ((uint64_t)n * h->n_colours * n_items >= 0xFFFFFFFFull)
         return fail(MC_E_ARG, "persistent launch of %u sweeps exceeds 2^32 work units", n);
@@ -1108,6 +1128,11 @@ mc_status mc_set_tile(mc_sim *h, int32_t kernel, int32_t tx, int32_t ty, int32_t
                                                       (h->prec == MC_F64 ? 8u : 4u));
     mc_status st = check_tile(t, h->kind, max_bytes);
     if (st != MC_OK) return st;
+    if (kernel == KERNEL_PAIR)
+        for (int r = 0; r < h->n_reps; ++r)
+            if (row_len(h->desc[r]) % 2)
+                return fail(MC_E_UNSUPPORTED, "pair kernel: replica %d has an odd number (%d) of "
+                                              "packed columns per row", r, row_len(h->desc[r]));
     std::vector<WorkItem> work;
     std::vector<uint32_t> b, e;
     make_work(h->desc.data(), h->n_reps, t, work, b, e);
@@ -1161,6 +1186,12 @@ std::vector<Tile> tile_candidates(const mc_sim *h)
             if (whole > 64) base.push_back(Tile{KERNEL_STRIP, 64, ry, 1});
         }
         for (int ry : {2, 4}) base.push_back(Tile{KERNEL_BAND, 256, ry, 1});
+        bool even = true;
+        for (const auto &d : h->desc) even &= row_len(d) % 2 == 0;
+        if (even) {
+            const int pairs = std::min(256, ((W + 1) / 2 + 63) / 64 * 64);
+            for (int ry : {1, 2, 4}) base.push_back(Tile{KERNEL_PAIR, pairs, ry, 1});
+        }
     }
     for (int tx : {64, 32, 16, 8}) {
         if (tx > 2 * pow2_at_least(W) && tx > 8) continue;

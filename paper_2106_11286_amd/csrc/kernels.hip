@@ -559,6 +559,243 @@ __device__ __forceinline__ void sc_strip_body(const PassLaunch &P, int colour, u
 }
 
 // ---------------------------------------------------------------------------
+// Pair kernel (simple cubic): the row-strip scheme with two adjacent packed
+// columns per lane, loaded and stored as one 8-byte (FP32) or 16-byte (FP64)
+// buffer access.  Columns 2l and 2l+1 of lane l are each other's in-row
+// neighbours on one side; the column beyond the pair comes from one lane
+// shift per row and component (lane l-1's second column when the row parity
+// is 0, lane l+1's first column when it is 1), or from memory at wave edges
+// and at the periodic wrap.  Rows of an even number of packed columns only
+// (pairs stay aligned).  A tile is 2 tx columns x ty rows per thread x zc
+// planes.
+// ---------------------------------------------------------------------------
+template <typename T> struct Row2 {
+    T xa, ya, za, xb, yb, zb; // components of the pair's columns a = 2l, b = 2l+1
+};
+__device__ __forceinline__ void buf_load2(rsrc_t r, uint32_t voff, uint32_t soff, float &a, float &b)
+{
+    typedef uint32_t v2u __attribute__((ext_vector_type(2)));
+    const v2u v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+    // elements go through scalars first: a bit cast applied directly to a
+    // vector element reads the vector's first element
+    const uint32_t lo = v.x, hi = v.y;
+    a = __uint_as_float(lo);
+    b = __uint_as_float(hi);
+}
+__device__ __forceinline__ void buf_load2(rsrc_t r, uint32_t voff, uint32_t soff, double &a,
+                                          double &b)
+{
+    typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+    const v4u v = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+    a = __hiloint2double((int)v.y, (int)v.x);
+    b = __hiloint2double((int)v.w, (int)v.z);
+}
+__device__ __forceinline__ void buf_store2(float a, float b, rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    typedef uint32_t v2u __attribute__((ext_vector_type(2)));
+    v2u v;
+    v.x = __builtin_bit_cast(uint32_t, a);
+    v.y = __builtin_bit_cast(uint32_t, b);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, soff, 0);
+}
+__device__ __forceinline__ void buf_store2(double a, double b, rsrc_t r, uint32_t voff,
+                                           uint32_t soff)
+{
+    typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+    v4u v;
+    v.x = (uint32_t)__double2loint(a);
+    v.y = (uint32_t)__double2hiint(a);
+    v.z = (uint32_t)__double2loint(b);
+    v.w = (uint32_t)__double2hiint(b);
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, voff, soff, 0);
+}
+
+template <typename T, bool MEASURE, int MODE, int RY>
+__device__ __forceinline__ void sc_pair_body(const PassLaunch &P, int colour, uint32_t item,
+                                             uint32_t t)
+{
+    // every descriptor field is read into registers before the first store, so
+    // the loads stay scalar (memory that the kernel may write cannot be)
+    const WorkItem w = P.work_dev[item];
+    const RepDev &R = P.reps_dev[w.rep];
+    const int Ly = R.Ly, Lz = R.Lz, Lxh = R.Lxh, Lx = R.Lx;
+    void *const base_x = R.sx, *const base_y = R.sy, *const base_z = R.sz;
+    const uint32_t rid = R.rid;
+    const int lane = threadIdx.x & 63;
+    const int xraw = w.x0 + 2 * (int)threadIdx.x;
+    const bool xin = xraw < Lxh && (int)threadIdx.x < P.tile.tx;
+    const int xa = xin ? xraw : Lxh - 2, xb = xa + 1;
+    const uint32_t plane = R.plane;
+    const uint32_t own = colour ? plane : 0u, oth = colour ? 0u : plane;
+    const T J = (T)R.J, K = (T)R.K, ex = (T)R.e[0], ey = (T)R.e[1], ez = (T)R.e[2];
+    const T beta = (T)R.beta;
+    const bool greedy = R.greedy != 0;
+    const bool px = R.pmask & 1u, py = R.pmask & 2u, pz = R.pmask & 4u;
+    const int xl = xa > 0 ? xa - 1 : (px ? Lxh - 1 : -1);  // column left of the pair
+    const int xr = xb < Lxh - 1 ? xb + 1 : (px ? 0 : -1);  // column right of the pair
+    const bool left_mem = lane == 0 || xa == 0;           // xa-1 not held by lane-1
+    const bool right_mem = lane == 63 || xb >= Lxh - 1;   // xb+1 not held by lane+1
+    const uint32_t b_c = (uint32_t)xa * (uint32_t)sizeof(T);
+    const uint32_t b_l = (uint32_t)(xl < 0 ? 0 : xl) * (uint32_t)sizeof(T);
+    const uint32_t b_r = (uint32_t)(xr < 0 ? 0 : xr) * (uint32_t)sizeof(T);
+    const uint32_t row_bytes = (uint32_t)Lxh * (uint32_t)sizeof(T);
+    const PlaneRs<T> q = {plane_rsrc<T>(base_x, 0, R.n_box), plane_rsrc<T>(base_y, 0, R.n_box),
+                          plane_rsrc<T>(base_z, 0, R.n_box)};
+    const uint32_t own_b = own * (uint32_t)sizeof(T), oth_b = oth * (uint32_t)sizeof(T);
+    auto row_off = [&](int y, int z) -> uint32_t {
+        return ((uint32_t)z * (uint32_t)Ly + (uint32_t)y) * row_bytes;
+    };
+    auto load_row = [&](uint32_t soff) -> Row2<T> {
+        Row2<T> v;
+        buf_load2(q.x, b_c, soff, v.xa, v.xb);
+        buf_load2(q.y, b_c, soff, v.ya, v.yb);
+        buf_load2(q.z, b_c, soff, v.za, v.zb);
+        return v;
+    };
+
+    // rows y0-1 .. y0+RY: lattice row index or -1 (open face)
+    int yrow[RY + 2];
+#pragma unroll
+    for (int k = -1; k <= RY; ++k) {
+        int y = w.y0 + k;
+        if (y < 0 || y >= Ly) {
+            if (!py) y = -1;
+            else {
+                while (y < 0) y += Ly;
+                while (y >= Ly) y -= Ly;
+            }
+        }
+        yrow[k + 1] = y;
+    }
+    auto load_rows = [&](int z, Row2<T> *dst) {
+        const bool z_ok = z >= 0;
+        const int zc = z_ok ? z : 0;
+        for (int k = 0; k < RY + 2; ++k) {
+            const int y = yrow[k];
+            dst[k] = load_row(oth_b + row_off(y < 0 ? 0 : y, zc));
+            if (!z_ok || y < 0) dst[k] = Row2<T>{T(0), T(0), T(0), T(0), T(0), T(0)};
+        }
+    };
+    // the in-row neighbour beyond the pair where the lane shift cannot supply
+    // it, loaded one plane ahead
+    auto load_edges = [&](int z, Vec3<T> (&dst)[RY]) {
+#pragma unroll
+        for (int k = 0; k < RY; ++k) {
+            const int yk = w.y0 + k;
+            const int yc = yk < Ly ? yk : Ly - 1;
+            const int p = (colour + yc + z) & 1;
+            const bool need = p ? right_mem : left_mem;
+            const int col = p ? xr : xl;
+            if (need && col >= 0) {
+                const uint32_t soff = oth_b + row_off(yc, z);
+                const uint32_t v = p ? b_r : b_l;
+                dst[k] = {buf_load(q.x, v, soff, T()), buf_load(q.y, v, soff, T()),
+                          buf_load(q.z, v, soff, T())};
+            } else {
+                dst[k] = {T(0), T(0), T(0)};
+            }
+        }
+    };
+
+    const int z0 = w.z0, z1 = min(w.z0 + P.tile.zc, Lz);
+    double acc[Q_N] = {0, 0, 0, 0, 0, 0};
+    uint32_t n_acc = 0;
+    auto site = [&](T &sx, T &sy, T &sz, T hx, T hy, T hz, uint32_t s, bool live,
+                    uint32_t i) -> bool {
+        hx *= J;
+        hy *= J;
+        hz *= J;
+        bool a = false;
+        if (MODE != 1) {
+            T dH;
+            a = metropolis<T>(sx, sy, sz, hx, hy, hz, s, rid, t, P.seed_lo, P.seed_hi, K, ex, ey,
+                              ez, beta, greedy, dH);
+            if (MODE == 2 && live) {
+                ((T *)P.dbg_dh)[i] = dH;
+                P.dbg_acc[i] = a ? 1 : 0;
+            }
+        }
+        if (MEASURE && live) {
+            acc[Q_MX] += (double)sx;
+            acc[Q_MY] += (double)sy;
+            acc[Q_MZ] += (double)sz;
+            const double pe = (double)(sx * ex + sy * ey + sz * ez);
+            acc[Q_PE2] += pe * pe;
+            if (colour == 1) acc[Q_SH] += (double)(sx * hx + sy * hy + sz * hz);
+            n_acc += a ? 1u : 0u;
+        }
+        return a;
+    };
+    auto step = [&](const Row2<T> (&pm)[RY + 2], const Row2<T> (&pc)[RY + 2],
+                    Row2<T> (&pn)[RY + 2], const Vec3<T> (&ec)[RY], Vec3<T> (&en)[RY], int z) {
+        const int zn = z < Lz - 1 ? z + 1 : (pz ? 0 : -1);
+        load_rows(zn, pn);
+        if (z + 1 < z1) load_edges(zn, en);
+#pragma unroll
+        for (int k = 0; k < RY; ++k) {
+            const int yk = w.y0 + k;
+            const bool row_in = yk < Ly;
+            const int yc = row_in ? yk : Ly - 1;
+            const int p = (colour + yc + z) & 1; // uniform over the workgroup
+            const uint32_t s_own = own_b + row_off(yc, z);
+            Row2<T> me;
+            buf_load2(q.x, b_c, s_own, me.xa, me.xb);
+            buf_load2(q.y, b_c, s_own, me.ya, me.yb);
+            buf_load2(q.z, b_c, s_own, me.za, me.zb);
+            const Row2<T> c = pc[k + 1];
+            // the other colour's column beyond the pair
+            Vec3<T> nb;
+            if (p == 0)
+                nb = {from_lower_lane(c.xb), from_lower_lane(c.yb), from_lower_lane(c.zb)};
+            else
+                nb = {from_upper_lane(c.xa), from_upper_lane(c.ya), from_upper_lane(c.za)};
+            if (p ? right_mem : left_mem) nb = ec[k];
+            // in-row neighbours (x-1, x+1) of column a and of column b
+            const T lax = p ? c.xa : nb.x, lay = p ? c.ya : nb.y, laz = p ? c.za : nb.z;
+            const T hax = p ? c.xb : c.xa, hay = p ? c.yb : c.ya, haz = p ? c.zb : c.za;
+            const T lbx = p ? c.xb : c.xa, lby = p ? c.yb : c.ya, lbz = p ? c.zb : c.za;
+            const T hbx = p ? nb.x : c.xb, hby = p ? nb.y : c.yb, hbz = p ? nb.z : c.zb;
+            // fixed order: -z, -y, -x, +x, +y, +z
+            const T hxa = pm[k + 1].xa + pc[k].xa + lax + hax + pc[k + 2].xa + pn[k + 1].xa;
+            const T hya = pm[k + 1].ya + pc[k].ya + lay + hay + pc[k + 2].ya + pn[k + 1].ya;
+            const T hza = pm[k + 1].za + pc[k].za + laz + haz + pc[k + 2].za + pn[k + 1].za;
+            const T hxb = pm[k + 1].xb + pc[k].xb + lbx + hbx + pc[k + 2].xb + pn[k + 1].xb;
+            const T hyb = pm[k + 1].yb + pc[k].yb + lby + hby + pc[k + 2].yb + pn[k + 1].yb;
+            const T hzb = pm[k + 1].zb + pc[k].zb + lbz + hbz + pc[k + 2].zb + pn[k + 1].zb;
+            const bool live = xin && row_in;
+            const uint32_t s0 = (uint32_t)(z * Ly + yc) * (uint32_t)Lx + 2u * xa + p;
+            const uint32_t i0 = own + (uint32_t)(z * Ly + yc) * Lxh + xa;
+            const bool aa = site(me.xa, me.ya, me.za, hxa, hya, hza, s0, live, i0);
+            const bool ab = site(me.xb, me.yb, me.zb, hxb, hyb, hzb, s0 + 2u, live, i0 + 1u);
+            // a pair with one accepted move rewrites the other column's
+            // unchanged value (same bits; no other workgroup owns it)
+            if (MODE != 1 && live && (aa || ab)) {
+                buf_store2(me.xa, me.xb, q.x, b_c, s_own);
+                buf_store2(me.ya, me.yb, q.y, b_c, s_own);
+                buf_store2(me.za, me.zb, q.z, b_c, s_own);
+            }
+        }
+    };
+    Row2<T> ra[RY + 2], rb[RY + 2], rc[RY + 2];
+    Vec3<T> ea[RY], eb[RY], ee[RY];
+    load_rows(z0 > 0 ? z0 - 1 : (pz ? Lz - 1 : -1), ra);
+    load_rows(z0, rb);
+    load_edges(z0, eb);
+    int z = z0;
+    for (; z + 2 < z1; z += 3) {
+        step(ra, rb, rc, eb, ee, z);
+        step(rb, rc, ra, ee, ea, z + 1);
+        step(rc, ra, rb, ea, eb, z + 2);
+    }
+    if (z < z1) step(ra, rb, rc, eb, ee, z);
+    if (z + 1 < z1) step(rb, rc, ra, ee, ea, z + 1);
+    if (MEASURE) {
+        acc[Q_NACC] = (double)n_acc;
+        block_store_partials(acc, P.partials_dev + ((size_t)colour * P.n_items + item) * NQ);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Band kernel (simple cubic): the row-strip scheme without idle lanes.  Rows
 // are grouped into bands of RY rows; the positions (band, xh) are numbered
 // band-major and dealt to the lanes contiguously, so a wave may run from the
@@ -892,6 +1129,14 @@ __global__ void __launch_bounds__(256) k_sc_band(PassLaunch P, int colour)
     sc_band_body<T, MEASURE, MODE, RY>(P, colour, item, *P.tctr_dev + P.t_off);
 }
 
+template <typename T, bool MEASURE, int MODE, int RY>
+__global__ void __launch_bounds__(256) k_sc_pair(PassLaunch P, int colour)
+{
+    uint32_t item;
+    if (!logical_item(P, item)) return;
+    sc_pair_body<T, MEASURE, MODE, RY>(P, colour, item, *P.tctr_dev + P.t_off);
+}
+
 template <int KIND, int B, typename T, bool MEASURE, int MODE>
 __global__ void __launch_bounds__(256) k_basis_pass(PassLaunch P)
 {
@@ -913,6 +1158,7 @@ __device__ __forceinline__ void unit_body(const PassLaunch &P, int c, uint32_t i
     if constexpr (KIND == SC) {
         if constexpr (KERNEL == KERNEL_STRIP) sc_strip_body<T, MEASURE, 0, RY>(P, c, item, t);
         else if constexpr (KERNEL == KERNEL_BAND) sc_band_body<T, MEASURE, 0, RY>(P, c, item, t);
+        else if constexpr (KERNEL == KERNEL_PAIR) sc_pair_body<T, MEASURE, 0, RY>(P, c, item, t);
         else sc_tile_body<T, MEASURE, 0>(P, c, item, t);
     } else {
         switch (c) {
@@ -1355,6 +1601,16 @@ static hipError_t sc_launch(int colour, const PassLaunch &p, hipStream_t st)
         }
         return hipGetLastError();
     }
+    if (p.tile.kernel == KERNEL_PAIR) {
+        const dim3 g = pass_grid(p), b(p.tile.tx);
+        switch (p.tile.ty) {
+        case 1: hipLaunchKernelGGL((k_sc_pair<T, MEASURE, MODE, 1>), g, b, 0, st, p, colour); break;
+        case 2: hipLaunchKernelGGL((k_sc_pair<T, MEASURE, MODE, 2>), g, b, 0, st, p, colour); break;
+        case 4: hipLaunchKernelGGL((k_sc_pair<T, MEASURE, MODE, 4>), g, b, 0, st, p, colour); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     if (p.tile.kernel == KERNEL_STRIP) {
         const dim3 g = pass_grid(p), b(p.tile.tx);
         switch (p.tile.ty) {
@@ -1503,6 +1759,10 @@ static hipError_t persist_dispatch(int kind, const PassLaunch &p, const PersistL
         hipLaunchKernelGGL((k_persistent<T, MEASURE, SC, KERNEL_STRIP, 2>), g, b, 0, st, p, a);
     } else if (p.tile.kernel == KERNEL_STRIP && p.tile.ty == 4) {
         hipLaunchKernelGGL((k_persistent<T, MEASURE, SC, KERNEL_STRIP, 4>), g, b, 0, st, p, a);
+    } else if (p.tile.kernel == KERNEL_PAIR && p.tile.ty == 1) {
+        hipLaunchKernelGGL((k_persistent<T, MEASURE, SC, KERNEL_PAIR, 1>), g, b, 0, st, p, a);
+    } else if (p.tile.kernel == KERNEL_PAIR && p.tile.ty == 2) {
+        hipLaunchKernelGGL((k_persistent<T, MEASURE, SC, KERNEL_PAIR, 2>), g, b, 0, st, p, a);
     } else if (p.tile.kernel == KERNEL_BAND && p.tile.ty == 2) {
         hipLaunchKernelGGL((k_persistent<T, MEASURE, SC, KERNEL_BAND, 2>), g, b, 0, st, p, a);
     } else if (p.tile.kernel == KERNEL_BAND && p.tile.ty == 4) {

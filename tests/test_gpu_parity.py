@@ -236,7 +236,8 @@ MEASURE_CASES = [("sc", (64, 40, 30), None), ("sc", (64, 40, 30), (0, 16, 16, 1)
                  ("sc", (64, 40, 30), (2, 256, 4, 1)), ("sc", (150, 14, 12), (1, 128, 2, 3)),
                  ("bcc", (9, 8, 7), None), ("fcc", (7, 6, 5), None),
                  ("bcc", (9, 8, 7), (0, 8, 8, 2)), ("fcc", (7, 6, 5), (0, 8, 8, 1)),
-                 ("sc", (16, 12, 10), (3, 256, 1, 1))]
+                 ("sc", (16, 12, 10), (3, 256, 1, 1)), ("sc", (64, 40, 30), (4, 64, 2, 3)),
+                 ("sc", (64, 40, 30), (4, 64, 4, 7))]
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
@@ -249,9 +250,11 @@ def test_measuring_does_not_change_the_chain(M, case, prec):
     kind, L, tile = MEASURE_CASES[case]
     rep = M.Replica(kind=kind, L=L, K=0.1, T=1.3, e=(0.0, 0.6, 0.8))
     sims = []
-    # the persistent kernel has no instantiation for strips of 1 or 8 rows
-    modes = ("plain", "measured") if tile and tile[0] == 1 and tile[2] in (1, 8) else \
-        ("plain", "measured", "persistent")
+    # the persistent kernel has no instantiation for strips of 1 or 8 rows or
+    # for pair tiles
+    no_persistent = tile and ((tile[0] == 4 and tile[2] == 4) or
+                              (tile[0] == 1 and tile[2] in (1, 8)))
+    modes = ("plain", "measured") if no_persistent else ("plain", "measured", "persistent")
     for mode in modes:
         s = M.Simulation([rep], precision=prec, seed=8,
                          scratch=torch.empty(32 << 20, dtype=torch.uint8, device="cuda"))
@@ -271,6 +274,46 @@ def test_measuring_does_not_change_the_chain(M, case, prec):
         with pytest.raises(M.MCError) as ei:
             s.sweep(1, persistent=True)
         assert ei.value.status == -2
+
+
+PAIR_TILES = [(4, 64, 1, 5), (4, 128, 2, 3), (4, 64, 4, 34), (4, 256, 2, 7), (4, 192, 1, 1),
+              (4, 64, 2, 1)]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_pair_kernel_is_bitwise(M, prec):
+    """Two packed columns per thread (8/16-byte accesses): spins equal the
+    default kernel's bitwise on rows of an even number of packed columns,
+    including rows spread over several tiles, ragged rows and open faces."""
+    import torch
+
+    base = dict(kind="sc", J=1.0, K=0.1, e=(0.0, 0.6, 0.8))
+    reps = [M.Replica(L=(24, 24, 24), T=1.0, replica_id=0, periodic_mask=7, **base),
+            M.Replica(L=(40, 38, 34), T=1.5, replica_id=1, periodic_mask=7, **base),
+            M.Replica(L=(148, 14, 12), T=0.7, replica_id=2, periodic_mask=7, **base),
+            M.Replica(L=(132, 9, 7), T=1.2, replica_id=3, periodic_mask=1, **base),
+            M.Replica(L=(520, 4, 6), T=1.3, replica_id=4, periodic_mask=6, **base)]
+    ref = M.Simulation(reps, precision=prec, seed=9,
+                       scratch=torch.empty(16 << 20, dtype=torch.uint8, device="cuda"))
+    ref.set_tile(16, 16, 2, kernel=0)
+    ref.sweep(6, measure=True)
+    obs_r = ref.observables()
+    for tile in PAIR_TILES:
+        scratch = torch.empty(16 << 20, dtype=torch.uint8, device="cuda")
+        one = M.Simulation(reps, precision=prec, seed=9, scratch=scratch)
+        one.set_tile(tile[1], tile[2], tile[3], kernel=tile[0])
+        one.sweep(2)
+        one.sweep(4, measure=True)
+        o = one.observables()
+        for r in range(len(reps)):
+            for a, b in zip(natural(one, r), natural(ref, r)):
+                assert np.array_equal(a, b), (r, tile)
+            assert o[r]["n_accepted"] == obs_r[r]["n_accepted"]
+            assert abs(o[r]["E"] - obs_r[r]["E"]) <= 1e-9 * abs(o[r]["E"])
+    odd = M.Simulation([M.Replica(kind="sc", L=(150, 14, 12))], precision=prec)
+    with pytest.raises(M.MCError) as ei:
+        odd.set_tile(64, 2, 3, kernel=4)
+    assert ei.value.status == -2
 
 
 LDS_CASES = [("sc", (16, 16, 16), 7, 0.0, "f64"), ("sc", (16, 16, 16), 7, 0.0, "f32"),
@@ -482,7 +525,7 @@ def test_full_size_sc464_sampled(M):
     w = W.C5_SC464_ROOFLINE
     rep = M.Replica(**W.replica_fields(w))
     sim = M.Simulation([rep], precision="f32", seed=w["seed"])
-    assert sim.get_tile()[0] == 2  # the band kernel the benchmark times
+    assert sim.get_tile()[0] == 4  # the pair kernel the benchmark times
     sim.sweep(99)
     sim.sweep(1, measure=True)
     fused = sim.observables()[0]
