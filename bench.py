@@ -128,26 +128,39 @@ def cpu_baseline(W, sweeps):
 
 
 def copy_probe(gib=2.0, reps=20, emit=True):
-    """Device-to-device copy of `gib` GiB (read + write of that size each)."""
+    """Device bandwidth probes with torch's elementwise kernels: a copy of
+    `gib` GiB (read + write that size) and an add of two `gib`/2 GiB operands
+    into a third (read two streams, write one: the access pattern of a colour
+    pass, 24 B read and 12 B written per update)."""
     import torch
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        for _ in range(reps):
+            fn()
+        e.record()
+        e.synchronize()
+        return s.elapsed_time(e) / reps
 
     n = int(gib * 2**30) // 4
     a = torch.ones(n, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
-    for _ in range(3):
-        b.copy_(a)
-    torch.cuda.synchronize()
-    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    s.record()
-    for _ in range(reps):
-        b.copy_(a)
-    e.record()
-    e.synchronize()
-    ms = s.elapsed_time(e) / reps
-    gbps = 2 * n * 4 / (ms * 1e-3) / 1e9
+    ms = timed(lambda: b.copy_(a))
     res = {"probe": "device copy", "bytes_read": n * 4, "bytes_written": n * 4, "ms": ms,
-           "GBps": gbps}
+           "GBps": 2 * n * 4 / (ms * 1e-3) / 1e9}
     del a, b
+    m = n // 2
+    x = torch.ones(m, dtype=torch.float32, device="cuda")
+    y = torch.ones(m, dtype=torch.float32, device="cuda")
+    z = torch.empty_like(x)
+    ms2 = timed(lambda: torch.add(x, y, out=z))
+    res["read2_write1"] = {"bytes_read": 2 * m * 4, "bytes_written": m * 4, "ms": ms2,
+                           "GBps": 3 * m * 4 / (ms2 * 1e-3) / 1e9}
+    del x, y, z
     torch.cuda.empty_cache()
     if emit:
         print(json.dumps(res), flush=True)
@@ -330,7 +343,8 @@ def main():
     traffic = measured_traffic([KERNEL_NAMES.index(t32["kernel"]), t32["tx"], t32["ty"],
                                 t32["zc"]])
     copy = copy_probe(emit=False)
-    log(f"[bench] device copy {copy['GBps']:.0f} GB/s")
+    log(f"[bench] device copy {copy['GBps']:.0f} GB/s, read-two-write-one "
+        f"{copy['read2_write1']['GBps']:.0f} GB/s")
     ach = r32["achieved_GBps"]
     out = {
         "metric": "spin-update attempts/ns (G updates/s) + % HBM roofline, FP32 vs FP64, 10^8 spins",
@@ -353,6 +367,7 @@ def main():
                      "unit": "GB/s", "frac": ach / HBM_PEAK_GBPS,
                      "traffic": traffic,
                      "copy_GBps": copy["GBps"], "frac_of_copy": ach / copy["GBps"],
+                     "read2_write1_GBps": copy["read2_write1"]["GBps"],
                      # the same updates priced at the 24 B/update minimum (each
                      # spin read and written once per sweep)
                      "frac_at_24B_per_update": r32["value"] * 24.0 / HBM_PEAK_GBPS,
