@@ -24,7 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0           # MI355X HBM3E
-KERNEL_NAMES = ["tile", "strip", "band", "lds", "pair"]  # mc_set_tile kernel ids
+KERNEL_NAMES = ["tile", "strip", "band", "lds", "pair", "pband"]  # mc_set_tile kernel ids
 BYTES_PER_UPDATE = {"f32": 36, "f64": 72}  # two-pass colour-packed: read own + other, write own
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sc_pass_f32_L464_traffic.json")
 # sources whose change invalidates the committed counter readings
@@ -104,6 +104,21 @@ def time_precision(M, W, prec, steps, warmup, tile=None):
     torch.cuda.empty_cache()
     log(f"[bench] {prec}: {res['value']:.2f} updates/ns, pass {pass_ms:.4f} ms")
     return res
+
+
+def pattern_probe(M, n_box, grids=(1024, 2048, 8192, 32768), reps=10):
+    """The colour pass's HBM access pattern without its arithmetic
+    (mc_stream_probe) on three FP32 planes of the benchmark's size: the
+    best rate over a few grid sizes, in algorithmic GB/s (36 B per update,
+    N/2 updates per pass)."""
+    import torch
+
+    half = n_box // 2
+    xs = [torch.zeros(2 * half, dtype=torch.float32, device="cuda") for _ in range(3)]
+    best = min(M.stream_probe(*xs, grid=g, reps=reps) for g in grids)
+    del xs
+    torch.cuda.empty_cache()
+    return 36.0 * half / (best * 1e-3) / 1e9, best
 
 
 def cpu_baseline(W, sweeps):
@@ -342,6 +357,8 @@ def main():
     t32 = r32["tile"]
     traffic = measured_traffic([KERNEL_NAMES.index(t32["kernel"]), t32["tx"], t32["ty"],
                                 t32["zc"]])
+    pat_gbps, pat_ms = pattern_probe(M, r32["n_spins"])
+    log(f"[bench] pass access pattern without arithmetic: {pat_ms * 1e3:.1f} us, {pat_gbps:.0f} GB/s")
     copy = copy_probe(emit=False)
     log(f"[bench] device copy {copy['GBps']:.0f} GB/s, read-two-write-one "
         f"{copy['read2_write1']['GBps']:.0f} GB/s")
@@ -368,6 +385,8 @@ def main():
                      "traffic": traffic,
                      "copy_GBps": copy["GBps"], "frac_of_copy": ach / copy["GBps"],
                      "read2_write1_GBps": copy["read2_write1"]["GBps"],
+                     # the pass's own access pattern with no arithmetic
+                     "pattern_GBps": pat_gbps, "frac_of_pattern": ach / pat_gbps,
                      # the same updates priced at the 24 B/update minimum (each
                      # spin read and written once per sweep)
                      "frac_at_24B_per_update": r32["value"] * 24.0 / HBM_PEAK_GBPS,

@@ -242,7 +242,10 @@ mc_status mc_set_sweep(mc_sim *h, uint64_t t);
  *    default when every row also has at least 96 packed columns): as
  *    kernel 1 with two adjacent columns per thread, read and written as one
  *    8-byte (FP32) or 16-byte (FP64) access; tx threads (64 .. 256) cover 2 tx
- *    columns, ty rows per thread (1, 2 or 4; persistent sweeps: 1 or 2).
+ *    columns, ty rows per thread (1, 2 or 4; persistent sweeps: 1 or 2);
+ *  kernel 5 (sc only, even packed rows): as kernel 2 with two adjacent
+ *    columns per thread: tx (64 .. 256) (band, pair) positions per workgroup,
+ *    bands of ty rows (2 or 4; persistent sweeps: 2).
  * The spins do not depend on the choice (only the FP64 summation order of the
  * observables does).  A shape whose work list does not fit the handle's
  * scratch gives MC_E_BUFFER.  Choosing kernel 0-2 discards the record of the
@@ -284,6 +287,20 @@ mc_status mc_synchronize(mc_sim *h);
 
 /* Release the handle (never the caller's buffers, scratch or stream). */
 void mc_destroy(mc_sim *h);
+
+/* Measurement aid (no handle): the HBM access pattern of one simple-cubic
+ * colour pass without its arithmetic, as a ceiling for the pass kernels.
+ * x, y, z: caller-owned device arrays of 2*half_elems elements of `prec`
+ * each (one component plane per colour, like the spin planes); their
+ * contents are overwritten.  Each launch reads both halves and writes the
+ * first in place (24 B read, 12 B written per FP32 element of the first
+ * half), two elements per lane per access, on `grid` workgroups of 256
+ * threads.  One untimed launch, then `reps` timed launches on hip_stream
+ * (NULL: the default stream); *ms = mean time per launch.  half_elems must
+ * be even and >= 2, grid in [1, 2^20], reps >= 1; MC_E_BUFFER for a NULL or
+ * too small array.  Synchronises. */
+mc_status mc_stream_probe(mc_precision prec, void *x, void *y, void *z, uint64_t half_elems,
+                          uint32_t grid, uint32_t reps, void *hip_stream, double *ms);
 
 /* Message of the last error on this thread ("" if none). */
 const char *mc_last_error(void);

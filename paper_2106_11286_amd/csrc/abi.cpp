@@ -134,8 +134,9 @@ int pow2_at_least(int v)
 // Workgroup tiles covering one z plane of a replica.
 uint64_t xy_tiles(const mc_replica_desc &d, const Tile &t)
 {
-    if (t.kernel == KERNEL_BAND) {
-        const uint64_t F = (uint64_t)((d.Ly + t.ty - 1) / t.ty) * row_len(d);
+    if (t.kernel == KERNEL_BAND || t.kernel == KERNEL_PBAND) {
+        const int cols = t.kernel == KERNEL_PBAND ? row_len(d) / 2 : row_len(d);
+        const uint64_t F = (uint64_t)((d.Ly + t.ty - 1) / t.ty) * cols;
         return (F + t.tx - 1) / t.tx;
     }
     const int wx = t.kernel == KERNEL_PAIR ? 2 * t.tx : t.tx; // packed columns per tile
@@ -197,6 +198,14 @@ mc_status check_tile(const Tile &t, int kind, uint64_t max_component_bytes)
             return fail(MC_E_ARG, "band tile: tx must be 64, 128, 192 or 256 (got %d)", t.tx);
         if (t.ty != 2 && t.ty != 4)
             return fail(MC_E_ARG, "band tile: ty (rows per band) must be 2 or 4");
+    } else if (t.kernel == KERNEL_PBAND) {
+        if (kind != MC_SC) return fail(MC_E_ARG, "the band-pair kernel is for simple cubic lattices");
+        if (max_component_bytes > 0xFFFFFFFFull)
+            return fail(MC_E_UNSUPPORTED, "band-pair kernel: a spin component array exceeds 4 GiB");
+        if (t.tx < 64 || t.tx > 256 || t.tx % 64)
+            return fail(MC_E_ARG, "band-pair tile: tx must be 64, 128, 192 or 256 (got %d)", t.tx);
+        if (t.ty != 2 && t.ty != 4)
+            return fail(MC_E_ARG, "band-pair tile: ty (rows per band) must be 2 or 4");
     } else if (t.kernel == KERNEL_PAIR) {
         if (kind != MC_SC) return fail(MC_E_ARG, "the pair kernel is for simple cubic lattices");
         if (max_component_bytes > 0xFFFFFFFFull)
@@ -244,14 +253,15 @@ void make_work(const mc_replica_desc *reps, int n, const Tile &t, std::vector<Wo
         begin[r] = (uint32_t)work.size();
         const int W = row_len(d);
         const bool sc = d.kind == MC_SC;
-        if (t.kernel == KERNEL_BAND) {
+        if (t.kernel == KERNEL_BAND || t.kernel == KERNEL_PBAND) {
             const int rows = t.ty;
-            const int F = (d.Ly + rows - 1) / rows * W;
+            const int cols = t.kernel == KERNEL_PBAND ? W / 2 : W; // positions per row
+            const int F = (d.Ly + rows - 1) / rows * cols;
             for (int z0 = 0; z0 < d.Lz; z0 += t.zc)
                 for (int f0 = 0; f0 < F; f0 += t.tx) {
                     if (d.sphere_radius > 0.0) {
-                        const int y0 = f0 / W * rows;
-                        const int y1 = std::min(d.Ly, ((f0 + t.tx - 1) / W + 1) * rows) - 1;
+                        const int y0 = f0 / cols * rows;
+                        const int y1 = std::min(d.Ly, ((f0 + t.tx - 1) / cols + 1) * rows) - 1;
                         const int cz1 = std::min(d.Lz, z0 + t.zc) - 1;
                         const int64_t m = min_sq(-d.Lx, d.Lx - 1) +
                                           min_sq(2 * y0 - d.Ly, 2 * y1 + 1 - d.Ly) +
@@ -465,6 +475,7 @@ mc_status enqueue_sweeps(mc_sim *h, uint32_t n, bool measure, uint32_t slot0)
 bool persistent_supported(const Tile &t)
 {
     if (t.kernel == KERNEL_PAIR) return t.ty == 1 || t.ty == 2;
+    if (t.kernel == KERNEL_PBAND) return t.ty == 2;
     return t.kernel != KERNEL_STRIP || t.ty == 2 || t.ty == 4;
 }
 
@@ -647,6 +658,42 @@ extern "C" {
 const char *mc_last_error(void) { return g_err.c_str(); }
 
 const char *mc_version(void) { return "mcheis 0.1 (gfx950)"; }
+
+mc_status mc_stream_probe(mc_precision prec, void *x, void *y, void *z, uint64_t half_elems,
+                          uint32_t grid, uint32_t reps, void *hip_stream, double *ms)
+{
+    if (prec != MC_F32 && prec != MC_F64) return fail(MC_E_ARG, "unknown precision %d", (int)prec);
+    if (!ms) return fail(MC_E_ARG, "ms is NULL");
+    if (half_elems < 2 || half_elems % 2)
+        return fail(MC_E_ARG, "half_elems must be even and >= 2");
+    if (grid < 1 || grid > (1u << 20)) return fail(MC_E_ARG, "grid must be in [1, 2^20]");
+    if (reps < 1) return fail(MC_E_ARG, "reps must be >= 1");
+    const uint64_t bytes = 2 * half_elems * (prec == MC_F64 ? sizeof(double) : sizeof(float));
+    void *pl[3] = {x, y, z};
+    const char *nm[3] = {"x", "y", "z"};
+    for (int a = 0; a < 3; ++a) {
+        mc_status s = check_device_buffer(pl[a], bytes, nm[a], -1);
+        if (s != MC_OK) return s;
+    }
+    hipStream_t st = (hipStream_t)hip_stream;
+    const bool f64 = prec == MC_F64;
+    HIP_TRY(launch_stream_probe(f64, x, y, z, half_elems, grid, st));
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    hipError_t err = hipEventRecord(e0, st);
+    for (uint32_t r = 0; r < reps && err == hipSuccess; ++r)
+        err = launch_stream_probe(f64, x, y, z, half_elems, grid, st);
+    if (err == hipSuccess) err = hipEventRecord(e1, st);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float t = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return fail(MC_E_DEVICE, "stream probe: %s", hipGetErrorString(err));
+    *ms = (double)t / reps;
+    return MC_OK;
+}
 
 mc_status mc_required_sites(const mc_replica_desc *d, uint64_t *sites)
 {
@@ -1128,10 +1175,10 @@ mc_status mc_set_tile(mc_sim *h, int32_t kernel, int32_t tx, int32_t ty, int32_t
                                                       (h->prec == MC_F64 ? 8u : 4u));
     mc_status st = check_tile(t, h->kind, max_bytes);
     if (st != MC_OK) return st;
-    if (kernel == KERNEL_PAIR)
+    if (kernel == KERNEL_PAIR || kernel == KERNEL_PBAND)
         for (int r = 0; r < h->n_reps; ++r)
             if (row_len(h->desc[r]) % 2)
-                return fail(MC_E_UNSUPPORTED, "pair kernel: replica %d has an odd number (%d) of "
+                return fail(MC_E_UNSUPPORTED, "pair kernels: replica %d has an odd number (%d) of "
                                               "packed columns per row", r, row_len(h->desc[r]));
     std::vector<WorkItem> work;
     std::vector<uint32_t> b, e;
@@ -1191,6 +1238,8 @@ std::vector<Tile> tile_candidates(const mc_sim *h)
         if (even) {
             const int pairs = std::min(256, ((W + 1) / 2 + 63) / 64 * 64);
             for (int ry : {1, 2, 4}) base.push_back(Tile{KERNEL_PAIR, pairs, ry, 1});
+            for (int ry : {2, 4}) base.push_back(Tile{KERNEL_PBAND, 256, ry, 1});
+            base.push_back(Tile{KERNEL_PBAND, 128, 2, 1});
         }
     }
     for (int tx : {64, 32, 16, 8}) {

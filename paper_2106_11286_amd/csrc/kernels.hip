@@ -796,6 +796,202 @@ __device__ __forceinline__ void sc_pair_body(const PassLaunch &P, int colour, ui
 }
 
 // ---------------------------------------------------------------------------
+// Band-pair kernel (simple cubic, rows of an even number of packed columns):
+// the pair scheme with the band layout.  Rows are grouped into bands of RY
+// rows; the (band, pair) positions are numbered band-major and dealt to the
+// lanes contiguously, so no lane idles whatever the row length, and the bands
+// of one workgroup share their halo rows through the CU's cache.  With RY
+// even the row parity depends only on (k, z), so it is uniform over a wave.
+// ---------------------------------------------------------------------------
+template <typename T, bool MEASURE, int MODE, int RY>
+__device__ __forceinline__ void sc_pband_body(const PassLaunch &P, int colour, uint32_t item,
+                                              uint32_t t)
+{
+    static_assert(RY % 2 == 0, "band rows must be even");
+    // every descriptor field is read into registers before the first store, so
+    // the loads stay scalar (memory that the kernel may write cannot be)
+    const WorkItem w = P.work_dev[item];
+    const RepDev &R = P.reps_dev[w.rep];
+    const int Ly = R.Ly, Lz = R.Lz, Lxh = R.Lxh, Lx = R.Lx;
+    void *const base_x = R.sx, *const base_y = R.sy, *const base_z = R.sz;
+    const uint32_t rid = R.rid;
+    const int lane = threadIdx.x & 63;
+    const int NP = Lxh >> 1; // pairs per row
+    const int n_bands = (Ly + RY - 1) / RY;
+    const int F = n_bands * NP; // positions (band, pair)
+    const int fraw = w.x0 + (int)threadIdx.x;
+    const bool fin = fraw < F && (int)threadIdx.x < P.tile.tx;
+    const int f = fin ? fraw : F - 1;
+    const int band = f / NP;
+    const int xa = 2 * (f - band * NP), xb = xa + 1;
+    const int yb = band * RY; // first row of the band
+    const uint32_t plane = R.plane;
+    const uint32_t own = colour ? plane : 0u, oth = colour ? 0u : plane;
+    const T J = (T)R.J, K = (T)R.K, ex = (T)R.e[0], ey = (T)R.e[1], ez = (T)R.e[2];
+    const T beta = (T)R.beta;
+    const bool greedy = R.greedy != 0;
+    const bool px = R.pmask & 1u, py = R.pmask & 2u, pz = R.pmask & 4u;
+    const int xl = xa > 0 ? xa - 1 : (px ? Lxh - 1 : -1);  // column left of the pair
+    const int xr = xb < Lxh - 1 ? xb + 1 : (px ? 0 : -1);  // column right of the pair
+    const bool left_mem = lane == 0 || xa == 0;           // xa-1 not held by lane-1
+    const bool right_mem = lane == 63 || xb >= Lxh - 1;   // xb+1 not held by lane+1
+    const uint32_t row_bytes = (uint32_t)Lxh * (uint32_t)sizeof(T);
+    const uint32_t b_c = (uint32_t)xa * (uint32_t)sizeof(T);
+    const uint32_t b_l = (uint32_t)(xl < 0 ? 0 : xl) * (uint32_t)sizeof(T);
+    const uint32_t b_r = (uint32_t)(xr < 0 ? 0 : xr) * (uint32_t)sizeof(T);
+    const PlaneRs<T> q = {plane_rsrc<T>(base_x, 0, R.n_box), plane_rsrc<T>(base_y, 0, R.n_box),
+                          plane_rsrc<T>(base_z, 0, R.n_box)};
+    const uint32_t own_b = own * (uint32_t)sizeof(T), oth_b = oth * (uint32_t)sizeof(T);
+    const uint32_t zplane_b = (uint32_t)Ly * row_bytes;
+
+    // this lane's rows yb-1 .. yb+RY (wrapped on periodic faces) as byte
+    // offsets within a z plane, and which of them exist (open faces)
+    uint32_t roff[RY + 2];
+    uint32_t row_ok = 0;
+#pragma unroll
+    for (int k = -1; k <= RY; ++k) {
+        int y = yb + k;
+        bool ok = true;
+        if (y < 0 || y >= Ly) {
+            if (py) {
+                while (y < 0) y += Ly;
+                while (y >= Ly) y -= Ly;
+            } else {
+                ok = false;
+                y = y < 0 ? 0 : Ly - 1;
+            }
+        }
+        roff[k + 1] = (uint32_t)y * row_bytes + b_c;
+        row_ok |= (ok ? 1u : 0u) << (k + 1);
+    }
+    auto load_rows = [&](int z, Row2<T> *dst) {
+        if (z < 0) {
+#pragma unroll
+            for (int k = 0; k < RY + 2; ++k) dst[k] = Row2<T>{T(0), T(0), T(0), T(0), T(0), T(0)};
+            return;
+        }
+        const uint32_t soff = oth_b + (uint32_t)z * zplane_b;
+#pragma unroll
+        for (int k = 0; k < RY + 2; ++k) {
+            buf_load2(q.x, roff[k], soff, dst[k].xa, dst[k].xb);
+            buf_load2(q.y, roff[k], soff, dst[k].ya, dst[k].yb);
+            buf_load2(q.z, roff[k], soff, dst[k].za, dst[k].zb);
+            if (!py && !((row_ok >> k) & 1u)) dst[k] = Row2<T>{T(0), T(0), T(0), T(0), T(0), T(0)};
+        }
+    };
+    // the in-row neighbour beyond the pair where the lane shift cannot supply
+    // it (wave edges, band seams, the periodic wrap, open faces), loaded one
+    // plane ahead
+    auto load_edges = [&](int z, Vec3<T> *dst) {
+        const uint32_t soff = oth_b + (uint32_t)z * zplane_b;
+#pragma unroll
+        for (int k = 0; k < RY; ++k) {
+            const int p = (colour + k + z) & 1;
+            const bool need = p ? right_mem : left_mem;
+            const int col = p ? xr : xl;
+            if (need && col >= 0) {
+                const uint32_t v = roff[k + 1] - b_c + (p ? b_r : b_l);
+                dst[k] = {buf_load(q.x, v, soff, T()), buf_load(q.y, v, soff, T()),
+                          buf_load(q.z, v, soff, T())};
+            } else {
+                dst[k] = {T(0), T(0), T(0)};
+            }
+        }
+    };
+
+    double acc[Q_N] = {0, 0, 0, 0, 0, 0};
+    uint32_t n_acc = 0;
+    auto site = [&](T &sx, T &sy, T &sz, T hx, T hy, T hz, uint32_t s, bool live,
+                    uint32_t i) -> bool {
+        hx *= J;
+        hy *= J;
+        hz *= J;
+        bool a = false;
+        if (MODE != 1) {
+            T dH;
+            a = metropolis<T>(sx, sy, sz, hx, hy, hz, s, rid, t, P.seed_lo, P.seed_hi, K, ex, ey,
+                              ez, beta, greedy, dH);
+            if (MODE == 2 && live) {
+                ((T *)P.dbg_dh)[i] = dH;
+                P.dbg_acc[i] = a ? 1 : 0;
+            }
+        }
+        if (MEASURE && live) {
+            acc[Q_MX] += (double)sx;
+            acc[Q_MY] += (double)sy;
+            acc[Q_MZ] += (double)sz;
+            const double pe = (double)(sx * ex + sy * ey + sz * ez);
+            acc[Q_PE2] += pe * pe;
+            if (colour == 1) acc[Q_SH] += (double)(sx * hx + sy * hy + sz * hz);
+            n_acc += a ? 1u : 0u;
+        }
+        return a;
+    };
+
+    const int z0 = w.z0, z1 = min(w.z0 + P.tile.zc, Lz);
+    Row2<T> om[RY + 2], oc[RY + 2], op[RY + 2];
+    Vec3<T> ec[RY], en[RY];
+    load_rows(z0 > 0 ? z0 - 1 : (pz ? Lz - 1 : -1), om);
+    load_rows(z0, oc);
+    load_edges(z0, ec);
+    for (int z = z0; z < z1; ++z) {
+        const int zn = z < Lz - 1 ? z + 1 : (pz ? 0 : -1);
+        load_rows(zn, op);
+        if (z + 1 < z1) load_edges(zn, en);
+        const uint32_t s_own = own_b + (uint32_t)z * zplane_b;
+#pragma unroll
+        for (int k = 0; k < RY; ++k) {
+            const int y = yb + k;
+            const bool live = fin && y < Ly;
+            const int p = (colour + k + z) & 1; // uniform over the wave (RY even)
+            Row2<T> me;
+            buf_load2(q.x, roff[k + 1], s_own, me.xa, me.xb);
+            buf_load2(q.y, roff[k + 1], s_own, me.ya, me.yb);
+            buf_load2(q.z, roff[k + 1], s_own, me.za, me.zb);
+            const Row2<T> c = oc[k + 1];
+            // the other colour's column beyond the pair
+            Vec3<T> nb;
+            if (p == 0)
+                nb = {from_lower_lane(c.xb), from_lower_lane(c.yb), from_lower_lane(c.zb)};
+            else
+                nb = {from_upper_lane(c.xa), from_upper_lane(c.ya), from_upper_lane(c.za)};
+            if (p ? right_mem : left_mem) nb = ec[k];
+            // in-row neighbours (x-1, x+1) of column a and of column b
+            const T lax = p ? c.xa : nb.x, lay = p ? c.ya : nb.y, laz = p ? c.za : nb.z;
+            const T hax = p ? c.xb : c.xa, hay = p ? c.yb : c.ya, haz = p ? c.zb : c.za;
+            const T lbx = p ? c.xb : c.xa, lby = p ? c.yb : c.ya, lbz = p ? c.zb : c.za;
+            const T hbx = p ? nb.x : c.xb, hby = p ? nb.y : c.yb, hbz = p ? nb.z : c.zb;
+            // fixed order: -z, -y, -x, +x, +y, +z
+            const T hxa = om[k + 1].xa + oc[k].xa + lax + hax + oc[k + 2].xa + op[k + 1].xa;
+            const T hya = om[k + 1].ya + oc[k].ya + lay + hay + oc[k + 2].ya + op[k + 1].ya;
+            const T hza = om[k + 1].za + oc[k].za + laz + haz + oc[k + 2].za + op[k + 1].za;
+            const T hxb = om[k + 1].xb + oc[k].xb + lbx + hbx + oc[k + 2].xb + op[k + 1].xb;
+            const T hyb = om[k + 1].yb + oc[k].yb + lby + hby + oc[k + 2].yb + op[k + 1].yb;
+            const T hzb = om[k + 1].zb + oc[k].zb + lbz + hbz + oc[k + 2].zb + op[k + 1].zb;
+            const uint32_t s0 = (uint32_t)(z * Ly + y) * (uint32_t)Lx + 2u * xa + p;
+            const uint32_t i0 = own + (uint32_t)(z * Ly + y) * Lxh + xa;
+            const bool aa = site(me.xa, me.ya, me.za, hxa, hya, hza, s0, live, i0);
+            const bool ab = site(me.xb, me.yb, me.zb, hxb, hyb, hzb, s0 + 2u, live, i0 + 1u);
+            if (MODE != 1 && live && (aa || ab)) {
+                buf_store2(me.xa, me.xb, q.x, roff[k + 1], s_own);
+                buf_store2(me.ya, me.yb, q.y, roff[k + 1], s_own);
+                buf_store2(me.za, me.zb, q.z, roff[k + 1], s_own);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < RY + 2; ++k) om[k] = oc[k];
+#pragma unroll
+        for (int k = 0; k < RY + 2; ++k) oc[k] = op[k];
+#pragma unroll
+        for (int k = 0; k < RY; ++k) ec[k] = en[k];
+    }
+    if (MEASURE) {
+        acc[Q_NACC] = (double)n_acc;
+        block_store_partials(acc, P.partials_dev + ((size_t)colour * P.n_items + item) * NQ);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Band kernel (simple cubic): the row-strip scheme without idle lanes.  Rows
 // are grouped into bands of RY rows; the positions (band, xh) are numbered
 // band-major and dealt to the lanes contiguously, so a wave may run from the
@@ -1137,6 +1333,14 @@ __global__ void __launch_bounds__(256) k_sc_pair(PassLaunch P, int colour)
     sc_pair_body<T, MEASURE, MODE, RY>(P, colour, item, *P.tctr_dev + P.t_off);
 }
 
+template <typename T, bool MEASURE, int MODE, int RY>
+__global__ void __launch_bounds__(256) k_sc_pband(PassLaunch P, int colour)
+{
+    uint32_t item;
+    if (!logical_item(P, item)) return;
+    sc_pband_body<T, MEASURE, MODE, RY>(P, colour, item, *P.tctr_dev + P.t_off);
+}
+
 template <int KIND, int B, typename T, bool MEASURE, int MODE>
 __global__ void __launch_bounds__(256) k_basis_pass(PassLaunch P)
 {
@@ -1159,6 +1363,7 @@ __device__ __forceinline__ void unit_body(const PassLaunch &P, int c, uint32_t i
         if constexpr (KERNEL == KERNEL_STRIP) sc_strip_body<T, MEASURE, 0, RY>(P, c, item, t);
         else if constexpr (KERNEL == KERNEL_BAND) sc_band_body<T, MEASURE, 0, RY>(P, c, item, t);
         else if constexpr (KERNEL == KERNEL_PAIR) sc_pair_body<T, MEASURE, 0, RY>(P, c, item, t);
+        else if constexpr (KERNEL == KERNEL_PBAND) sc_pband_body<T, MEASURE, 0, RY>(P, c, item, t);
         else sc_tile_body<T, MEASURE, 0>(P, c, item, t);
     } else {
         switch (c) {
@@ -1585,6 +1790,31 @@ __global__ void k_fill_zero(double *p, uint64_t n)
 }
 
 // ---------------------------------------------------------------------------
+// Memory-pattern probe: the HBM streams of one colour pass without its
+// arithmetic.  Three component arrays of 2 P elements; the first half is read
+// and written in place, the second half read (24 B read and 12 B written per
+// FP32 element of the first half), two elements per lane per access.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_stream_probe(T *x, T *y, T *z, uint64_t P)
+{
+    const uint64_t n2 = P / 2; // element pairs per half
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n2;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t a = 2 * i, b = P + 2 * i;
+        const T x0 = x[a] + x[b], x1 = x[a + 1] + x[b + 1];
+        const T y0 = y[a] + y[b], y1 = y[a + 1] + y[b + 1];
+        const T z0 = z[a] + z[b], z1 = z[a + 1] + z[b + 1];
+        x[a] = x0;
+        x[a + 1] = x1;
+        y[a] = y0;
+        y[a + 1] = y1;
+        z[a] = z0;
+        z[a + 1] = z1;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
 static dim3 pass_grid(const PassLaunch &p) { return dim3(((p.n_blocks + 7u) >> 3) << 3); }
@@ -1597,6 +1827,15 @@ static hipError_t sc_launch(int colour, const PassLaunch &p, hipStream_t st)
         switch (p.tile.ty) {
         case 2: hipLaunchKernelGGL((k_sc_band<T, MEASURE, MODE, 2>), g, b, 0, st, p, colour); break;
         case 4: hipLaunchKernelGGL((k_sc_band<T, MEASURE, MODE, 4>), g, b, 0, st, p, colour); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
+    if (p.tile.kernel == KERNEL_PBAND) {
+        const dim3 g = pass_grid(p), b(p.tile.tx);
+        switch (p.tile.ty) {
+        case 2: hipLaunchKernelGGL((k_sc_pband<T, MEASURE, MODE, 2>), g, b, 0, st, p, colour); break;
+        case 4: hipLaunchKernelGGL((k_sc_pband<T, MEASURE, MODE, 4>), g, b, 0, st, p, colour); break;
         default: return hipErrorInvalidValue;
         }
         return hipGetLastError();
@@ -1759,6 +1998,8 @@ static hipError_t persist_dispatch(int kind, const PassLaunch &p, const PersistL
         hipLaunchKernelGGL((k_persistent<T, MEASURE, SC, KERNEL_STRIP, 2>), g, b, 0, st, p, a);
     } else if (p.tile.kernel == KERNEL_STRIP && p.tile.ty == 4) {
         hipLaunchKernelGGL((k_persistent<T, MEASURE, SC, KERNEL_STRIP, 4>), g, b, 0, st, p, a);
+    } else if (p.tile.kernel == KERNEL_PBAND && p.tile.ty == 2) {
+        hipLaunchKernelGGL((k_persistent<T, MEASURE, SC, KERNEL_PBAND, 2>), g, b, 0, st, p, a);
     } else if (p.tile.kernel == KERNEL_PAIR && p.tile.ty == 1) {
         hipLaunchKernelGGL((k_persistent<T, MEASURE, SC, KERNEL_PAIR, 1>), g, b, 0, st, p, a);
     } else if (p.tile.kernel == KERNEL_PAIR && p.tile.ty == 2) {
@@ -1852,6 +2093,19 @@ hipError_t launch_fill_zero(double *p, uint64_t n, hipStream_t st)
     if (n == 0) return hipSuccess;
     const unsigned g = grid_for((uint32_t)(n < 0xFFFFFFFFull ? n : 0xFFFFFFFFull));
     hipLaunchKernelGGL(k_fill_zero, dim3(g), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_probe(bool f64, void *x, void *y, void *z, uint64_t P, uint32_t grid,
+                               hipStream_t st)
+{
+    if (grid == 0 || P < 2) return hipErrorInvalidValue;
+    if (f64)
+        hipLaunchKernelGGL(k_stream_probe<double>, dim3(grid), dim3(256), 0, st, (double *)x,
+                           (double *)y, (double *)z, P);
+    else
+        hipLaunchKernelGGL(k_stream_probe<float>, dim3(grid), dim3(256), 0, st, (float *)x,
+                           (float *)y, (float *)z, P);
     return hipGetLastError();
 }
 

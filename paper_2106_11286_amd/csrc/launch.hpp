@@ -79,6 +79,9 @@ hipError_t launch_lds(int kind, bool f64, bool measure, const LdsLaunch &L, int 
 // Allow the LDS kernels of one lattice kind and precision `bytes` of dynamic LDS.
 hipError_t lds_allow(int kind, bool f64, uint32_t bytes);
 
+// The HBM streams of a colour pass without its arithmetic (see mc_stream_probe).
+hipError_t launch_stream_probe(bool f64, void *x, void *y, void *z, uint64_t P, uint32_t grid,
+                               hipStream_t st);
 hipError_t launch_advance(uint32_t *tctr_dev, uint32_t n, hipStream_t st);
 hipError_t launch_set_counter(uint32_t *tctr_dev, uint32_t v, hipStream_t st);
 hipError_t launch_fill_zero(double *p, uint64_t n, hipStream_t st);

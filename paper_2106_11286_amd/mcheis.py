@@ -112,6 +112,10 @@ _SIGNATURES = {
     "mc_destroy": (None, [ctypes.c_void_p]),
     "mc_last_error": (ctypes.c_char_p, []),
     "mc_version": (ctypes.c_char_p, []),
+    "mc_stream_probe": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32,
+                                       ctypes.c_uint32, ctypes.c_void_p,
+                                       ctypes.POINTER(ctypes.c_double)]),
 }
 
 
@@ -142,6 +146,24 @@ def last_error() -> str:
 
 def version() -> str:
     return LIB.mc_version().decode()
+
+
+def stream_probe(x, y, z, grid: int = 2048, reps: int = 10, stream=None) -> float:
+    """``mc_stream_probe``: mean ms per launch of a colour pass's HBM access
+    pattern (no arithmetic) over three device tensors of 2*P elements (float32
+    or float64; overwritten)."""
+    import torch
+
+    for t in (x, y, z):
+        if not (t.is_cuda and t.is_contiguous() and t.dtype == x.dtype and t.numel() == x.numel()):
+            raise ValueError("x, y, z must be contiguous CUDA tensors of one dtype and size")
+    prec = {torch.float32: F32, torch.float64: F64}[x.dtype]
+    st = (stream or torch.cuda.current_stream(x.device)).cuda_stream
+    ms = ctypes.c_double()
+    _check("mc_stream_probe", LIB.mc_stream_probe(prec, x.data_ptr(), y.data_ptr(), z.data_ptr(),
+                                                  x.numel() // 2, int(grid), int(reps),
+                                                  ctypes.c_void_p(st), ctypes.byref(ms)))
+    return ms.value
 
 
 @dataclass
@@ -349,7 +371,7 @@ class Simulation:
         """``mc_set_tile``: kernel 0 = tile (tx x ty threads), 1 = sc row strip
         (tx threads along the row, ty rows per thread), 2 = sc band, 3 = whole
         sweeps in LDS (tx threads per replica), 4 = sc pair strip (two columns
-        per thread); zc planes per tile."""
+        per thread), 5 = sc band of pairs; zc planes per tile."""
         _check("mc_set_tile", LIB.mc_set_tile(self.handle, int(kernel), int(tx), int(ty), int(zc)))
 
     def autotune(self, trial_sweeps: int = 5, measure: bool = True, persistent: bool = False,

@@ -237,7 +237,8 @@ MEASURE_CASES = [("sc", (64, 40, 30), None), ("sc", (64, 40, 30), (0, 16, 16, 1)
                  ("bcc", (9, 8, 7), None), ("fcc", (7, 6, 5), None),
                  ("bcc", (9, 8, 7), (0, 8, 8, 2)), ("fcc", (7, 6, 5), (0, 8, 8, 1)),
                  ("sc", (16, 12, 10), (3, 256, 1, 1)), ("sc", (64, 40, 30), (4, 64, 2, 3)),
-                 ("sc", (64, 40, 30), (4, 64, 4, 7))]
+                 ("sc", (64, 40, 30), (4, 64, 4, 7)), ("sc", (64, 40, 30), (5, 256, 2, 3)),
+                 ("sc", (64, 40, 30), (5, 128, 4, 2))]
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
@@ -252,7 +253,7 @@ def test_measuring_does_not_change_the_chain(M, case, prec):
     sims = []
     # the persistent kernel has no instantiation for strips of 1 or 8 rows or
     # for pair tiles
-    no_persistent = tile and ((tile[0] == 4 and tile[2] == 4) or
+    no_persistent = tile and ((tile[0] == 4 and tile[2] == 4) or (tile[0] == 5 and tile[2] == 4) or
                               (tile[0] == 1 and tile[2] in (1, 8)))
     modes = ("plain", "measured") if no_persistent else ("plain", "measured", "persistent")
     for mode in modes:
@@ -277,12 +278,14 @@ def test_measuring_does_not_change_the_chain(M, case, prec):
 
 
 PAIR_TILES = [(4, 64, 1, 5), (4, 128, 2, 3), (4, 64, 4, 34), (4, 256, 2, 7), (4, 192, 1, 1),
-              (4, 64, 2, 1)]
+              (4, 64, 2, 1), (5, 256, 2, 5), (5, 128, 4, 3), (5, 64, 2, 34), (5, 256, 4, 1),
+              (5, 192, 2, 2)]
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_pair_kernel_is_bitwise(M, prec):
-    """Two packed columns per thread (8/16-byte accesses): spins equal the
+    """Two packed columns per thread (8/16-byte accesses; strip and band
+    layouts): spins equal the
     default kernel's bitwise on rows of an even number of packed columns,
     including rows spread over several tiles, ragged rows and open faces."""
     import torch
@@ -311,9 +314,10 @@ def test_pair_kernel_is_bitwise(M, prec):
             assert o[r]["n_accepted"] == obs_r[r]["n_accepted"]
             assert abs(o[r]["E"] - obs_r[r]["E"]) <= 1e-9 * abs(o[r]["E"])
     odd = M.Simulation([M.Replica(kind="sc", L=(150, 14, 12))], precision=prec)
-    with pytest.raises(M.MCError) as ei:
-        odd.set_tile(64, 2, 3, kernel=4)
-    assert ei.value.status == -2
+    for k in (4, 5):
+        with pytest.raises(M.MCError) as ei:
+            odd.set_tile(64, 2, 3, kernel=k)
+        assert ei.value.status == -2
 
 
 LDS_CASES = [("sc", (16, 16, 16), 7, 0.0, "f64"), ("sc", (16, 16, 16), 7, 0.0, "f32"),
@@ -699,3 +703,22 @@ def test_autotune_keeps_chain_and_caches(M, tmp_path):
     assert c.autotune(trial_sweeps=2, measure=True, cache_path=cache) == tile
     assert c.get_sweep() == 0  # cache hit: no trial sweeps
     assert len(open(cache).read().splitlines()) == 1
+
+
+def test_stream_probe_pattern_and_errors(M):
+    """The memory-pattern probe reads both halves and writes the first in
+    place: after one untimed and two timed launches, first = first + 3 second."""
+    import torch
+
+    P = 1000
+    base = [torch.arange(2 * P, dtype=torch.float32, device="cuda") * (a + 1) for a in range(3)]
+    xs = [b.clone() for b in base]
+    ms = M.stream_probe(*xs, grid=3, reps=2)
+    assert ms > 0
+    for b, x in zip(base, xs):
+        want = b[:P] + 3 * b[P:]
+        assert torch.equal(x[:P], want) and torch.equal(x[P:], b[P:])
+    odd = [torch.zeros(2 * 7, dtype=torch.float32, device="cuda") for _ in range(3)]
+    with pytest.raises(M.MCError) as ei:
+        M.stream_probe(*odd)
+    assert ei.value.status == -1
