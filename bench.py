@@ -53,9 +53,12 @@ def measured_traffic(tile):
             d = json.load(f)
     except (OSError, ValueError):
         return None
-    if d.get("kernel_sha256_16") != kernel_hash() or list(d.get("tile", [])) != list(tile):
+    if d.get("kernel_sha256_16") != kernel_hash():
         return None
-    return d.get("bytes_per_pass_launch")
+    for e in d.get("entries", []):
+        if list(e.get("tile", [])) == list(tile):
+            return e.get("bytes_per_pass_launch")
+    return None
 
 
 def time_precision(M, W, prec, steps, warmup, tile=None):
