@@ -277,14 +277,13 @@ def run_c3(M, W, sweeps):
     scratch = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
     sim = M.Simulation(reps, precision="f32", seed=w["seed"], scratch=scratch)
     N = sum(sim.n_occ)
-    tile = sim.autotune(trial_sweeps=3, measure=True, persistent=True)
-    res = {"workload": w["name"], "replicas": len(reps), "spins": N, "sweeps": sweeps,
-           "tile": list(tile)}
-    sim.sweep(20, measure=True, persistent=True)
-    _, dt = _timed(lambda: sim.sweep(sweeps, measure=True, persistent=True))
-    res["persistent"] = {"s": dt, "updates_per_ns": N * sweeps / dt / 1e9}
-    _, dt = _timed(lambda: sim.sweep(sweeps, measure=True))
-    res["per_pass_launches"] = {"s": dt, "updates_per_ns": N * sweeps / dt / 1e9}
+    res = {"workload": w["name"], "replicas": len(reps), "spins": N, "sweeps": sweeps}
+    for mode, pers in (("per_pass_launches", False), ("persistent", True)):
+        tile = sim.autotune(trial_sweeps=3, measure=True, persistent=pers)
+        sim.sweep(20, measure=True, persistent=pers)
+        _, dt = _timed(lambda: sim.sweep(sweeps, measure=True, persistent=pers))
+        res[mode] = {"s": dt, "updates_per_ns": N * sweeps / dt / 1e9, "tile": list(tile)}
+        log(f"[bench] c3 {mode}: {res[mode]['updates_per_ns']:.1f} updates/ns, tile {tile}")
     return res
 
 
