@@ -389,6 +389,10 @@ def main():
                      "read2_write1_GBps": copy["read2_write1"]["GBps"],
                      # the pass's own access pattern with no arithmetic
                      "pattern_GBps": pat_gbps, "frac_of_pattern": ach / pat_gbps,
+                     # measured HBM bytes per pass (counters) over this run's pass time
+                     "traffic_GBps": traffic / (r32["pass_ms"] * 1e-3) / 1e9 if traffic else None,
+                     "traffic_frac": (traffic / (r32["pass_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBPS
+                                      if traffic else None),
                      # the same updates priced at the 24 B/update minimum (each
                      # spin read and written once per sweep)
                      "frac_at_24B_per_update": r32["value"] * 24.0 / HBM_PEAK_GBPS,
