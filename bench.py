@@ -24,7 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0           # MI355X HBM3E
-KERNEL_NAMES = ["tile", "strip", "band", "lds", "pair", "pband"]  # mc_set_tile kernel ids
+KERNEL_NAMES = ["tile", "strip", "band", "lds", "pair", "pband", "bstrip"]  # mc_set_tile ids
 BYTES_PER_UPDATE = {"f32": 36, "f64": 72}  # two-pass colour-packed: read own + other, write own
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sc_pass_f32_L464_traffic.json")
 # sources whose change invalidates the committed counter readings

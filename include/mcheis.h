@@ -245,7 +245,11 @@ mc_status mc_set_sweep(mc_sim *h, uint64_t t);
  *    columns, ty rows per thread (1, 2 or 4; persistent sweeps: 1 or 2);
  *  kernel 5 (sc only, even packed rows): as kernel 2 with two adjacent
  *    columns per thread: tx (64 .. 256) (band, pair) positions per workgroup,
- *    bands of ty rows (2 or 4; persistent sweeps: 2).
+ *    bands of ty rows (2 or 4; persistent sweeps: 2);
+ *  kernel 6 (bcc and fcc): tx lanes along x (64, 128, 192 or 256) times ty
+ *    rows (tx*ty <= 256), zc planes walked in z with the other basis sites'
+ *    planes kept in registers and the x neighbour taken from the adjacent
+ *    lane (persistent sweeps run the kernel-0 body on the same tile).
  * The spins do not depend on the choice (only the FP64 summation order of the
  * observables does).  A shape whose work list does not fit the handle's
  * scratch gives MC_E_BUFFER.  Choosing kernel 0-2 discards the record of the

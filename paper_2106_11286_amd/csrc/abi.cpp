@@ -222,6 +222,10 @@ mc_status check_tile(const Tile &t, int kind, uint64_t max_component_bytes)
             return fail(MC_E_ARG, "strip tile: tx must be 64, 128, 192 or 256 (got %d)", t.tx);
         if (t.ty != 1 && t.ty != 2 && t.ty != 4 && t.ty != 8)
             return fail(MC_E_ARG, "strip tile: ty (rows per thread) must be 1, 2, 4 or 8");
+    } else if (t.kernel == KERNEL_BSTRIP) {
+        if (kind == MC_SC) return fail(MC_E_ARG, "the basis strip kernel is for bcc and fcc lattices");
+        if (t.tx < 64 || t.tx > 256 || t.tx % 64 || t.ty < 1 || t.tx * t.ty > 256)
+            return fail(MC_E_ARG, "basis strip tile: tx must be 64, 128, 192 or 256 and tx*ty <= 256");
     } else if (t.kernel == KERNEL_TILE) {
         if (t.tx < 1 || t.ty < 1 || t.tx * t.ty > 256)
             return fail(MC_E_ARG, "tile %d x %d invalid (need >= 1 and tx*ty <= 256)", t.tx, t.ty);
@@ -1247,6 +1251,12 @@ std::vector<Tile> tile_candidates(const mc_sim *h)
         const int ty = std::min(256 / tx, pow2_at_least(Ly));
         base.push_back(Tile{KERNEL_TILE, tx, ty, 1});
     }
+    if (h->kind != MC_SC)
+        for (int tx : {64, 128, 256}) {
+            if (tx > 64 && tx / 2 >= W) continue;
+            base.push_back(Tile{KERNEL_BSTRIP, tx, 256 / tx, 1});
+            if (tx <= 128) base.push_back(Tile{KERNEL_BSTRIP, tx, 1, 1});
+        }
     std::vector<Tile> out;
     if (lds_fits(h))
         for (int threads : {256, 512, 1024}) out.push_back(Tile{KERNEL_LDS, threads, 1, 1});

@@ -238,7 +238,8 @@ MEASURE_CASES = [("sc", (64, 40, 30), None), ("sc", (64, 40, 30), (0, 16, 16, 1)
                  ("bcc", (9, 8, 7), (0, 8, 8, 2)), ("fcc", (7, 6, 5), (0, 8, 8, 1)),
                  ("sc", (16, 12, 10), (3, 256, 1, 1)), ("sc", (64, 40, 30), (4, 64, 2, 3)),
                  ("sc", (64, 40, 30), (4, 64, 4, 7)), ("sc", (64, 40, 30), (5, 256, 2, 3)),
-                 ("sc", (64, 40, 30), (5, 128, 4, 2))]
+                 ("sc", (64, 40, 30), (5, 128, 4, 2)), ("fcc", (70, 6, 5), (6, 64, 4, 2)),
+                 ("bcc", (9, 8, 7), (6, 64, 2, 3))]
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
@@ -318,6 +319,44 @@ def test_pair_kernel_is_bitwise(M, prec):
         with pytest.raises(M.MCError) as ei:
             odd.set_tile(64, 2, 3, kernel=k)
         assert ei.value.status == -2
+
+
+BSTRIP_TILES = [(6, 64, 1, 3), (6, 64, 4, 5), (6, 128, 2, 1), (6, 256, 1, 7), (6, 64, 2, 34)]
+
+
+@pytest.mark.parametrize("kind", ["bcc", "fcc"])
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_basis_strip_kernel_is_bitwise(M, kind, prec):
+    """bcc/fcc strip kernel (lanes along x, planes in registers, lane shifts):
+    spins equal the tile kernel's bitwise, on rows spanning several waves,
+    ragged rows and planes, open faces and the sphere."""
+    import torch
+
+    base = dict(kind=kind, J=1.0, K=0.15, e=(0.3, 0.5, 0.8))
+    reps = [M.Replica(L=(70, 9, 7), periodic_mask=7, T=1.1, replica_id=0, **base),
+            M.Replica(L=(130, 6, 5), periodic_mask=5, T=0.8, replica_id=1, **base),
+            M.Replica(L=(12, 10, 8), periodic_mask=0, sphere_radius=4.5, T=1.4, replica_id=2, **base),
+            M.Replica(L=(64, 7, 9), periodic_mask=2, T=1.7, replica_id=3, **base)]
+    ref = M.Simulation(reps, precision=prec, seed=17,
+                       scratch=torch.empty(16 << 20, dtype=torch.uint8, device="cuda"))
+    ref.set_tile(16, 16, 2, kernel=0)
+    ref.sweep(5, measure=True)
+    obs_r = ref.observables()
+    for tile in BSTRIP_TILES:
+        one = M.Simulation(reps, precision=prec, seed=17,
+                           scratch=torch.empty(16 << 20, dtype=torch.uint8, device="cuda"))
+        one.set_tile(tile[1], tile[2], tile[3], kernel=tile[0])
+        one.sweep(2)
+        one.sweep(3, measure=True)
+        o = one.observables()
+        for r in range(len(reps)):
+            for a, b in zip(natural(one, r), natural(ref, r)):
+                assert np.array_equal(a, b), (r, tile)
+            assert o[r]["n_accepted"] == obs_r[r]["n_accepted"], (r, tile)
+            assert abs(o[r]["E"] - obs_r[r]["E"]) <= 1e-9 * abs(o[r]["E"])
+    sc = M.Simulation([M.Replica(kind="sc", L=(16, 16, 16))], precision=prec)
+    with pytest.raises(M.MCError):
+        sc.set_tile(64, 1, 1, kernel=6)
 
 
 LDS_CASES = [("sc", (16, 16, 16), 7, 0.0, "f64"), ("sc", (16, 16, 16), 7, 0.0, "f32"),
