@@ -560,15 +560,23 @@ def torch_index(idx):
 
 
 def test_full_size_sc464_sampled(M):
-    """The benchmark lattice (sc L=464, 99,897,344 spins, FP32, default tiles):
-    after 100 sweeps, both colour passes of sweep 100 checked at 4096 sampled
+    """The benchmark lattice (sc L=464, 99,897,344 spins, FP32, the autotuned
+    tile the benchmark times): after the tuning sweeps and 100 more, both colour
+    passes of the next sweep checked at 4096 sampled
     sites each against the oracle's single-site evaluation from the same
     state, plus energy bookkeeping of the whole pass and fused-vs-recomputed
     observables."""
+    import torch
+
     w = W.C5_SC464_ROOFLINE
     rep = M.Replica(**W.replica_fields(w))
-    sim = M.Simulation([rep], precision="f32", seed=w["seed"])
-    assert sim.get_tile()[0] == 4  # the pair kernel the benchmark times
+    sim = M.Simulation([rep], precision="f32", seed=w["seed"],
+                       scratch=torch.empty(64 << 20, dtype=torch.uint8, device="cuda"))
+    assert sim.get_tile()[0] == 4  # default: the pair kernel
+    # the launch configuration the benchmark times: the autotuner's choice
+    tile = sim.autotune(trial_sweeps=6, measure=True)
+    print("autotuned tile", tile)
+    t0 = sim.get_sweep()
     sim.sweep(99)
     sim.sweep(1, measure=True)
     fused = sim.observables()[0]
@@ -580,7 +588,7 @@ def test_full_size_sc464_sampled(M):
     p = oracle_params(rep, w["seed"])
     rng = np.random.default_rng(464)
     t = sim.get_sweep()
-    assert t == 100
+    assert t == t0 + 100
     n_flip = 0
     for colour in (0, 1):
         before, after, dh, acc, nf = _sampled_pass(M, sim, rep, geo, p, t, colour, rng)
@@ -761,3 +769,26 @@ def test_stream_probe_pattern_and_errors(M):
     with pytest.raises(M.MCError) as ei:
         M.stream_probe(*odd)
     assert ei.value.status == -1
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+def test_schedule_measure_every(M, persistent):
+    """measure_every = 3 records every third sweep of the measurement phase;
+    each record equals the record of the same sweep in an every-sweep run."""
+    reps = [M.Replica(kind="sc", L=(40, 20, 12), K=0.1, T=1.0, replica_id=0),
+            M.Replica(kind="sc", L=(40, 20, 12), K=0.1, T=1.0, replica_id=1)]
+    T = [[1.2, 1.6], [0.9, 1.1]]
+    a = M.Simulation(reps, precision="f32", seed=31)
+    b = M.Simulation(reps, precision="f32", seed=31)
+    ra = a.run_schedule(T, n_equil=4, n_meas=12, measure_every=3, persistent=persistent)
+    rb = b.run_schedule(T, n_equil=4, n_meas=12, measure_every=1, persistent=persistent)
+    assert ra.shape == (2, 4, 2, 10) and rb.shape == (2, 12, 2, 10)
+    for i in range(2):
+        want = rb[i, 2::3]
+        # sweeps completed at records: 16 per temperature, 4 of them equilibration
+        sweeps = 16 * i + 4 + 3 * np.arange(1, 5)
+        assert np.array_equal(ra[i, :, :, 0], np.repeat(sweeps[:, None], 2, axis=1))
+        assert np.array_equal(ra[i], want)
+    for r in range(2):
+        for x, y in zip(natural(a, r), natural(b, r)):
+            assert np.array_equal(x, y)
