@@ -59,9 +59,9 @@ typedef enum { MC_INIT_RANDOM = 0, MC_INIT_ALIGNED = 1, MC_INIT_USER = 2 } mc_in
                          /* (sweep, colour, tile) are claimed in order by the resident */
                          /* workgroups, each replica advancing as soon as its previous */
                          /* pass is complete (no grid-wide barrier).  Results are      */
-                         /* bitwise identical to the default launches.  Strip tiles  */
-                         /* of 1 or 8 rows and pair tiles of 4 rows have no          */
-                         /* persistent kernel: MC_E_UNSUPPORTED.                      */
+                         /* bitwise identical to the default launches.  Tiles without */
+                         /* a persistent kernel (strips of 1 or 8 rows, pairs and     */
+                         /* bands of pairs of 4 rows) give MC_E_UNSUPPORTED.          */
 
 /* One replica: lattice geometry and model parameters (Eq. (1)).
  *  kind          sc / bcc / fcc conventional cubic cells.
@@ -151,7 +151,10 @@ mc_status mc_required_scratch(const mc_replica_desc *reps, int32_t n_reps, uint6
 
 /* Create a handle over n_reps replicas of one lattice kind and precision, and
  * write the initial state into the caller's buffers (unless MC_INIT_USER:
- * then the buffers already hold the state in the layout above).
+ * then the buffers already hold the state in the layout above).  The lattice
+ * and its parameters are those of Eq. (1) and of the paper's simulation-setup
+ * paragraph (cubic lattices, J, K, easy axis, T); the random start draws
+ * each spin uniformly on the sphere, the aligned start sets S = e.
  *  bufs[n_reps]  spin planes per replica (device memory);
  *  scratch       device memory of at least mc_required_scratch bytes, 256-byte
  *                aligned, owned by the caller, used only by this handle;
@@ -166,7 +169,10 @@ mc_status mc_init_lattice(const mc_replica_desc *reps, int32_t n_reps, mc_precis
                           void *scratch, uint64_t scratch_bytes, void *hip_stream, mc_sim **out);
 
 /* Enqueue n_sweeps sweeps of every replica (colour passes 0..C-1 each, sweep
- * counters t, t+1, ...).  With MC_MEASURE every sweep also reduces the FP64
+ * counters t, t+1, ...).  Each site of a pass takes the Metropolis step of
+ * the paper's Monte Carlo paragraph: field h = J sum of its neighbours' spins,
+ * a proposal S' uniform on the sphere, dH = -h.(S'-S) - K[(S'.e)^2 - (S.e)^2]
+ * from Eq. (1), acceptance if dH <= 0 or P <= exp(-dH/T), S <- S'/|S'|.  With MC_MEASURE every sweep also reduces the FP64
  * observables (fused into the passes; no extra spin traffic).  Asynchronous:
  * returns once the work is enqueued; device faults surface at the next
  * synchronising call. */
@@ -180,7 +186,8 @@ mc_status mc_sweep_timed(mc_sim *h, uint32_t n_sweeps, uint32_t flags, double *p
                          double *total_ms);
 
 /* Synchronise the stream and return the observables of the most recent
- * measured sweep of each replica (out[n_reps]).  MC_E_STATE if no sweep has
+ * measured sweep of each replica (out[n_reps]): the magnetisation of Eq. (2)
+ * and the two energy terms of Eq. (1).  MC_E_STATE if no sweep has
  * been measured since the handle was created. */
 mc_status mc_observables(mc_sim *h, mc_obs *out, int32_t n_reps);
 
@@ -188,7 +195,10 @@ mc_status mc_observables(mc_sim *h, mc_obs *out, int32_t n_reps);
  * all bonds, FP64), independent of the fused reduction.  Synchronises. */
 mc_status mc_measure_state(mc_sim *h, mc_obs *out, int32_t n_reps);
 
-/* Run a temperature schedule.  Sweeps are replayed as captured HIP graphs.
+/* Run a temperature schedule: at each temperature thermalise, then average
+ * (the paper's Monte Carlo and simulation-setup paragraphs: equilibration
+ * sweeps followed by measurement sweeps per temperature).  Sweeps are replayed
+ * as captured HIP graphs.
  * series receives the records in order [step][record][replica]; capacity is
  * its length in mc_obs elements and must be at least
  * n_T * (n_meas / measure_every) * n_reps.  n_written (may be NULL) receives
@@ -229,9 +239,8 @@ mc_status mc_set_sweep(mc_sim *h, uint64_t t);
  *    registers across planes;
  *  kernel 2 (sc only; the default for short or odd rows): as kernel 1, but
  *    rows grouped in bands of ty rows (2 or 4) and the (band, column)
- *    positions dealt to the tx threads
- *    contiguously, so no lane idles whatever the row length; a tile is tx
- *    positions x zc planes;
+ *    positions dealt to the tx threads contiguously, so no lane idles
+ *    whatever the row length; a tile is tx positions x zc planes;
  *  kernel 3 (any lattice whose three component planes fit one workgroup's
  *    LDS; the default then): whole sweeps in LDS, one workgroup of tx threads
  *    (64 .. 1024, multiple of 64) per replica, colour passes separated by
@@ -258,8 +267,8 @@ mc_status mc_set_tile(mc_sim *h, int32_t kernel, int32_t tx, int32_t ty, int32_t
 mc_status mc_get_tile(const mc_sim *h, int32_t *kernel, int32_t *tx, int32_t *ty, int32_t *zc,
                       uint64_t *n_items);
 
-/* Autotuner: time candidate kernels and tile shapes on the handle's own
- * lattices (trial_sweeps sweeps each, with `flags` as for mc_sweep) and keep
+/* Autotuner (a property of this implementation, not of the method): time
+ * candidate kernels and tile shapes on the handle's own lattices (trial_sweeps sweeps each, with `flags` as for mc_sweep) and keep
  * the fastest.  The trial sweeps are ordinary sweeps of the chain: they
  * advance the state and the sweep counter (results stay bitwise independent
  * of the shape).  cache_path (may be NULL) names a text file of earlier
@@ -274,7 +283,10 @@ mc_status mc_num_colours(const mc_sim *h, int32_t *n_colours);
 
 /* Equilibrium statistics of one replica's records (stride: elements between
  * consecutive records of that replica, e.g. n_reps for mc_run_schedule
- * output), at temperature T (used by C and chi). */
+ * output), at temperature T (used by C and chi): thermal averages of the
+ * Eq. (2) magnetisation and of the Eq. (1) energy per spin, with blocked
+ * errors; the Binder cumulant locates T_C as in the accuracy paragraph.
+ * MC_E_ARG for NULL pointers, n < 2 or stride < 1. */
 mc_status mc_series_stats(const mc_obs *series, uint64_t n, uint64_t stride, double T,
                           mc_stats *out);
 
