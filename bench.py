@@ -230,23 +230,24 @@ def run_c1(M, W, cpu):
     return res
 
 
-def run_c2(M, W):
-    """sc L=256 temperature ladder (17 T, 2000 + 2000 sweeps each, random
-    start, state carried up the ladder), FP32 and FP64 with independent seeds:
-    throughput and per-temperature averages with blocked errors."""
+def run_c2(M, W, init="random"):
+    """sc L=256 temperature ladder (17 T, 2000 + 2000 sweeps each, state
+    carried up the ladder; random start as configured, or aligned), FP32 and
+    FP64 with independent seeds: throughput and per-temperature averages with
+    blocked errors."""
     w = W.C2_SC256_TSWEEP
     rep = M.Replica(**W.replica_fields(w))
     Ts = list(w["T_ladder"])
     N = 256 ** 3
     res = {"workload": w["name"], "spins": N, "T": Ts, "n_equil": w["n_equil"],
-           "n_meas": w["n_meas"]}
+           "n_meas": w["n_meas"], "init": init}
     stats = {}
     for prec, seed in (("f32", w["seed"]), ("f64", w["seed"] + 100)):
         sim = M.Simulation([rep], precision=prec, seed=seed)
         tile = sim.autotune(trial_sweeps=4, measure=True)
         sim.set_sweep(0)
         sim.close()
-        sim = M.Simulation([rep], precision=prec, seed=seed)
+        sim = M.Simulation([rep], precision=prec, seed=seed, init=init)
         sim.set_tile(tile[1], tile[2], tile[3], kernel=tile[0])
         rec, dt = _timed(lambda: sim.run_schedule(Ts, w["n_equil"], w["n_meas"]))
         n_upd = N * len(Ts) * (w["n_equil"] + w["n_meas"])
@@ -315,6 +316,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--workload", default="c5", choices=["c5", "c1", "c2", "c3", "c4"],
                     help="c5 (default): the 10^8-spin headline; others print their own line")
+    ap.add_argument("--init", default="random", choices=["random", "aligned"],
+                    help="initial state of the c2 ladder")
     ap.add_argument("--tile", default=None,
                     help="kernel,tx,ty,zc for the FP32 leg instead of autotuning "
                          "(kernel 0 tile, 1 strip, 2 band)")
@@ -341,7 +344,7 @@ def main():
         if args.workload == "c1":
             out = run_c1(M, W, cpu=not args.no_cpu_baseline)
         elif args.workload == "c2":
-            out = run_c2(M, W)
+            out = run_c2(M, W, args.init)
         elif args.workload == "c3":
             out = run_c3(M, W, W.C3_BATCHED["sweeps"])
         else:
