@@ -83,14 +83,24 @@ def time_precision(M, W, prec, steps, warmup, tile=None):
     sim.synchronize()
     torch.cuda.synchronize()
     log(f"[bench] {prec}: timing {steps} sweeps")
+    # the timed steps run as (up to) five consecutive chunks, each timed with
+    # HIP events around every pass launch; the whole-run wall time gives value
+    chunks = [steps // 5 + (1 if i < steps % 5 else 0) for i in range(min(5, steps))]
     t0 = time.perf_counter()
-    pass_ms, total_ms = sim.sweep_timed(steps, measure=True)
+    parts = [sim.sweep_timed(c, measure=True) for c in chunks if c]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    done = [c for c in chunks if c]
+    pass_ms = sum(pm * c for (pm, _), c in zip(parts, done)) / sum(done)
+    total_ms = sum(tm for _, tm in parts)
+    chunk_rates = sorted(n * c / (tm * 1e6) for (_, tm), c in zip(parts, done))
+    median_rate = chunk_rates[len(chunk_rates) // 2]
     obs = sim.observables()[0]
     bpp = BYTES_PER_UPDATE[prec] * n / 2.0
     res = {
         "value": n * steps / (wall * 1e9),
+        "median_chunk_updates_per_ns": median_rate,
+        "chunks": len(done),
         "ms_per_step": wall * 1e3 / steps,
         "event_ms_per_step": total_ms / steps,
         "pass_ms": pass_ms,
@@ -298,10 +308,14 @@ def run_c4(M, W, sweeps):
     tile = sim.autotune(trial_sweeps=3, measure=True)
     sim.sweep(20, measure=True)
     _, dt = _timed(lambda: sim.sweep(sweeps, measure=True))
+    # the same measured sweeps replayed as captured graphs (schedule path)
+    sim.run_schedule([w["T"]], 0, 256)
+    _, dtg = _timed(lambda: sim.run_schedule([w["T"]], 0, sweeps))
     box = 4 * 128 ** 3
     return {"workload": w["name"], "spins": N, "box_sites": box, "sweeps": sweeps,
             "tile": list(tile), "s": dt, "updates_per_ns": N * sweeps / dt / 1e9,
-            "box_sites_per_ns": box * sweeps / dt / 1e9}
+            "box_sites_per_ns": box * sweeps / dt / 1e9,
+            "graph": {"s": dtg, "updates_per_ns": N * sweeps / dtg / 1e9}}
 
 
 def main():
