@@ -318,6 +318,97 @@ def run_c4(M, W, sweeps):
             "graph": {"s": dtg, "updates_per_ns": N * sweeps / dtg / 1e9}}
 
 
+F1_TEMPERATURES = (1.30, 1.32, 1.34, 1.36, 1.38, 1.40, 1.41, 1.42, 1.43, 1.44, 1.45, 1.46,
+                   1.48, 1.50)
+
+
+def run_f1(M, sizes, n_equil, n_meas, Ts=F1_TEMPERATURES, fit_max_T=1.42, K=0.01):
+    """The paper's accuracy experiment (accuracy paragraph, Fig. 3): sc L^3,
+    periodic, J = 1, K = 0.01 (or K as given), e = z, an ordered start at every temperature,
+    n_equil thermalisation and n_meas averaging sweeps.  All temperatures of
+    one size advance together as replicas of one simulation.  Reports <|m|>
+    and U4 with blocked / jackknife errors, fits <|m|> = A (Tc - T)^beta on
+    the largest lattice for T <= fit_max_T, and the Binder-cumulant crossings
+    of consecutive sizes."""
+    import numpy as np
+    import torch
+    from scipy.optimize import curve_fit
+
+    res = {"workload": "sc-accuracy-M(T)", "J": 1.0, "K": K, "n_equil": n_equil,
+           "n_meas": n_meas, "T": list(Ts), "sizes": {}}
+    chunk = 1000
+    for L in sizes:
+        reps = [M.Replica(kind="sc", L=(L, L, L), J=1.0, K=K, e=(0.0, 0.0, 1.0), T=T,
+                          replica_id=r) for r, T in enumerate(Ts)]
+        sim = M.Simulation(reps, precision="f32", seed=7 + L, init="aligned")
+        N = L ** 3
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tile = sim.autotune(trial_sweeps=2, measure=False)  # tuning sweeps count as thermalisation
+        while sim.get_sweep() < n_equil:
+            sim.sweep(min(chunk, n_equil - sim.get_sweep()))
+            sim.synchronize()
+            log(f"[bench] f1 L={L}: thermalisation {sim.get_sweep()}/{n_equil}")
+        recs = []
+        for done in range(0, n_meas, chunk):
+            k = min(chunk, n_meas - done)
+            recs.append(sim.run_schedule([list(Ts)], n_equil=0, n_meas=k)[0])
+            log(f"[bench] f1 L={L}: averaging {done + k}/{n_meas}")
+        dt = time.perf_counter() - t0
+        rec = np.concatenate(recs, axis=0)
+        rows = []
+        for r, T in enumerate(Ts):
+            st = M.series_stats(rec[:, r, :], N, T)
+            row = {k: st[k] for k in ("abs_m", "abs_m_err", "U4", "U4_err", "e", "e_err",
+                                       "acceptance")}
+            row["T"] = T
+            rows.append(row)
+        res["sizes"][str(L)] = {"rows": rows, "s": dt, "tile": list(tile),
+                                "updates_per_ns": N * len(Ts) * sim.get_sweep() / dt / 1e9}
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+    # M ~ A (Tc - T)^beta on the largest lattice, below fit_max_T
+    big = res["sizes"][str(max(sizes))]["rows"]
+    T = np.array([r["T"] for r in big if r["T"] <= fit_max_T])
+    m = np.array([r["abs_m"] for r in big if r["T"] <= fit_max_T])
+    dm = np.array([max(r["abs_m_err"], 1e-6) for r in big if r["T"] <= fit_max_T])
+    try:
+        def power(t, a, tc, b):
+            return a * np.clip(tc - t, 1e-9, None) ** b
+
+        p, cov = curve_fit(power, T, m, p0=(1.5, 1.445, 0.36), sigma=dm, absolute_sigma=True,
+                           maxfev=20000)
+        res["fit"] = {"L": max(sizes), "T_range": [float(T.min()), float(T.max())],
+                      "A": float(p[0]), "Tc": float(p[1]), "Tc_err": float(np.sqrt(cov[1, 1])),
+                      "beta": float(p[2]), "beta_err": float(np.sqrt(cov[2, 2]))}
+    except Exception as exc:  # a failed fit is reported, not fatal
+        res["fit"] = {"error": str(exc)}
+    # Binder crossings of consecutive sizes, as a bracket: from the highest
+    # temperature where U4(larger) - U4(smaller) is positive by more than two
+    # jackknife errors, to the first temperature above it where the difference
+    # is negative (above T_C a three-component order parameter gives U4 -> 4/9,
+    # and single noisy points there are not crossings); plus the linear
+    # interpolation inside the bracket
+    cross = []
+    sz = sorted(sizes)
+    for a, b in zip(sz, sz[1:]):
+        ra, rb = res["sizes"][str(a)]["rows"], res["sizes"][str(b)]["rows"]
+        d = np.array([y["U4"] - x["U4"] for x, y in zip(ra, rb)])
+        e = np.array([np.hypot(x["U4_err"], y["U4_err"]) for x, y in zip(ra, rb)])
+        j = next((k for k in range(len(Ts)) if d[k] < 0), None)
+        if j is None:
+            continue
+        sig = [k for k in range(j) if d[k] > 2 * e[k]]
+        if not sig:
+            continue
+        i = sig[-1]
+        tx = Ts[i] + (Ts[j] - Ts[i]) * d[i] / (d[i] - d[j])
+        cross.append({"sizes": [a, b], "bracket": [Ts[i], Ts[j]], "T": float(tx)})
+    res["binder_crossings"] = cross
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -328,8 +419,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
-    ap.add_argument("--workload", default="c5", choices=["c5", "c1", "c2", "c3", "c4"],
-                    help="c5 (default): the 10^8-spin headline; others print their own line")
+    ap.add_argument("--workload", default="c5", choices=["c5", "c1", "c2", "c3", "c4", "f1"],
+                    help="c5 (default): the 10^8-spin headline; others print their own line "
+                         "(f1: the paper's M(T) accuracy experiment)")
+    ap.add_argument("--f1-sizes", default="128,256,512")
+    ap.add_argument("--f1-sweeps", type=int, default=10000,
+                    help="thermalisation and averaging sweeps each")
+    ap.add_argument("--f1-K", type=float, default=0.01, help="anisotropy of the f1 lattices")
     ap.add_argument("--init", default="random", choices=["random", "aligned"],
                     help="initial state of the c2 ladder")
     ap.add_argument("--tile", default=None,
@@ -359,6 +455,9 @@ def main():
             out = run_c1(M, W, cpu=not args.no_cpu_baseline)
         elif args.workload == "c2":
             out = run_c2(M, W, args.init)
+        elif args.workload == "f1":
+            out = run_f1(M, [int(v) for v in args.f1_sizes.split(",")], args.f1_sweeps,
+                         args.f1_sweeps, K=args.f1_K)
         elif args.workload == "c3":
             out = run_c3(M, W, W.C3_BATCHED["sweeps"])
         else:
