@@ -318,6 +318,32 @@ def run_c4(M, W, sweeps):
             "graph": {"s": dtg, "updates_per_ns": N * sweeps / dtg / 1e9}}
 
 
+def run_big(M, L=1000, sweeps=20):
+    """One sc L^3 lattice of 10^9 spins (L = 1000, FP32, 12 GB): autotuned
+    throughput, and the fused FP64 observables of the last timed sweep against
+    a recomputation of the same state over every bond."""
+    import torch
+
+    rep = M.Replica(kind="sc", L=(L, L, L), J=1.0, K=0.02, e=(0.0, 0.0, 1.0), T=1.4)
+    sim = M.Simulation([rep], precision="f32", seed=5,
+                       scratch=torch.empty(64 << 20, dtype=torch.uint8, device="cuda"))
+    N = sim.n_occ[0]
+    default = sim.get_tile()
+    tile = sim.autotune(trial_sweeps=2, measure=True)
+    log(f"[bench] big L={L}: default tile {default}, autotuned {tile}")
+    sim.sweep(3, measure=True)
+    pass_ms, total_ms = sim.sweep_timed(sweeps, measure=True)
+    fused = sim.observables()[0]
+    full = sim.measure_state()[0]
+    dE = abs(fused["E"] - full["E"]) / abs(full["E"])
+    dM = float(max(abs(a - b) for a, b in zip(fused["M"], full["M"])))
+    return {"workload": f"sc-L{L}-1e9-spins", "spins": N, "bytes_state": 12 * N,
+            "default_tile": list(default), "tile": list(tile), "sweeps": sweeps,
+            "updates_per_ns": N * sweeps / (total_ms * 1e6), "pass_ms": pass_ms,
+            "algorithmic_GBps": 36 * N / 2 / (pass_ms * 1e-3) / 1e9,
+            "fused_vs_recomputed": {"E_rel": dE, "M_abs": dM, "ok": dE <= 1e-9 and dM <= 1e-12}}
+
+
 F1_TEMPERATURES = (1.30, 1.32, 1.34, 1.36, 1.38, 1.40, 1.41, 1.42, 1.43, 1.44, 1.45, 1.46,
                    1.48, 1.50)
 
@@ -419,7 +445,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
-    ap.add_argument("--workload", default="c5", choices=["c5", "c1", "c2", "c3", "c4", "f1"],
+    ap.add_argument("--workload", default="c5",
+                    choices=["c5", "c1", "c2", "c3", "c4", "f1", "big"],
                     help="c5 (default): the 10^8-spin headline; others print their own line "
                          "(f1: the paper's M(T) accuracy experiment)")
     ap.add_argument("--f1-sizes", default="128,256,512")
@@ -455,6 +482,8 @@ def main():
             out = run_c1(M, W, cpu=not args.no_cpu_baseline)
         elif args.workload == "c2":
             out = run_c2(M, W, args.init)
+        elif args.workload == "big":
+            out = run_big(M)
         elif args.workload == "f1":
             out = run_f1(M, [int(v) for v in args.f1_sizes.split(",")], args.f1_sweeps,
                          args.f1_sweeps, K=args.f1_K)

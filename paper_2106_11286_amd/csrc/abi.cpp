@@ -155,7 +155,9 @@ int z_chunk(const mc_replica_desc *reps, int n, const Tile &t)
     return (int)std::max<uint64_t>(1, std::min<uint64_t>(zc, planes));
 }
 
-Tile default_tile(const mc_replica_desc *reps, int n)
+// Default pass kernel and tile for replicas whose spins have `esz`-byte
+// elements.
+Tile default_tile(const mc_replica_desc *reps, int n, size_t esz)
 {
     int W = 1, Ly = 1, Wmin = 1 << 30;
     for (int r = 0; r < n; ++r) {
@@ -165,7 +167,7 @@ Tile default_tile(const mc_replica_desc *reps, int n)
     }
     Tile t;
     bool fits = true; // the strip kernel addresses each component array with 32-bit offsets
-    for (int r = 0; r < n; ++r) fits &= box_sites(reps[r]) * sizeof(double) <= 0xFFFFFFFFull;
+    for (int r = 0; r < n; ++r) fits &= box_sites(reps[r]) * esz <= 0xFFFFFFFFull;
     bool even = true; // every row holds an even number of packed columns
     for (int r = 0; r < n; ++r) even &= row_len(reps[r]) % 2 == 0;
     if (reps[0].kind == MC_SC && fits && even && Wmin >= 96) {
@@ -727,11 +729,16 @@ mc_status mc_required_scratch(const mc_replica_desc *reps, int32_t n_reps, uint6
         if (reps[r].kind != reps[0].kind)
             return fail(MC_E_ARG, "replica %d: all replicas must share one lattice kind", r);
     }
-    const Tile t = default_tile(reps, n_reps);
-    std::vector<WorkItem> work;
-    std::vector<uint32_t> b, e;
-    make_work(reps, n_reps, t, work, b, e);
-    *bytes = scratch_layout(n_reps, work.size(), n_colours_of(reps[0].kind)).total;
+    // the precision is not known here: the larger of the two default layouts
+    uint64_t need = 0;
+    for (size_t esz : {sizeof(float), sizeof(double)}) {
+        const Tile t = default_tile(reps, n_reps, esz);
+        std::vector<WorkItem> work;
+        std::vector<uint32_t> b, e;
+        make_work(reps, n_reps, t, work, b, e);
+        need = std::max(need, scratch_layout(n_reps, work.size(), n_colours_of(reps[0].kind)).total);
+    }
+    *bytes = need;
     return MC_OK;
 }
 
@@ -779,7 +786,7 @@ mc_status mc_init_lattice(const mc_replica_desc *reps, int32_t n_reps, mc_precis
     h->seed = seed;
     h->stream = (hipStream_t)hip_stream;
     h->desc.assign(reps, reps + n_reps);
-    h->tile = default_tile(reps, n_reps);
+    h->tile = default_tile(reps, n_reps, esz);
     h->pass_tile = h->tile;
     std::vector<uint32_t> b, e;
     make_work(reps, n_reps, h->pass_tile, h->work, b, e);
