@@ -27,9 +27,6 @@ HBM_PEAK_GBPS = 8000.0           # MI355X HBM3E
 KERNEL_NAMES = ["tile", "strip", "band", "lds", "pair", "pband", "bstrip"]  # mc_set_tile ids
 BYTES_PER_UPDATE = {"f32": 36, "f64": 72}  # two-pass colour-packed: read own + other, write own
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sc_pass_f32_L464_traffic.json")
-# sources whose change invalidates the committed counter readings
-KERNEL_SRCS = [os.path.join(ROOT, "paper_2106_11286_amd", "csrc", "kernels.hip"),
-               os.path.join(ROOT, "paper_2106_11286_amd", "build.py")]
 
 
 def log(msg):
@@ -37,8 +34,12 @@ def log(msg):
 
 
 def kernel_hash() -> str:
+    """Hash of every file the device code is built from (a change invalidates
+    the committed counter readings)."""
+    from paper_2106_11286_amd import build as B
+
     h = hashlib.sha256()
-    for path in KERNEL_SRCS:
+    for path in B.kernel_source_files():
         with open(path, "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]

@@ -14,7 +14,10 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmcheis.so")
-SOURCES = ["kernels.hip", "abi.cpp"]
+# device code: one translation unit per launch family (compiled in parallel)
+KERNEL_SOURCES = ["kernels_pass.hip", "kernels_persistent.hip", "kernels_lds.hip",
+                  "kernels_util.hip"]
+SOURCES = KERNEL_SOURCES + ["abi.cpp"]
 ARCH = os.environ.get("MCHEIS_ARCH", "gfx950")
 
 
@@ -25,10 +28,8 @@ def hipcc() -> str:
     return p
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source into ``libmcheis.so`` (always recompiles)."""
-    objdir = os.path.join(HERE, "_build")
-    os.makedirs(objdir, exist_ok=True)
+def compile_flags():
+    """(host-and-device flags, device flags) used for every source."""
     common = ["-std=c++17", "-O3", "-fPIC", "-I", INCLUDE, "-I", CSRC,
               "-Wall", "-Wno-unused-function"]
     dev = ["-x", "hip", "--offload-arch=" + ARCH,
@@ -39,14 +40,34 @@ def build(verbose: bool = False) -> str:
            # instantiation of a pass body (measured or not, any tile shape)
            # rounds the same way and the Markov chain does not depend on it
            "-ffp-contract=on"]
-    objs = []
-    for src in SOURCES:
+    return common, dev
+
+
+def kernel_source_files():
+    """Every file the device code is compiled from, plus this build script."""
+    names = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".hpp")))
+    return [os.path.join(CSRC, f) for f in names] + [os.path.abspath(__file__)]
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every source into ``libmcheis.so`` (always recompiles)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    common, dev = compile_flags()
+
+    def compile_one(src):
         obj = os.path.join(objdir, src + ".o")
         cmd = [hipcc()] + common + dev + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
-        objs.append(obj)
+        return obj
+
+    workers = max(1, min(len(SOURCES), os.cpu_count() or 1))
+    with ThreadPoolExecutor(max_workers=workers) as pool:
+        objs = list(pool.map(compile_one, SOURCES))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs
     if verbose:

@@ -1,4 +1,4 @@
-// launch.hpp -- host-callable launchers of the device kernels (kernels.hip).
+// launch.hpp -- host-callable launchers of the device kernels (kernels_*.hip).
 #pragma once
 
 #include <hip/hip_runtime_api.h>

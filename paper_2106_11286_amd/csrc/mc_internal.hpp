@@ -1,5 +1,5 @@
 // mc_internal.hpp -- structures shared by the host runtime (abi.cpp) and the
-// device kernels (kernels.hip).  Plain-old-data only: copied verbatim into the
+// device kernels (kernels_*.hip).  Plain-old-data only: copied verbatim into the
 // caller's scratch buffer.
 #pragma once
 

@@ -14,16 +14,29 @@ CSRC = os.path.join(ROOT, "paper_2106_11286_amd", "csrc")
 
 @pytest.fixture(scope="module")
 def asm(tmp_path_factory):
+    """Assembly of every device source, compiled with the library's own flags."""
     hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
     if not os.path.exists(hipcc):
         pytest.skip("hipcc not available")
-    out = str(tmp_path_factory.mktemp("isa") / "kernels.s")
-    subprocess.check_call([hipcc, "-std=c++17", "-O3", "-x", "hip", "--offload-arch=gfx950",
-                           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-                           "-fgpu-flush-denormals-to-zero", "-I", os.path.join(ROOT, "include"),
-                           "-I", CSRC, "--offload-device-only", "-S", "-o", out,
-                           os.path.join(CSRC, "kernels.hip")], stderr=subprocess.DEVNULL)
-    return open(out).read()
+    import sys
+
+    sys.path.insert(0, ROOT)
+    from concurrent.futures import ThreadPoolExecutor
+
+    from paper_2106_11286_amd import build as B
+
+    common, dev = B.compile_flags()
+    d = tmp_path_factory.mktemp("isa")
+
+    def one(src):
+        out = str(d / (src + ".s"))
+        subprocess.check_call([hipcc] + common + dev + ["--offload-device-only", "-S", "-o", out,
+                                                        os.path.join(CSRC, src)],
+                              stderr=subprocess.DEVNULL)
+        return open(out).read()
+
+    with ThreadPoolExecutor(max_workers=len(B.KERNEL_SOURCES)) as pool:
+        return "\n".join(pool.map(one, B.KERNEL_SOURCES))
 
 
 def test_no_scalar_memory_writes(asm):
