@@ -280,8 +280,9 @@ def run_c2(M, W, init="random"):
 
 def run_c3(M, W, sweeps):
     """64 sc replicas (L in {32, 48, 64, 96}, T 0.8 .. 2.0), FP32, all advanced
-    by one persistent launch per call; autotuned tile; also the same sweeps as
-    per-pass launches."""
+    by one persistent launch per call, with one work queue per XCD and with a
+    single queue; also the same sweeps as per-pass launches.  Each mode runs
+    on its own autotuned tile."""
     import torch
 
     w = W.C3_BATCHED
@@ -290,11 +291,17 @@ def run_c3(M, W, sweeps):
     sim = M.Simulation(reps, precision="f32", seed=w["seed"], scratch=scratch)
     N = sum(sim.n_occ)
     res = {"workload": w["name"], "replicas": len(reps), "spins": N, "sweeps": sweeps}
-    for mode, pers in (("per_pass_launches", False), ("persistent", True)):
+    for mode, pers, queues in (("per_pass_launches", False, None),
+                               ("persistent", True, "auto"),
+                               ("persistent_one_queue", True, "global")):
+        if queues:
+            sim.set_persistent_mode(queues)
         tile = sim.autotune(trial_sweeps=3, measure=True, persistent=pers)
         sim.sweep(20, measure=True, persistent=pers)
         _, dt = _timed(lambda: sim.sweep(sweeps, measure=True, persistent=pers))
         res[mode] = {"s": dt, "updates_per_ns": N * sweeps / dt / 1e9, "tile": list(tile)}
+        if queues:
+            res[mode]["queues"] = sim.persistent_queues()
         log(f"[bench] c3 {mode}: {res[mode]['updates_per_ns']:.1f} updates/ns, tile {tile}")
     return res
 

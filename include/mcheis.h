@@ -61,7 +61,8 @@ typedef enum { MC_INIT_RANDOM = 0, MC_INIT_ALIGNED = 1, MC_INIT_USER = 2 } mc_in
                          /* pass is complete (no grid-wide barrier).  Results are      */
                          /* bitwise identical to the default launches.  Tiles without */
                          /* a persistent kernel (strips of 1 or 8 rows, pairs and     */
-                         /* bands of pairs of 4 rows) give MC_E_UNSUPPORTED.          */
+                         /* bands of pairs of 4 rows) give MC_E_UNSUPPORTED.  Queues: */
+                         /* see mc_set_persistent_mode.                               */
 
 /* One replica: lattice geometry and model parameters (Eq. (1)).
  *  kind          sc / bcc / fcc conventional cubic cells.
@@ -292,10 +293,36 @@ mc_status mc_series_stats(const mc_obs *series, uint64_t n, uint64_t stride, dou
 
 /* Bounded wait of persistent launches: a work unit waiting for its replica's
  * previous pass gives up after `spins` polls (about 0.1 us each; default
- * 2^24).  A launch that gave up sets the handle's watchdog flag: the next
- * synchronising call returns MC_E_DEVICE and the spins of that call are
- * incomplete.  Every workgroup still exits normally. */
+ * 2^24).  A launch that gave up sets the handle's watchdog flag, which later
+ * launches keep: the next synchronising call returns MC_E_DEVICE (and clears
+ * the flag) and the spins of that call are incomplete.  Every workgroup still
+ * exits normally.  Waits for the handle's enqueued work first. */
 mc_status mc_set_watchdog(mc_sim *h, uint32_t spins);
+
+/* Work queues of persistent launches (MC_PERSISTENT).  The replicas of a
+ * handle are independent Markov chains, so a launch may serve each replica
+ * from one XCD:
+ *  MC_PERSIST_GLOBAL  one queue of all work units; a unit's spin stores are
+ *                     written back from its XCD's L2 before the replica's
+ *                     next pass may read them.
+ *  MC_PERSIST_XCD     eight queues: the replicas are dealt to the eight XCDs
+ *                     (largest first, each to the least loaded XCD, load =
+ *                     work units of a sweep) and only workgroups running on
+ *                     XCD g take units of queue g, so a replica's spins stay
+ *                     in one L2 for the whole launch and no write-back is
+ *                     needed.  Needs a device that deals workgroups to eight
+ *                     XCDs in turn (checked once per device when a handle is
+ *                     created); otherwise MC_E_UNSUPPORTED.
+ *  MC_PERSIST_AUTO    (default) XCD queues when the device allows them, the
+ *                     batch has at least 8 replicas and the most loaded queue
+ *                     holds at most 1.25 times the mean load; else one queue.
+ * Both give spins, records and observables bitwise identical to the default
+ * launches.  The choice applies to later persistent calls, also after
+ * mc_set_tile and mc_autotune (which re-deal the replicas); it drops captured
+ * graphs.  mc_get_persistent_queues returns the queues in effect (1 or 8). */
+typedef enum { MC_PERSIST_AUTO = 0, MC_PERSIST_GLOBAL = 1, MC_PERSIST_XCD = 2 } mc_persist_mode;
+mc_status mc_set_persistent_mode(mc_sim *h, mc_persist_mode mode);
+mc_status mc_get_persistent_queues(const mc_sim *h, int32_t *n_queues);
 
 /* Wait for all enqueued work of the handle and report deferred errors
  * (device faults, a tripped persistent-launch watchdog). */

@@ -14,6 +14,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <sstream>
 #include <new>
 #include <string>
@@ -303,8 +304,12 @@ void make_work(const mc_replica_desc *reps, int n, const Tile &t, std::vector<Wo
 
 struct ScratchLayout {
     uint64_t off_ctr, off_reps, off_work, off_partials, off_records, off_stage, off_count,
-        off_persist, total;
+        off_persist, off_queues, total;
 };
+
+// Words of the persistent-queue region: 16 queue offsets, then every item
+// index once (at least 64 words: it also takes the XCD probe's output).
+inline uint64_t queue_words(uint64_t n_items) { return 16 + std::max<uint64_t>(n_items, 64); }
 
 ScratchLayout scratch_layout(int n_reps, uint64_t n_items, int n_colours)
 {
@@ -327,6 +332,8 @@ ScratchLayout scratch_layout(int n_reps, uint64_t n_items, int n_colours)
     o = align_up(o + sizeof(uint32_t) * n_reps, 256);
     L.off_persist = o;
     o = align_up(o + sizeof(uint32_t) * persist_state_words(n_reps), 256);
+    L.off_queues = o;
+    o = align_up(o + sizeof(uint32_t) * queue_words(n_items), 256);
     L.total = o;
     return L;
 }
@@ -385,8 +392,13 @@ struct mc_sim {
     double *stage = nullptr;    // finalise stage slots
     uint32_t *fin_count = nullptr;
     uint32_t *pstate = nullptr; // persistent-launch counters
+    uint32_t *queues_dev = nullptr; // queue offsets [16], then queue items
     uint32_t spin_limit = 1u << 24;
     bool persist_used = false;
+    int persist_mode = MC_PERSIST_AUTO;
+    bool xcd_ok = false;            // workgroups are dealt to 8 XCDs in turn
+    uint32_t n_queues = 1, max_queue_items = 0;
+    std::vector<uint32_t> q_host;   // queue table as uploaded (offsets [16], items)
     double *host_rec = nullptr; // pinned, (kRing + 1) * n_reps * NR
     uint64_t t = 0;             // sweeps done
     uint64_t n_measured = 0;
@@ -477,6 +489,84 @@ mc_status enqueue_sweeps(mc_sim *h, uint32_t n, bool measure, uint32_t slot0)
     return MC_OK;
 }
 
+// Whether the device deals workgroups to its eight XCDs in turn (workgroup b
+// on XCD b mod 8), checked once per device with a 64-workgroup launch that
+// records each workgroup's XCD.  `buf` holds at least 64 words.
+bool device_deals_xcds(mc_sim *h, uint32_t *buf)
+{
+    static std::mutex mu;
+    static signed char known[64];
+    static bool init = false;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        (void)hipGetLastError();
+        return false;
+    }
+    std::lock_guard<std::mutex> lock(mu);
+    if (!init) {
+        std::memset(known, -1, sizeof known);
+        init = true;
+    }
+    if (known[dev] >= 0) return known[dev] == 1;
+    uint32_t v[64];
+    bool ok = launch_xcd_probe(buf, 64, h->stream) == hipSuccess &&
+              hipMemcpyAsync(v, buf, sizeof v, hipMemcpyDeviceToHost, h->stream) == hipSuccess &&
+              hipStreamSynchronize(h->stream) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        return false; // not cached: a later handle checks again
+    }
+    for (uint32_t b = 0; b < 64; ++b) ok = ok && v[b] == b % 8;
+    known[dev] = ok ? 1 : 0;
+    return ok;
+}
+
+// Deal the replicas to the persistent-launch queues (see
+// mc_set_persistent_mode) and upload the queue table.  Asynchronous on the
+// handle's stream; h->q_host stays alive until the next call.
+mc_status plan_queues(mc_sim *h)
+{
+    const int n = h->n_reps;
+    std::vector<uint64_t> load(n);
+    uint64_t sum = 0;
+    for (int r = 0; r < n; ++r) {
+        load[r] = h->reps[r].item_end - h->reps[r].item_begin;
+        sum += load[r];
+    }
+    std::vector<int> order(n), home(n, 0);
+    for (int r = 0; r < n; ++r) order[r] = r;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return load[a] > load[b]; });
+    uint64_t q_load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int r : order) {
+        int g = 0;
+        for (int k = 1; k < 8; ++k)
+            if (q_load[k] < q_load[g]) g = k;
+        home[r] = g;
+        q_load[g] += load[r];
+    }
+    const uint64_t max_load = *std::max_element(q_load, q_load + 8);
+    bool xcd = false;
+    if (h->persist_mode == MC_PERSIST_XCD) xcd = true;
+    else if (h->persist_mode == MC_PERSIST_AUTO)
+        xcd = h->xcd_ok && n >= 8 && 8 * max_load * 4 <= sum * 5; // max <= 1.25 x mean
+    h->n_queues = xcd ? 8 : 1;
+    h->max_queue_items = xcd ? (uint32_t)max_load : (uint32_t)sum;
+    h->q_host.assign(16 + h->work.size(), 0u);
+    uint32_t pos = 0;
+    for (int g = 0; g < 8; ++g) {
+        h->q_host[g] = pos;
+        for (int r = 0; r < n; ++r)
+            if (home[r] == g)
+                for (uint32_t it = h->reps[r].item_begin; it < h->reps[r].item_end; ++it)
+                    h->q_host[16 + pos++] = it;
+    }
+    h->q_host[8] = pos;
+    HIP_TRY(hipMemcpyAsync(h->queues_dev, h->q_host.data(), sizeof(uint32_t) * h->q_host.size(),
+                           hipMemcpyHostToDevice, h->stream));
+    return MC_OK;
+}
+
 // Tile shapes the persistent kernel is instantiated for.
 bool persistent_supported(const Tile &t)
 {
@@ -509,9 +599,16 @@ mc_status enqueue_persistent(mc_sim *h, uint32_t n, bool measure, uint32_t slot0
     a.records = h->records;
     a.ring = kRing;
     a.slot0 = slot0;
-    HIP_TRY(launch_zero_u32(h->pstate, persist_state_words(h->n_reps), h->stream));
+    a.n_queues = h->n_queues;
+    a.max_queue_items = h->max_queue_items;
+    a.q_off = h->queues_dev;
+    a.q_items = h->queues_dev + 16;
+    // clear the per-launch words (the sticky ones stay until read)
+    HIP_TRY(launch_zero_u32(h->pstate + PS_ABORT, persist_state_words(h->n_reps) - PS_ABORT,
+                            h->stream));
     HIP_TRY(launch_persistent(h->kind, h->prec == MC_F64, measure, pass_args(h, 0, n_items, 0), a,
                               h->stream));
+    HIP_TRY(launch_persist_check(a, n_items, h->stream));
     HIP_TRY(launch_advance(h->tctr, n, h->stream));
     h->persist_used = true;
     return MC_OK;
@@ -522,13 +619,21 @@ mc_status enqueue_persistent(mc_sim *h, uint32_t n, bool measure, uint32_t slot0
 mc_status check_persistent(mc_sim *h)
 {
     if (!h->persist_used) return MC_OK;
-    uint32_t hdr[4] = {0, 0, 0, 0};
+    uint32_t hdr[2] = {0, 0};
     HIP_TRY(hipMemcpy(hdr, h->pstate, sizeof hdr, hipMemcpyDeviceToHost));
     h->persist_used = false;
-    if (hdr[2])
+    if (hdr[PS_STICKY_WATCHDOG] || hdr[PS_STICKY_UNDRAINED]) {
+        HIP_TRY(launch_zero_u32(h->pstate, 2, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+    }
+    if (hdr[PS_STICKY_WATCHDOG])
         return fail(MC_E_DEVICE, "persistent sweep: a wait for a replica's previous pass exceeded "
                                  "%u spins; the state of that call is incomplete",
                     h->spin_limit);
+    if (hdr[PS_STICKY_UNDRAINED])
+        return fail(MC_E_DEVICE, "persistent sweep: a work queue was left with unclaimed units "
+                                 "(no workgroup ran on its XCD); the state of that call is "
+                                 "incomplete");
     return MC_OK;
 }
 
@@ -815,6 +920,7 @@ mc_status mc_init_lattice(const mc_replica_desc *reps, int32_t n_reps, mc_precis
     h->stage = (double *)(h->scratch + h->lay.off_stage);
     h->fin_count = (uint32_t *)(h->scratch + h->lay.off_count);
     h->pstate = (uint32_t *)(h->scratch + h->lay.off_persist);
+    h->queues_dev = (uint32_t *)(h->scratch + h->lay.off_queues);
 
     h->reps.resize(n_reps);
     h->n_occ.resize(n_reps);
@@ -851,7 +957,9 @@ mc_status mc_init_lattice(const mc_replica_desc *reps, int32_t n_reps, mc_precis
         h->host_rec = nullptr;
         return cleanup(fail(MC_E_DEVICE, "pinned host allocation failed"));
     }
+    h->xcd_ok = device_deals_xcds(h, h->queues_dev);
     mc_status s;
+    if ((s = plan_queues(h)) != MC_OK) return cleanup(s);
     if ((s = upload_reps(h)) != MC_OK) return cleanup(s);
     if (hipMemcpyAsync(h->work_dev, h->work.data(), sizeof(WorkItem) * h->work.size(),
                        hipMemcpyHostToDevice, h->stream) != hipSuccess ||
@@ -1104,9 +1212,36 @@ mc_status mc_run_schedule(mc_sim *h, const mc_schedule *s, mc_obs *series, uint6
     return MC_OK;
 }
 
+mc_status mc_set_persistent_mode(mc_sim *h, mc_persist_mode mode)
+{
+    if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
+    if (mode != MC_PERSIST_AUTO && mode != MC_PERSIST_GLOBAL && mode != MC_PERSIST_XCD)
+        return fail(MC_E_ARG, "unknown persistent mode %d", (int)mode);
+    if (mode == MC_PERSIST_XCD && !h->xcd_ok)
+        return fail(MC_E_UNSUPPORTED, "per-XCD queues: this device does not deal workgroups to "
+                                      "eight XCDs in turn");
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    for (auto &kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+    h->graphs.clear();
+    h->persist_mode = mode;
+    mc_status st = plan_queues(h);
+    if (st != MC_OK) return st;
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return MC_OK;
+}
+
+mc_status mc_get_persistent_queues(const mc_sim *h, int32_t *n_queues)
+{
+    if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
+    if (!n_queues) return fail(MC_E_ARG, "n_queues is NULL");
+    *n_queues = (int32_t)h->n_queues;
+    return MC_OK;
+}
+
 mc_status mc_set_watchdog(mc_sim *h, uint32_t spins)
 {
     if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
+    HIP_TRY(hipStreamSynchronize(h->stream)); // no captured graph may be in flight
     h->spin_limit = spins;
     for (auto &kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
     h->graphs.clear();
@@ -1199,6 +1334,8 @@ mc_status mc_set_tile(mc_sim *h, int32_t kernel, int32_t tx, int32_t ty, int32_t
         return fail(MC_E_BUFFER, "tile %d x %d x %d needs %llu scratch bytes, handle has %llu", tx,
                     ty, zc, (unsigned long long)lay.total, (unsigned long long)h->scratch_bytes);
     HIP_TRY(hipStreamSynchronize(h->stream));
+    // a deferred persistent-launch error lives in the state words that move
+    if ((st = check_persistent(h)) != MC_OK) return st;
     for (auto &kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
     h->graphs.clear();
     h->tile = t;
@@ -1212,14 +1349,17 @@ mc_status mc_set_tile(mc_sim *h, int32_t kernel, int32_t tx, int32_t ty, int32_t
     h->stage = (double *)(h->scratch + lay.off_stage);
     h->fin_count = (uint32_t *)(h->scratch + lay.off_count);
     h->pstate = (uint32_t *)(h->scratch + lay.off_persist);
+    h->queues_dev = (uint32_t *)(h->scratch + lay.off_queues);
     h->last_slot = -1;
     HIP_TRY(launch_zero_u32(h->fin_count, (uint32_t)h->n_reps, h->stream));
+    HIP_TRY(launch_zero_u32(h->pstate, persist_state_words(h->n_reps), h->stream));
     for (int r = 0; r < h->n_reps; ++r) {
         h->reps[r].item_begin = b[r];
         h->reps[r].item_end = e[r];
     }
     HIP_TRY(hipMemcpyAsync(h->work_dev, h->work.data(), sizeof(WorkItem) * h->work.size(),
                            hipMemcpyHostToDevice, h->stream));
+    if ((st = plan_queues(h)) != MC_OK) return st;
     return upload_reps(h);
 }
 
@@ -1304,7 +1444,9 @@ std::string tune_key(const mc_sim *h, uint32_t flags)
     }
     std::ostringstream k;
     k << "gfx950/kind" << h->kind << "/prec" << (int)h->prec << "/flags" << flags << "/reps"
-      << h->n_reps << "/" << std::hex << hash;
+      << h->n_reps;
+    if (flags & MC_PERSISTENT) k << "/queues" << h->persist_mode;
+    k << "/" << std::hex << hash;
     return k.str();
 }
 

@@ -160,6 +160,14 @@ __device__ __forceinline__ bool logical_item(const PassLaunch &P, uint32_t &item
     return l < P.n_blocks;
 }
 
+// The XCD (0..7) the calling wave runs on (hardware register XCC_ID).
+__device__ __forceinline__ uint32_t xcd_id()
+{
+    uint32_t v;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
+    return v & 7u;
+}
+
 // ---------------------------------------------------------------------------
 // Block reduction of Q_N doubles (fixed order: wave butterflies, then waves in
 // index order), written to one partial slot.

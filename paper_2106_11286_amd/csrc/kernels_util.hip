@@ -247,6 +247,18 @@ hipError_t launch_zero_u32(uint32_t *p, uint32_t n, hipStream_t st)
     return hipGetLastError();
 }
 
+__global__ void k_xcd_probe(uint32_t *out, uint32_t n)
+{
+    if (threadIdx.x == 0 && blockIdx.x < n) out[blockIdx.x] = xcd_id();
+}
+
+hipError_t launch_xcd_probe(uint32_t *out, uint32_t n, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_xcd_probe, dim3(n), dim3(64), 0, st, out, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_advance(uint32_t *tctr_dev, uint32_t n, hipStream_t st)
 {
     hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, st, tctr_dev, n);

@@ -52,16 +52,28 @@ hipError_t launch_zero_u32(uint32_t *p, uint32_t n, hipStream_t st);
 //   [0] next unit, [1] abort, [2] watchdog tripped, [3] unused,
 //   [4 .. 4+n_reps) items done per replica, [4+n_reps .. 4+2 n_reps) phases released.
 struct PersistLaunch {
-    uint32_t *state;
+    uint32_t *state;      // PERSIST_HDR header words, then done[n_reps], ready[n_reps]
     uint32_t n_sweeps, n_colours, n_reps;
     uint32_t spin_limit;  // bounded wait: spins of ~0.1 us before the watchdog trips
     double *records;      // ring [ring][n_reps][NR]
     uint32_t ring, slot0; // record slot of sweep s = (slot0 + s) % ring
+    // 1: one queue of all items in order; 8: queue g holds the items
+    // q_items[q_off[g] .. q_off[g+1]) and is served by XCD g only
+    uint32_t n_queues, max_queue_items;
+    const uint32_t *q_off, *q_items;
 };
-inline uint32_t persist_state_words(int n_reps) { return 4u + 2u * (uint32_t)n_reps; }
+// Header words.  Sticky (kept across launches until the host reads them):
+// a launch's bounded wait gave up; a launch left a queue undrained.  Per
+// launch (cleared before each): abort, wait gave up, claim counter of queue g.
+constexpr uint32_t PS_STICKY_WATCHDOG = 0, PS_STICKY_UNDRAINED = 1, PS_ABORT = 2, PS_TRIPPED = 3,
+                   PS_CLAIM = 4, PERSIST_HDR = 12;
+inline uint32_t persist_state_words(int n_reps) { return PERSIST_HDR + 2u * (uint32_t)n_reps; }
 
 hipError_t launch_persistent(int kind, bool f64, bool measure, const PassLaunch &p,
                              const PersistLaunch &a, hipStream_t st);
+// After a persistent launch over n_items items: fold its watchdog flag into
+// the sticky word and flag any queue whose units were not all claimed.
+hipError_t launch_persist_check(const PersistLaunch &a, uint32_t n_items, hipStream_t st);
 
 // Whole sweeps of small replicas in LDS: one workgroup per replica (every
 // replica's three planes, lds_bytes in all, fit one workgroup's LDS).
@@ -82,6 +94,8 @@ hipError_t lds_allow(int kind, bool f64, uint32_t bytes);
 // The HBM streams of a colour pass without its arithmetic (see mc_stream_probe).
 hipError_t launch_stream_probe(bool f64, void *x, void *y, void *z, uint64_t P, uint32_t grid,
                                hipStream_t st);
+// XCC_ID of workgroups 0..n-1 (thread 0 of each writes one word).
+hipError_t launch_xcd_probe(uint32_t *out, uint32_t n, hipStream_t st);
 hipError_t launch_advance(uint32_t *tctr_dev, uint32_t n, hipStream_t st);
 hipError_t launch_set_counter(uint32_t *tctr_dev, uint32_t v, hipStream_t st);
 hipError_t launch_fill_zero(double *p, uint64_t n, hipStream_t st);

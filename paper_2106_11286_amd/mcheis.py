@@ -105,6 +105,8 @@ _SIGNATURES = {
     "mc_series_stats": (ctypes.c_int, [ctypes.POINTER(Obs), ctypes.c_uint64, ctypes.c_uint64,
                                        ctypes.c_double, ctypes.POINTER(Stats)]),
     "mc_set_watchdog": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32]),
+    "mc_set_persistent_mode": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "mc_get_persistent_queues": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
     "mc_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_char_p,
                                    ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                    ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
@@ -307,6 +309,20 @@ class Simulation:
 
     def set_watchdog(self, spins: int):
         _check("mc_set_watchdog", LIB.mc_set_watchdog(self.handle, int(spins)))
+
+    PERSIST_MODES = {"auto": 0, "global": 1, "xcd": 2}
+
+    def set_persistent_mode(self, mode: str):
+        """``mc_set_persistent_mode``: work queues of persistent launches,
+        "auto", "global" (one queue) or "xcd" (one queue per XCD)."""
+        _check("mc_set_persistent_mode",
+               LIB.mc_set_persistent_mode(self.handle, self.PERSIST_MODES[mode]))
+
+    def persistent_queues(self) -> int:
+        """Queues a persistent launch uses now (1 or 8)."""
+        n = ctypes.c_int32()
+        _check("mc_get_persistent_queues", LIB.mc_get_persistent_queues(self.handle, ctypes.byref(n)))
+        return int(n.value)
 
     def sweep_timed(self, n: int, measure: bool = False):
         """``mc_sweep_timed``: (mean ms per colour-pass launch, total ms)."""

@@ -728,6 +728,106 @@ def test_persistent_watchdog_exits_cleanly(M):
     assert all(x["n_sites"] > 0 for x in o)
 
 
+def _xcd_batch(M, kind, n=16):
+    """n replicas of four sizes and temperatures from 0.8 to 2.0."""
+    if kind == "sc":
+        Ls = [(40, 40, 40), (32, 32, 32), (24, 24, 24), (16, 16, 16)]
+    else:
+        Ls = [(10, 10, 10), (8, 9, 7), (7, 7, 7), (5, 6, 5)]
+    return [M.Replica(kind=kind, L=Ls[r % 4], J=1.0, K=0.1, e=(0.0, 0.0, 1.0),
+                      T=0.8 + 1.2 * r / max(n - 1, 1), replica_id=r) for r in range(n)]
+
+
+def _queues(M, sim, mode):
+    try:
+        sim.set_persistent_mode(mode)
+    except M.MCError as e:
+        if mode == "xcd" and e.status == -2:
+            pytest.skip("device does not deal workgroups to eight XCDs in turn")
+        raise
+    return sim.persistent_queues()
+
+
+@pytest.mark.parametrize("kind,prec,tile,n", [
+    ("sc", "f32", None, 16), ("sc", "f32", (5, 256, 2, 7), 16), ("sc", "f32", (0, 32, 8, 4), 16),
+    ("sc", "f64", (1, 64, 4, 3), 16), ("sc", "f32", None, 5),
+    ("bcc", "f32", (0, 16, 16, 1), 16), ("fcc", "f64", (0, 16, 16, 1), 16)])
+def test_xcd_queues_match_eager(M, kind, prec, tile, n):
+    """Persistent launches with one queue per XCD and with one queue give the
+    default launches' chain: spins bitwise equal after three measured calls of
+    5 sweeps, the same acceptance counts and energies; the two queue modes
+    also give bitwise equal records.  Five replicas leave three queues empty."""
+    import torch
+
+    reps = _xcd_batch(M, kind, n)
+    sims = [M.Simulation(reps, precision=prec, seed=41,
+                         scratch=torch.empty(16 << 20, dtype=torch.uint8, device="cuda"))
+            for _ in range(3)]
+    if tile is not None:
+        for s in sims:
+            s.set_tile(tile[1], tile[2], tile[3], kernel=tile[0])
+    assert _queues(M, sims[0], "xcd") == 8
+    assert _queues(M, sims[1], "global") == 1
+    eager = sims[2]
+    for rnd in range(3):
+        for s in sims[:2]:
+            s.sweep(5, measure=True, persistent=True)
+        eager.sweep(5, measure=True)
+        oe = eager.observables()
+        for s in sims[:2]:
+            for x, y in zip(s.observables(), oe):
+                assert x["sweep"] == y["sweep"] and x["n_accepted"] == y["n_accepted"]
+                assert abs(x["E"] - y["E"]) <= 1e-12 * abs(y["E"])
+                assert np.max(np.abs(x["M"] - y["M"])) <= 1e-14
+    for r in range(n):
+        ref = natural(eager, r)
+        for s in sims[:2]:
+            for x, y in zip(natural(s, r), ref):
+                assert np.array_equal(x, y), r
+    T = np.linspace(0.9, 1.9, n)
+    rx = sims[0].run_schedule(T, n_equil=3, n_meas=6, persistent=True)
+    rg = sims[1].run_schedule(T, n_equil=3, n_meas=6, persistent=True)
+    assert np.array_equal(rx, rg)
+    for s in sims:
+        s.close()
+
+
+def test_xcd_queue_auto_and_retile(M):
+    """Auto mode takes per-XCD queues for 16 balanced replicas and one queue
+    for 2; a tile change re-deals the replicas and keeps the chain."""
+    reps = _xcd_batch(M, "sc", 16)
+    a = M.Simulation(reps, precision="f32", seed=43)
+    b = M.Simulation(reps, precision="f32", seed=43)
+    q = _queues(M, a, "auto")
+    if q != 8:
+        pytest.skip("device does not deal workgroups to eight XCDs in turn")
+    assert M.Simulation(reps[:2], precision="f32", seed=43).persistent_queues() == 1
+    a.sweep(3, persistent=True)
+    a.set_tile(32, 8, 4, kernel=0)
+    assert a.persistent_queues() == 8
+    a.sweep(4, measure=True, persistent=True)
+    b.sweep(7, measure=True)
+    for r in range(len(reps)):
+        for x, y in zip(natural(a, r), natural(b, r)):
+            assert np.array_equal(x, y), r
+
+
+def test_persistent_watchdog_is_sticky(M):
+    """A launch that gave up is reported even when another persistent launch
+    followed it before the synchronising call."""
+    reps = _batch(M)[:2]
+    sim = M.Simulation(reps, precision="f32", seed=5)
+    sim.set_watchdog(0)
+    sim.sweep(40, persistent=True)
+    sim.set_watchdog(1 << 24)
+    sim.sweep(2, persistent=True)
+    with pytest.raises(M.MCError) as ei:
+        sim.synchronize_checked()
+    assert ei.value.status == -4 and "persistent" in str(ei.value)
+    sim.sweep(2, persistent=True)
+    sim.synchronize_checked()
+
+
 def test_autotune_keeps_chain_and_caches(M, tmp_path):
     """The autotuner's trials are ordinary sweeps: after it, the state equals a
     plain run of the same number of sweeps; a second call hits the cache."""
