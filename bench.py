@@ -24,7 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0           # MI355X HBM3E
-KERNEL_NAMES = ["tile", "strip", "band", "lds", "pair", "pband", "bstrip"]  # mc_set_tile ids
+KERNEL_NAMES = ["tile", "strip", "band", "lds", "pair", "pband", "bstrip", "bpair"]  # mc_set_tile ids
 BYTES_PER_UPDATE = {"f32": 36, "f64": 72}  # two-pass colour-packed: read own + other, write own
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sc_pass_f32_L464_traffic.json")
 
@@ -352,6 +352,43 @@ def run_big(M, L=1000, sweeps=20):
             "fused_vs_recomputed": {"E_rel": dE, "M_abs": dM, "ok": dE <= 1e-9 and dM <= 1e-12}}
 
 
+def run_bcc(M, W, sweeps):
+    """bcc at the 10^8 scale (2 x 368^3 = 99,672,064 spins, periodic): FP32 and
+    FP64 throughput on autotuned tiles, algorithmic bandwidth of a basis pass
+    (own basis read and written, the other basis read: 36 B per update FP32,
+    72 B FP64), and the fused FP64 observables against a recomputation."""
+    import torch
+
+    w = W.BCC_368_1E8
+    rep = M.Replica(**W.replica_fields(w))
+    res = {"workload": w["name"], "sweeps": sweeps}
+    for prec, bpu in (("f32", 36), ("f64", 72)):
+        sim = M.Simulation([rep], precision=prec, seed=w["seed"],
+                           scratch=torch.empty(64 << 20, dtype=torch.uint8, device="cuda"))
+        N = sim.n_occ[0]
+        default = sim.get_tile()
+        tile = sim.autotune(trial_sweeps=2, measure=True)
+        sim.sweep(5, measure=True)
+        pass_ms, total_ms = sim.sweep_timed(sweeps, measure=True)
+        fused = sim.observables()[0]
+        full = sim.measure_state()[0]
+        dE = abs(fused["E"] - full["E"]) / abs(full["E"])
+        dM = float(max(abs(a - b) for a, b in zip(fused["M"], full["M"])))
+        gbps = bpu * N / 2 / (pass_ms * 1e-3) / 1e9
+        res["spins"] = N
+        res[prec] = {"default_tile": list(default), "tile": list(tile),
+                     "updates_per_ns": N * sweeps / (total_ms * 1e6), "pass_ms": pass_ms,
+                     "algorithmic_GBps": gbps, "frac_of_8TBps": gbps / 8000.0,
+                     "acceptance": fused["n_accepted"] / N,
+                     "fused_vs_recomputed": {"E_rel": dE, "M_abs": dM,
+                                             "ok": dE <= 1e-9 and dM <= 1e-12}}
+        log(f"[bench] bcc {prec}: {res[prec]['updates_per_ns']:.1f} updates/ns, tile {tile}, "
+            f"pass {pass_ms * 1e3:.1f} us, {gbps:.0f} GB/s algorithmic")
+        sim.close()
+        del sim
+    return res
+
+
 F1_TEMPERATURES = (1.30, 1.32, 1.34, 1.36, 1.38, 1.40, 1.41, 1.42, 1.43, 1.44, 1.45, 1.46,
                    1.48, 1.50)
 
@@ -454,7 +491,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--workload", default="c5",
-                    choices=["c5", "c1", "c2", "c3", "c4", "f1", "big"],
+                    choices=["c5", "c1", "c2", "c3", "c4", "f1", "big", "bcc"],
                     help="c5 (default): the 10^8-spin headline; others print their own line "
                          "(f1: the paper's M(T) accuracy experiment)")
     ap.add_argument("--f1-sizes", default="128,256,512")
@@ -492,6 +529,8 @@ def main():
             out = run_c2(M, W, args.init)
         elif args.workload == "big":
             out = run_big(M)
+        elif args.workload == "bcc":
+            out = run_bcc(M, W, W.BCC_368_1E8["sweeps"])
         elif args.workload == "f1":
             out = run_f1(M, [int(v) for v in args.f1_sizes.split(",")], args.f1_sweeps,
                          args.f1_sweeps, K=args.f1_K)

@@ -259,7 +259,13 @@ mc_status mc_set_sweep(mc_sim *h, uint64_t t);
  *  kernel 6 (bcc and fcc): tx lanes along x (64, 128, 192 or 256) times ty
  *    rows (tx*ty <= 256), zc planes walked in z with the other basis sites'
  *    planes kept in registers and the x neighbour taken from the adjacent
- *    lane (persistent sweeps run the kernel-0 body on the same tile).
+ *    lane (persistent sweeps run the kernel-0 body on the same tile);
+ *  kernel 7 (bcc and fcc, every replica with Lx even; the default then, up
+ *    to 4 GiB per spin component array): two adjacent cells of one basis per
+ *    thread (one 8-byte FP32 / 16-byte FP64 access per component), bands of
+ *    ty rows (1 or 2), tx (64 .. 256) (band, pair) positions per workgroup,
+ *    zc planes walked in z with the other bases' rows kept in registers.  A
+ *    larger array or an odd Lx gives MC_E_UNSUPPORTED.
  * The spins do not depend on the choice (only the FP64 summation order of the
  * observables does).  A shape whose work list does not fit the handle's
  * scratch gives MC_E_BUFFER.  Choosing kernel 0-2 discards the record of the

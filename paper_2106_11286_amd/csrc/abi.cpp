@@ -135,8 +135,8 @@ int pow2_at_least(int v)
 // Workgroup tiles covering one z plane of a replica.
 uint64_t xy_tiles(const mc_replica_desc &d, const Tile &t)
 {
-    if (t.kernel == KERNEL_BAND || t.kernel == KERNEL_PBAND) {
-        const int cols = t.kernel == KERNEL_PBAND ? row_len(d) / 2 : row_len(d);
+    if (t.kernel == KERNEL_BAND || t.kernel == KERNEL_PBAND || t.kernel == KERNEL_BPAIR) {
+        const int cols = t.kernel == KERNEL_BAND ? row_len(d) : row_len(d) / 2;
         const uint64_t F = (uint64_t)((d.Ly + t.ty - 1) / t.ty) * cols;
         return (F + t.tx - 1) / t.tx;
     }
@@ -169,7 +169,7 @@ Tile default_tile(const mc_replica_desc *reps, int n, size_t esz)
     Tile t;
     bool fits = true; // the strip kernel addresses each component array with 32-bit offsets
     for (int r = 0; r < n; ++r) fits &= box_sites(reps[r]) * esz <= 0xFFFFFFFFull;
-    bool even = true; // every row holds an even number of packed columns
+    bool even = true; // every row holds an even number of packed columns (sc) or cells
     for (int r = 0; r < n; ++r) even &= row_len(reps[r]) % 2 == 0;
     if (reps[0].kind == MC_SC && fits && even && Wmin >= 96) {
         // long rows: two columns per thread, 2 rows per thread, whole rows
@@ -182,6 +182,12 @@ Tile default_tile(const mc_replica_desc *reps, int n, size_t esz)
         t.kernel = KERNEL_BAND;
         t.tx = 256;
         t.ty = 2;
+    } else if (reps[0].kind != MC_SC && fits && even) {
+        // bcc / fcc: bands of cell pairs (fcc keeps one row per band: three
+        // other bases' rows in registers)
+        t.kernel = KERNEL_BPAIR;
+        t.tx = 256;
+        t.ty = reps[0].kind == MC_FCC ? 1 : 2;
     } else {
         t.kernel = KERNEL_TILE;
         t.tx = std::min(64, pow2_at_least(W));
@@ -225,6 +231,14 @@ mc_status check_tile(const Tile &t, int kind, uint64_t max_component_bytes)
             return fail(MC_E_ARG, "strip tile: tx must be 64, 128, 192 or 256 (got %d)", t.tx);
         if (t.ty != 1 && t.ty != 2 && t.ty != 4 && t.ty != 8)
             return fail(MC_E_ARG, "strip tile: ty (rows per thread) must be 1, 2, 4 or 8");
+    } else if (t.kernel == KERNEL_BPAIR) {
+        if (kind == MC_SC) return fail(MC_E_ARG, "the basis pair kernel is for bcc and fcc lattices");
+        if (max_component_bytes > 0xFFFFFFFFull)
+            return fail(MC_E_UNSUPPORTED, "basis pair kernel: a spin component array exceeds 4 GiB");
+        if (t.tx < 64 || t.tx > 256 || t.tx % 64)
+            return fail(MC_E_ARG, "basis pair tile: tx must be 64, 128, 192 or 256 (got %d)", t.tx);
+        if (t.ty != 1 && t.ty != 2)
+            return fail(MC_E_ARG, "basis pair tile: ty (rows per band) must be 1 or 2");
     } else if (t.kernel == KERNEL_BSTRIP) {
         if (kind == MC_SC) return fail(MC_E_ARG, "the basis strip kernel is for bcc and fcc lattices");
         if (t.tx < 64 || t.tx > 256 || t.tx % 64 || t.ty < 1 || t.tx * t.ty > 256)
@@ -260,9 +274,9 @@ void make_work(const mc_replica_desc *reps, int n, const Tile &t, std::vector<Wo
         begin[r] = (uint32_t)work.size();
         const int W = row_len(d);
         const bool sc = d.kind == MC_SC;
-        if (t.kernel == KERNEL_BAND || t.kernel == KERNEL_PBAND) {
+        if (t.kernel == KERNEL_BAND || t.kernel == KERNEL_PBAND || t.kernel == KERNEL_BPAIR) {
             const int rows = t.ty;
-            const int cols = t.kernel == KERNEL_PBAND ? W / 2 : W; // positions per row
+            const int cols = t.kernel == KERNEL_BAND ? W : W / 2; // positions per row
             const int F = (d.Ly + rows - 1) / rows * cols;
             for (int z0 = 0; z0 < d.Lz; z0 += t.zc)
                 for (int f0 = 0; f0 < F; f0 += t.tx) {
@@ -572,6 +586,7 @@ bool persistent_supported(const Tile &t)
 {
     if (t.kernel == KERNEL_PAIR) return t.ty == 1 || t.ty == 2;
     if (t.kernel == KERNEL_PBAND) return t.ty == 2;
+    if (t.kernel == KERNEL_BPAIR) return t.ty == 1 || t.ty == 2;
     return t.kernel != KERNEL_STRIP || t.ty == 2 || t.ty == 4;
 }
 
@@ -1321,11 +1336,12 @@ mc_status mc_set_tile(mc_sim *h, int32_t kernel, int32_t tx, int32_t ty, int32_t
                                                       (h->prec == MC_F64 ? 8u : 4u));
     mc_status st = check_tile(t, h->kind, max_bytes);
     if (st != MC_OK) return st;
-    if (kernel == KERNEL_PAIR || kernel == KERNEL_PBAND)
+    if (kernel == KERNEL_PAIR || kernel == KERNEL_PBAND || kernel == KERNEL_BPAIR)
         for (int r = 0; r < h->n_reps; ++r)
             if (row_len(h->desc[r]) % 2)
                 return fail(MC_E_UNSUPPORTED, "pair kernels: replica %d has an odd number (%d) of "
-                                              "packed columns per row", r, row_len(h->desc[r]));
+                                              "%s per row", r, row_len(h->desc[r]),
+                            h->kind == MC_SC ? "packed columns" : "cells");
     std::vector<WorkItem> work;
     std::vector<uint32_t> b, e;
     make_work(h->desc.data(), h->n_reps, t, work, b, e);
@@ -1398,12 +1414,20 @@ std::vector<Tile> tile_candidates(const mc_sim *h)
         const int ty = std::min(256 / tx, pow2_at_least(Ly));
         base.push_back(Tile{KERNEL_TILE, tx, ty, 1});
     }
-    if (h->kind != MC_SC)
+    if (h->kind != MC_SC) {
         for (int tx : {64, 128, 256}) {
             if (tx > 64 && tx / 2 >= W) continue;
             base.push_back(Tile{KERNEL_BSTRIP, tx, 256 / tx, 1});
             if (tx <= 128) base.push_back(Tile{KERNEL_BSTRIP, tx, 1, 1});
         }
+        bool even = true;
+        for (const auto &d : h->desc) even &= d.Lx % 2 == 0;
+        if (even)
+            for (int ry : {1, 2}) {
+                base.push_back(Tile{KERNEL_BPAIR, 256, ry, 1});
+                base.push_back(Tile{KERNEL_BPAIR, 128, ry, 1});
+            }
+    }
     std::vector<Tile> out;
     if (lds_fits(h))
         for (int threads : {256, 512, 1024}) out.push_back(Tile{KERNEL_LDS, threads, 1, 1});

@@ -165,6 +165,9 @@ hipError_t launch_pass(int kind, bool f64, int colour, bool measure, int mode, c
                        hipStream_t st)
 {
     if (p.n_blocks == 0) return hipSuccess;
+    if (mode == 2 && (!p.dbg_dh || !p.dbg_acc)) return hipErrorInvalidValue;
+    if (kind != SC && p.tile.kernel == KERNEL_BPAIR)
+        return launch_basis_pair(kind, f64, colour, measure, mode, p, st);
     if (mode == 1) {
         return f64 ? pass_dispatch<double, true, 1>(kind, colour, p, st)
                    : pass_dispatch<float, true, 1>(kind, colour, p, st);

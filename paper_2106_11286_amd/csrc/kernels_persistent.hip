@@ -29,6 +29,17 @@ __device__ __forceinline__ void unit_body(const PassLaunch &P, int c, uint32_t i
         else if constexpr (KERNEL == KERNEL_PAIR) sc_pair_body<T, MEASURE, 0, RY>(P, c, item, t);
         else if constexpr (KERNEL == KERNEL_PBAND) sc_pband_body<T, MEASURE, 0, RY>(P, c, item, t);
         else sc_tile_body<T, MEASURE, 0>(P, c, item, t);
+    } else if constexpr (KERNEL == KERNEL_BPAIR) {
+        switch (c) {
+        case 0: basis_pair_body<KIND, 0, T, MEASURE, 0, RY>(P, item, t); break;
+        case 1: basis_pair_body<KIND, 1, T, MEASURE, 0, RY>(P, item, t); break;
+        case 2:
+            if constexpr (KIND == FCC) basis_pair_body<KIND, 2, T, MEASURE, 0, RY>(P, item, t);
+            break;
+        default:
+            if constexpr (KIND == FCC) basis_pair_body<KIND, 3, T, MEASURE, 0, RY>(P, item, t);
+            break;
+        }
     } else {
         switch (c) {
         case 0: basis_body<KIND, 0, T, MEASURE, 0>(P, item, t); break;
@@ -184,7 +195,19 @@ static hipError_t persist_dispatch(int kind, const PassLaunch &p, const PersistL
     const bool tile_shaped = p.tile.kernel == KERNEL_TILE || p.tile.kernel == KERNEL_BSTRIP;
     const int threads = tile_shaped ? ((p.tile.tx * p.tile.ty + 63) / 64) * 64 : p.tile.tx;
     const dim3 g(grid), b(threads);
-    if (kind == BCC) {
+    if (kind != SC && p.tile.kernel == KERNEL_BPAIR) {
+        const dim3 bp(p.tile.tx);
+        if (kind == BCC && p.tile.ty == 1)
+            hipLaunchKernelGGL((k_persistent<T, MEASURE, BCC, KERNEL_BPAIR, 1>), g, bp, 0, st, p, a);
+        else if (kind == BCC && p.tile.ty == 2)
+            hipLaunchKernelGGL((k_persistent<T, MEASURE, BCC, KERNEL_BPAIR, 2>), g, bp, 0, st, p, a);
+        else if (kind == FCC && p.tile.ty == 1)
+            hipLaunchKernelGGL((k_persistent<T, MEASURE, FCC, KERNEL_BPAIR, 1>), g, bp, 0, st, p, a);
+        else if (kind == FCC && p.tile.ty == 2)
+            hipLaunchKernelGGL((k_persistent<T, MEASURE, FCC, KERNEL_BPAIR, 2>), g, bp, 0, st, p, a);
+        else
+            return hipErrorInvalidValue;
+    } else if (kind == BCC) {
         hipLaunchKernelGGL((k_persistent<T, MEASURE, BCC, KERNEL_TILE, 1>), g, b, 0, st, p, a);
     } else if (kind == FCC) {
         hipLaunchKernelGGL((k_persistent<T, MEASURE, FCC, KERNEL_TILE, 1>), g, b, 0, st, p, a);

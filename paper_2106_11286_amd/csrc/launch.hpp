@@ -28,6 +28,9 @@ struct PassLaunch {
 //       2 = update writing per-site dH and decisions to p.dbg_dh / p.dbg_acc
 hipError_t launch_pass(int kind, bool f64, int colour, bool measure, int mode,
                        const PassLaunch &p, hipStream_t st);
+// The basis pair kernels (bcc, fcc; called by launch_pass for that tile).
+hipError_t launch_basis_pair(int kind, bool f64, int colour, bool measure, int mode,
+                             const PassLaunch &p, hipStream_t st);
 
 hipError_t launch_init(bool f64, int kind, const RepDev *rep_host, int mode, uint32_t seed_lo,
                        uint32_t seed_hi, hipStream_t st);

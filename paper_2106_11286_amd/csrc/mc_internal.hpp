@@ -53,6 +53,7 @@ enum : int32_t {
     KERNEL_PAIR = 4,  // sc only, even packed rows: as KERNEL_STRIP with two columns per thread
     KERNEL_PBAND = 5, // sc only, even packed rows: as KERNEL_BAND with two columns per thread
     KERNEL_BSTRIP = 6, // bcc / fcc: tx (multiple of 64) lanes along x, ty rows, planes in registers
+    KERNEL_BPAIR = 7,  // bcc / fcc, even Lx: tx threads over (band, pair) positions, ty rows per band
 };
 
 // Tile of one workgroup: tx row columns x ty rows x zc planes, and the kernel

@@ -387,7 +387,8 @@ class Simulation:
         """``mc_set_tile``: kernel 0 = tile (tx x ty threads), 1 = sc row strip
         (tx threads along the row, ty rows per thread), 2 = sc band, 3 = whole
         sweeps in LDS (tx threads per replica), 4 = sc pair strip (two columns
-        per thread), 5 = sc band of pairs, 6 = bcc/fcc strip; zc planes per tile."""
+        per thread), 5 = sc band of pairs, 6 = bcc/fcc strip, 7 = bcc/fcc band of
+        cell pairs; zc planes per tile."""
         _check("mc_set_tile", LIB.mc_set_tile(self.handle, int(kernel), int(tx), int(ty), int(zc)))
 
     def autotune(self, trial_sweeps: int = 5, measure: bool = True, persistent: bool = False,

@@ -36,6 +36,13 @@ C5_SC464_ROOFLINE = dict(
     name="sc-L464-1e8-spins", kind="sc", L=(464, 464, 464), periodic_mask=7,
     J=1.0, K=0.02, e=(0.0, 0.0, 1.0), T=1.4, seed=4, sweeps=1000)
 
+# bcc at the benchmark's scale: 2 x 368^3 = 99,672,064 spins, periodic, in the
+# ordered phase at moderate acceptance (the "any crystal lattice" claim at the
+# paper's 10^8-spin size)
+BCC_368_1E8 = dict(
+    name="bcc-L368-1e8-spins", kind="bcc", L=(368, 368, 368), periodic_mask=7,
+    J=1.0, K=0.02, e=(0.0, 0.0, 1.0), T=1.9, seed=6, sweeps=200)
+
 REPLICA_KEYS = ("kind", "L", "periodic_mask", "sphere_radius", "J", "K", "e", "T", "replica_id")
 
 

@@ -359,6 +359,67 @@ def test_basis_strip_kernel_is_bitwise(M, kind, prec):
         sc.set_tile(64, 1, 1, kernel=6)
 
 
+BPAIR_TILES = [(7, 64, 1, 3), (7, 64, 2, 5), (7, 128, 2, 1), (7, 256, 1, 7), (7, 64, 2, 34)]
+
+
+@pytest.mark.parametrize("kind", ["bcc", "fcc"])
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_basis_pair_kernel_is_bitwise(M, kind, prec):
+    """bcc/fcc pair kernel (two cells per lane, bands of rows dealt over the
+    lanes, lane shifts and edge words): spins equal the tile kernel's bitwise
+    and acceptance counts match, on rows spanning several waves and bands
+    running across waves, ragged bands and planes, open faces and the sphere;
+    also through persistent launches and the debug pass."""
+    import torch
+
+    base = dict(kind=kind, J=1.0, K=0.15, e=(0.3, 0.5, 0.8))
+    reps = [M.Replica(L=(70, 9, 7), periodic_mask=7, T=1.1, replica_id=0, **base),
+            M.Replica(L=(130, 5, 5), periodic_mask=5, T=0.8, replica_id=1, **base),
+            M.Replica(L=(12, 10, 8), periodic_mask=0, sphere_radius=4.5, T=1.4, replica_id=2, **base),
+            M.Replica(L=(6, 7, 9), periodic_mask=2, T=1.7, replica_id=3, **base),
+            M.Replica(L=(64, 7, 9), periodic_mask=3, T=1.3, replica_id=4, **base)]
+    mk = lambda: M.Simulation(reps, precision=prec, seed=17,
+                              scratch=torch.empty(16 << 20, dtype=torch.uint8, device="cuda"))
+    ref = mk()
+    ref.set_tile(16, 16, 2, kernel=0)
+    ref.sweep(5, measure=True)
+    obs_r = ref.observables()
+    for tile in BPAIR_TILES:
+        for pers in (False, True):
+            one = mk()
+            one.set_tile(tile[1], tile[2], tile[3], kernel=tile[0])
+            one.sweep(2, persistent=pers)
+            one.sweep(3, measure=True, persistent=pers)
+            o = one.observables()
+            for r in range(len(reps)):
+                for a, b in zip(natural(one, r), natural(ref, r)):
+                    assert np.array_equal(a, b), (r, tile, pers)
+                assert o[r]["n_accepted"] == obs_r[r]["n_accepted"], (r, tile, pers)
+                assert abs(o[r]["E"] - obs_r[r]["E"]) <= 1e-9 * abs(o[r]["E"])
+            one.close()
+    # the debug pass: per-site dH and decisions equal the tile kernel's
+    a, b = mk(), mk()
+    a.set_tile(128, 2, 3, kernel=7)
+    b.set_tile(16, 16, 2, kernel=0)
+    a.sweep(2)
+    b.sweep(2)
+    n_colours = 2 if kind == "bcc" else 4
+    for c in range(n_colours):
+        da, aa = a.debug_pass(c)
+        db, ab = b.debug_pass(c)
+        for r in range(len(reps)):
+            assert torch.equal(aa[r], ab[r]), (c, r)
+            sel = ab[r] != 255
+            assert torch.equal(da[r][sel], db[r][sel]), (c, r)
+    odd = M.Simulation([M.Replica(kind=kind, L=(7, 6, 6))], precision=prec)
+    with pytest.raises(M.MCError) as ei:
+        odd.set_tile(64, 1, 1, kernel=7)
+    assert ei.value.status == -2
+    sc = M.Simulation([M.Replica(kind="sc", L=(16, 16, 16))], precision=prec)
+    with pytest.raises(M.MCError):
+        sc.set_tile(64, 1, 1, kernel=7)
+
+
 LDS_CASES = [("sc", (16, 16, 16), 7, 0.0, "f64"), ("sc", (16, 16, 16), 7, 0.0, "f32"),
              ("sc", (12, 10, 8), 5, 0.0, "f32"), ("bcc", (8, 8, 8), 7, 0.0, "f64"),
              ("bcc", (7, 9, 5), 3, 0.0, "f32"), ("fcc", (6, 6, 6), 0, 2.6, "f32"),
@@ -652,6 +713,55 @@ def test_full_size_fcc_particle_sampled(M):
             if checked >= 1500:
                 break
         assert checked >= 1500
+
+
+def test_full_size_bcc_sampled(M):
+    """bcc at the benchmark's scale (2 x 368^3 = 99,672,064 spins, FP32, the
+    autotuned tile): after the tuning sweeps and 10 more, both colour passes of
+    the next sweep at 1500 sampled sites each against the oracle's single-site
+    evaluation, and the fused observables against a recomputation."""
+    import torch
+
+    w = W.BCC_368_1E8
+    rep = M.Replica(**W.replica_fields(w))
+    sim = M.Simulation([rep], precision="f32", seed=w["seed"],
+                       scratch=torch.empty(64 << 20, dtype=torch.uint8, device="cuda"))
+    tile = sim.autotune(trial_sweeps=2, measure=True)
+    print("autotuned tile", tile)
+    sim.sweep(9)
+    sim.sweep(1, measure=True)
+    fused = sim.observables()[0]
+    full = sim.measure_state()[0]
+    assert fused["n_sites"] == 2 * 368**3
+    assert abs(fused["E"] - full["E"]) <= 1e-9 * abs(full["E"])
+    assert np.max(np.abs(fused["M"] - full["M"])) <= 1e-12
+    geo = O.Geometry(O.BCC, *rep.L, periodic_mask=rep.periodic_mask)
+    p = oracle_params(rep, w["seed"])
+    rng = np.random.default_rng(368)
+    t = sim.get_sweep()
+    cells_n = 368**3
+    n_flip = 0
+    for colour in (0, 1):
+        before = natural(sim)
+        dh, acc = sim.debug_pass(colour)
+        after = natural(sim)
+        cells = rng.integers(0, cells_n, size=1500)
+        k = torch_index(colour * cells_n + cells)
+        dhs = dh[0][k].double().cpu().numpy()
+        accs = acc[0][k].cpu().numpy()
+        del dh, acc
+        for j, cell in enumerate(cells):
+            site = int(cell) * 2 + colour
+            r = geo.site_attempt(p, t, before, site)
+            assert abs(dhs[j] - r["dH"]) <= 1e-5 * max(abs(r["dH"]), 1.0), (site, dhs[j], r)
+            if bool(accs[j]) != r["accepted"]:
+                assert abs(r["margin"]) < 1e-4, (site, r)
+                n_flip += 1
+                continue
+            got = np.array([after[0][site], after[1][site], after[2][site]])
+            assert np.max(np.abs(got - r["S_after"])) <= 2e-6
+        del before, after
+    assert n_flip <= 2
 
 
 # --------------------------------------------------------------------------
