@@ -16,6 +16,7 @@ from scipy import integrate
 
 from oracle import oracle as O
 from oracle import stats as OS
+from oracle import tempering as PT
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -566,3 +567,55 @@ def test_single_site_attempt_equals_pass():
                 assert np.array_equal(r["S_after"], [s[0][site], s[1][site], s[2][site]])
             for site in np.nonzero(~occ)[0][:5]:
                 assert geo.site_attempt(p, 4, before, int(site)) is None
+
+
+# --------------------------------------------------------------------------
+# Replica exchange between neighbouring temperatures (oracle/tempering.py)
+# --------------------------------------------------------------------------
+def test_exchange_pairs_alternate_and_equal_energies_swap():
+    """Guards: wrong pair parity, the ladder order, an attempt with Delta = 0
+    rejected."""
+    rep_at, Ts = PT.ladder([1.6, 1.0, 1.4, 1.2, 1.8])
+    assert rep_at == [1, 3, 2, 0, 4] and Ts == [1.0, 1.2, 1.4, 1.6, 1.8]
+    out = PT.swap_round([3.0] * 5, Ts, rep_at, 0, 5, 1)
+    assert out == [(0, True), (2, True)]
+    assert rep_at == [3, 1, 0, 2, 4]
+    out = PT.swap_round([3.0] * 5, Ts, rep_at, 1, 6, 1)
+    assert out == [(1, True), (3, True)]
+    assert rep_at == [3, 0, 1, 4, 2]
+
+
+def test_exchange_acceptance_is_exp_delta():
+    """Guards: an inverted comparison, the sign of Delta, beta taken as T,
+    a biased uniform.  Slot 0 at T = 1, slot 1 at T = 2; the replica at slot 0
+    has E = -2, the other -1: Delta = (1 - 1/2)(-2 + 1) = -1/2, so the
+    exchange is accepted with probability exp(-1/2); the reverse energies
+    always exchange."""
+    n = 20000
+    acc = sum(PT.swap_round([-2.0, -1.0], [1.0, 2.0], [0, 1], 0, t, 99)[0][1] for t in range(n))
+    p = np.exp(-0.5)
+    assert abs(acc / n - p) <= 4.0 * np.sqrt(p * (1 - p) / n), acc / n
+    assert all(PT.swap_round([-1.0, -2.0], [1.0, 2.0], [0, 1], 0, t, 99)[0][1] for t in range(200))
+
+
+def test_exchange_keeps_each_slot_boltzmann():
+    """Guards: any error in the exchange rule that breaks detailed balance.
+    Three two-level systems (E in {0, 1}) at T = 0.5, 1, 4, each redrawn from
+    its slot's Boltzmann distribution (exact heat bath, numpy) before every
+    exchange round: after the exchanges the replica at slot k must still have
+    P(E = 1) = 1 / (1 + exp(1/T_k)).  A wrong sign of Delta moves the excited
+    systems to the cold slots by ~0.1 in probability, 30 standard errors."""
+    rng = np.random.default_rng(5)
+    rep_at, Ts = PT.ladder([4.0, 0.5, 1.0])
+    E = [0.0, 0.0, 0.0]
+    n = 30000
+    ones = np.zeros(3)
+    for r in range(n):
+        for k in range(3):
+            E[rep_at[k]] = 1.0 if rng.random() < 1.0 / (1.0 + np.exp(1.0 / Ts[k])) else 0.0
+        PT.swap_round(E, Ts, rep_at, r, r, 3)
+        for k in range(3):
+            ones[k] += E[rep_at[k]]
+    for k in range(3):
+        p = 1.0 / (1.0 + np.exp(1.0 / Ts[k]))
+        assert abs(ones[k] / n - p) <= 5.0 * np.sqrt(p * (1 - p) / n), (k, ones[k] / n, p)
