@@ -389,6 +389,43 @@ def run_bcc(M, W, sweeps):
     return res
 
 
+def run_exchange(M, W):
+    """Replica exchange: 32 copies of one sc 64^3 lattice (FP32) at T evenly
+    spaced over the critical region; rounds of sweeps (the last measured)
+    each followed by the device exchange step, through persistent launches
+    (queues per XCD) and through per-pass launches.  Reports the update rate
+    with the exchange steps included and the acceptance per slot pair."""
+    import numpy as np
+    import torch
+
+    w = W.EXCHANGE_SC64
+    Ts = np.linspace(w["T_range"][0], w["T_range"][1], w["n_reps"])
+    reps = [M.Replica(**W.replica_fields(w, T=float(T), replica_id=r)) for r, T in enumerate(Ts)]
+    res = {"workload": w["name"], "replicas": len(reps), "rounds": w["rounds"],
+           "sweeps_per_round": w["sweeps_per_round"]}
+    for mode, pers in (("persistent", True), ("per_pass_launches", False)):
+        sim = M.Simulation(reps, precision="f32", seed=w["seed"],
+                           scratch=torch.empty(64 << 20, dtype=torch.uint8, device="cuda"))
+        N = sum(sim.n_occ)
+        tile = sim.autotune(trial_sweeps=8, measure=True, persistent=pers)
+        sim.exchange_init()
+        sim.exchange_sweep(10, w["sweeps_per_round"], persistent=pers)
+        sim.exchange_state()
+        _, dt = _timed(lambda: (sim.exchange_sweep(w["rounds"], w["sweeps_per_round"],
+                                                   persistent=pers), sim.exchange_state()))
+        st = sim.exchange_state()
+        rate = np.array(st["accepted"]) / np.maximum(np.array(st["attempted"]), 1)
+        n_sw = w["rounds"] * w["sweeps_per_round"]
+        res["spins"] = N
+        res[mode] = {"tile": list(tile), "s": dt, "updates_per_ns": N * n_sw / dt / 1e9,
+                     "acceptance_mean": float(rate.mean()), "acceptance_min": float(rate.min()),
+                     "queues": sim.persistent_queues() if pers else None}
+        log(f"[bench] exchange {mode}: {res[mode]['updates_per_ns']:.1f} updates/ns, "
+            f"exchange acceptance mean {rate.mean():.2f} min {rate.min():.2f}")
+        sim.close()
+    return res
+
+
 F1_TEMPERATURES = (1.30, 1.32, 1.34, 1.36, 1.38, 1.40, 1.41, 1.42, 1.43, 1.44, 1.45, 1.46,
                    1.48, 1.50)
 
@@ -491,7 +528,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--workload", default="c5",
-                    choices=["c5", "c1", "c2", "c3", "c4", "f1", "big", "bcc"],
+                    choices=["c5", "c1", "c2", "c3", "c4", "f1", "big", "bcc", "exchange"],
                     help="c5 (default): the 10^8-spin headline; others print their own line "
                          "(f1: the paper's M(T) accuracy experiment)")
     ap.add_argument("--f1-sizes", default="128,256,512")
@@ -531,6 +568,8 @@ def main():
             out = run_big(M)
         elif args.workload == "bcc":
             out = run_bcc(M, W, W.BCC_368_1E8["sweeps"])
+        elif args.workload == "exchange":
+            out = run_exchange(M, W)
         elif args.workload == "f1":
             out = run_f1(M, [int(v) for v in args.f1_sizes.split(",")], args.f1_sweeps,
                          args.f1_sweeps, K=args.f1_K)

@@ -305,6 +305,33 @@ mc_status mc_series_stats(const mc_obs *series, uint64_t n, uint64_t stride, dou
  * exits normally.  Waits for the handle's enqueued work first. */
 mc_status mc_set_watchdog(mc_sim *h, uint32_t spins);
 
+/* Replica exchange (parallel tempering) between the handle's replicas, an
+ * extension of the paper's one-temperature runs for batches of identical
+ * lattices (standard replica exchange: Swendsen and Wang; Hukushima and
+ * Nemoto).  mc_exchange_init takes the replicas' current temperatures as the
+ * ladder T_0 <= ... <= T_{n-1} (slot k; ties in replica order), each replica
+ * at the slot of its own T; all replicas must differ only in T (0 < T < inf)
+ * and replica_id (else MC_E_ARG); at least 2 replicas.
+ * mc_exchange_sweep runs n_rounds rounds: sweeps_per_round sweeps (the last
+ * one measured; with MC_PERSISTENT all of them, in one launch per round),
+ * then one exchange step on the
+ * device: round r attempts the slot pairs (k, k+1), k = r mod 2, r mod 2 + 2,
+ * ..., with Delta = (1/T_k - 1/T_{k+1}) (E_i - E_j) for the replicas i at k and
+ * j at k+1 and E the total Eq. (1) energy of the measured sweep; accepted iff
+ * Delta >= 0 or u < exp(Delta), u the uniform of Philox counter
+ * (k, 0, t, 2) under the handle's seed, t the sweeps done.  An accepted pair
+ * swaps temperatures (the spins stay).  Asynchronous.
+ * mc_exchange_state synchronises and returns replica_at_slot[n], T_slot[n],
+ * attempted[n-1] and accepted[n-1] per pair (k, k+1) and the rounds done
+ * (any pointer may be NULL); afterwards each replica's T in the handle is its
+ * current slot's.  mc_set_temperatures (and mc_run_schedule) end the
+ * exchange; mc_exchange_sweep then gives MC_E_STATE until the next init. */
+mc_status mc_exchange_init(mc_sim *h);
+mc_status mc_exchange_sweep(mc_sim *h, uint32_t n_rounds, uint32_t sweeps_per_round,
+                            uint32_t flags);
+mc_status mc_exchange_state(mc_sim *h, int32_t *replica_at_slot, double *T_slot,
+                            uint64_t *attempted, uint64_t *accepted, uint64_t *rounds);
+
 /* Work queues of persistent launches (MC_PERSISTENT).  The replicas of a
  * handle are independent Markov chains, so a launch may serve each replica
  * from one XCD:

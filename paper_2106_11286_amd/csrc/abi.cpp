@@ -318,7 +318,7 @@ void make_work(const mc_replica_desc *reps, int n, const Tile &t, std::vector<Wo
 
 struct ScratchLayout {
     uint64_t off_ctr, off_reps, off_work, off_partials, off_records, off_stage, off_count,
-        off_persist, off_queues, total;
+        off_persist, off_queues, off_exchange, total;
 };
 
 // Words of the persistent-queue region: 16 queue offsets, then every item
@@ -333,6 +333,11 @@ ScratchLayout scratch_layout(int n_reps, uint64_t n_items, int n_colours)
     o += 256;
     L.off_reps = o;
     o = align_up(o + sizeof(RepDev) * n_reps, 256);
+    // replica exchange: beta[n], attempted[n], accepted[n] (8 bytes each),
+    // rep_at[n], round; placed before every region that depends on the work
+    // list, so a tile change does not move it
+    L.off_exchange = o;
+    o = align_up(o + 24ull * n_reps + 4ull * n_reps + 4, 256);
     L.off_work = o;
     o = align_up(o + sizeof(WorkItem) * std::max<uint64_t>(n_items, 1), 256);
     L.off_partials = o;
@@ -407,6 +412,10 @@ struct mc_sim {
     uint32_t *fin_count = nullptr;
     uint32_t *pstate = nullptr; // persistent-launch counters
     uint32_t *queues_dev = nullptr; // queue offsets [16], then queue items
+    // replica exchange (mc_exchange_*): device table in scratch, host ladder
+    bool xchg_active = false;
+    std::vector<double> xchg_T, xchg_beta; // per slot
+    std::vector<uint32_t> xchg_rep_host;   // upload staging
     uint32_t spin_limit = 1u << 24;
     bool persist_used = false;
     int persist_mode = MC_PERSIST_AUTO;
@@ -665,19 +674,64 @@ void record_to_obs(const mc_sim *h, const double *rec, int r, mc_obs *o)
     o->E = o->E_exch + o->E_anis;
 }
 
+void set_temperature(RepDev &R, double T)
+{
+    R.greedy = T == 0.0;
+    R.beta = (T > 0.0 && std::isfinite(T)) ? 1.0 / T : 0.0;
+}
+
+// Device pointers of the replica-exchange table (scratch, off_exchange).
+struct XchgPtrs {
+    double *beta;
+    uint64_t *attempted, *accepted;
+    uint32_t *rep_at, *round;
+};
+XchgPtrs xchg_ptrs(const mc_sim *h)
+{
+    char *b = h->scratch + h->lay.off_exchange;
+    const size_t n = (size_t)h->n_reps;
+    return {(double *)b, (uint64_t *)(b + 8 * n), (uint64_t *)(b + 16 * n),
+            (uint32_t *)(b + 24 * n), (uint32_t *)(b + 28 * n)};
+}
+
+// While exchange is active the device descriptors hold each replica's current
+// temperature; copy it into the host descriptors (before they are uploaded).
+mc_status xchg_pull(mc_sim *h)
+{
+    if (!h->xchg_active) return MC_OK;
+    std::vector<uint32_t> rep_at(h->n_reps);
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    HIP_TRY(hipMemcpy(rep_at.data(), xchg_ptrs(h).rep_at, sizeof(uint32_t) * h->n_reps,
+                      hipMemcpyDeviceToHost));
+    for (int k = 0; k < h->n_reps; ++k) {
+        const uint32_t r = rep_at[k];
+        if (r >= (uint32_t)h->n_reps) return fail(MC_E_DEVICE, "exchange table corrupted");
+        h->desc[r].T = h->xchg_T[k];
+        set_temperature(h->reps[r], h->xchg_T[k]);
+    }
+    return MC_OK;
+}
+
+// Identical lattices and couplings (all but T and replica_id).
+bool same_system(const mc_replica_desc &a, const mc_replica_desc &b)
+{
+    return a.kind == b.kind && a.Lx == b.Lx && a.Ly == b.Ly && a.Lz == b.Lz &&
+           a.periodic_mask == b.periodic_mask && a.sphere_radius == b.sphere_radius &&
+           a.J == b.J && a.K == b.K && a.e[0] == b.e[0] && a.e[1] == b.e[1] && a.e[2] == b.e[2];
+}
+
 mc_status upload_reps(mc_sim *h)
 {
+    {
+        mc_status s = xchg_pull(h);
+        if (s != MC_OK) return s;
+    }
     HIP_TRY(hipMemcpyAsync(h->reps_dev, h->reps.data(), sizeof(RepDev) * h->n_reps,
                            hipMemcpyHostToDevice, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
     return MC_OK;
 }
 
-void set_temperature(RepDev &R, double T)
-{
-    R.greedy = T == 0.0;
-    R.beta = (T > 0.0 && std::isfinite(T)) ? 1.0 / T : 0.0;
-}
 
 mc_status run_chunk(mc_sim *h, uint32_t n, bool measure, uint32_t slot0, bool persistent)
 {
@@ -1165,6 +1219,8 @@ mc_status mc_set_temperatures(mc_sim *h, const double *T, int32_t n_reps)
     if (n_reps != h->n_reps) return fail(MC_E_ARG, "n_reps %d != handle's %d", n_reps, h->n_reps);
     for (int r = 0; r < n_reps; ++r)
         if (!(T[r] >= 0.0)) return fail(MC_E_ARG, "replica %d: T must be >= 0", r);
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    h->xchg_active = false; // explicit temperatures end replica exchange
     for (int r = 0; r < n_reps; ++r) {
         h->desc[r].T = T[r];
         set_temperature(h->reps[r], T[r]);
@@ -1225,6 +1281,111 @@ mc_status mc_run_schedule(mc_sim *h, const mc_schedule *s, mc_obs *series, uint6
     if (fin != MC_OK) return fin;
     if (n_written) *n_written = written;
     return MC_OK;
+}
+
+mc_status mc_exchange_init(mc_sim *h)
+{
+    if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
+    const int n = h->n_reps;
+    if (n < 2) return fail(MC_E_ARG, "replica exchange needs at least 2 replicas");
+    for (int r = 0; r < n; ++r) {
+        if (!same_system(h->desc[r], h->desc[0]))
+            return fail(MC_E_ARG, "replica %d: exchange needs replicas that differ only in T and "
+                                  "replica_id", r);
+        const double T = h->desc[r].T;
+        if (!(T > 0.0) || !std::isfinite(T))
+            return fail(MC_E_ARG, "replica %d: exchange needs 0 < T < inf (T = %g)", r, T);
+    }
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    std::vector<int> order(n);
+    for (int r = 0; r < n; ++r) order[r] = r;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return h->desc[a].T < h->desc[b].T; });
+    h->xchg_T.resize(n);
+    h->xchg_beta.resize(n);
+    h->xchg_rep_host.resize(n);
+    for (int k = 0; k < n; ++k) {
+        h->xchg_T[k] = h->desc[order[k]].T;
+        h->xchg_beta[k] = 1.0 / h->xchg_T[k];
+        h->xchg_rep_host[k] = (uint32_t)order[k];
+    }
+    const XchgPtrs x = xchg_ptrs(h);
+    HIP_TRY(hipMemcpyAsync(x.beta, h->xchg_beta.data(), sizeof(double) * n, hipMemcpyHostToDevice,
+                           h->stream));
+    HIP_TRY(hipMemcpyAsync(x.rep_at, h->xchg_rep_host.data(), sizeof(uint32_t) * n,
+                           hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(launch_zero_u32((uint32_t *)x.attempted, 4u * (uint32_t)n, h->stream));
+    HIP_TRY(launch_zero_u32(x.round, 1u, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    h->xchg_active = true;
+    return MC_OK;
+}
+
+mc_status mc_exchange_sweep(mc_sim *h, uint32_t n_rounds, uint32_t sweeps_per_round,
+                            uint32_t flags)
+{
+    if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
+    if (!h->xchg_active) return fail(MC_E_STATE, "replica exchange not initialised (mc_exchange_init)");
+    if (flags & ~MC_PERSISTENT) return fail(MC_E_ARG, "unknown flags 0x%x", flags);
+    if (sweeps_per_round < 1) return fail(MC_E_ARG, "sweeps_per_round must be >= 1");
+    if (h->t + (uint64_t)n_rounds * sweeps_per_round > 0xFFFFFFFFull)
+        return fail(MC_E_STATE, "sweep counter would exceed 2^32-1");
+    const XchgPtrs x = xchg_ptrs(h);
+    for (uint32_t k = 0; k < n_rounds; ++k) {
+        mc_status st;
+        if (flags & MC_PERSISTENT) {
+            // one launch per round: every sweep measured (the records are a
+            // by-product; the chain does not depend on them)
+            if ((st = mc_sweep(h, sweeps_per_round, MC_MEASURE | flags)) != MC_OK) return st;
+        } else {
+            if (sweeps_per_round > 1 && (st = mc_sweep(h, sweeps_per_round - 1, flags)) != MC_OK)
+                return st;
+            if ((st = mc_sweep(h, 1, MC_MEASURE | flags)) != MC_OK) return st;
+        }
+        ExchangeLaunch L;
+        L.reps_dev = h->reps_dev;
+        L.records = h->records + (size_t)h->last_slot * h->n_reps * NR;
+        L.beta = x.beta;
+        L.rep_at = x.rep_at;
+        L.round = x.round;
+        L.attempted = x.attempted;
+        L.accepted = x.accepted;
+        L.tctr_dev = h->tctr;
+        L.n = (uint32_t)h->n_reps;
+        L.seed_lo = (uint32_t)h->seed;
+        L.seed_hi = (uint32_t)(h->seed >> 32);
+        HIP_TRY(launch_exchange(L, h->stream));
+    }
+    return MC_OK;
+}
+
+mc_status mc_exchange_state(mc_sim *h, int32_t *replica_at_slot, double *T_slot,
+                            uint64_t *attempted, uint64_t *accepted, uint64_t *rounds)
+{
+    if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
+    if (!h->xchg_active) return fail(MC_E_STATE, "replica exchange not initialised (mc_exchange_init)");
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    mc_status st = check_persistent(h);
+    if (st != MC_OK) return st;
+    const int n = h->n_reps;
+    const XchgPtrs x = xchg_ptrs(h);
+    std::vector<uint32_t> rep_at(n);
+    std::vector<uint64_t> att(n), acc(n);
+    uint32_t rnd = 0;
+    HIP_TRY(hipMemcpy(rep_at.data(), x.rep_at, sizeof(uint32_t) * n, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(att.data(), x.attempted, sizeof(uint64_t) * n, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(acc.data(), x.accepted, sizeof(uint64_t) * n, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(&rnd, x.round, sizeof rnd, hipMemcpyDeviceToHost));
+    for (int k = 0; k < n; ++k) {
+        if (replica_at_slot) replica_at_slot[k] = (int32_t)rep_at[k];
+        if (T_slot) T_slot[k] = h->xchg_T[k];
+        if (k + 1 < n) {
+            if (attempted) attempted[k] = att[k];
+            if (accepted) accepted[k] = acc[k];
+        }
+    }
+    if (rounds) *rounds = rnd;
+    return xchg_pull(h);
 }
 
 mc_status mc_set_persistent_mode(mc_sim *h, mc_persist_mode mode)

@@ -247,6 +247,42 @@ hipError_t launch_zero_u32(uint32_t *p, uint32_t n, hipStream_t st)
     return hipGetLastError();
 }
 
+// Replica exchange (one workgroup; the pairs of a round are disjoint, so
+// each thread owns the slots it writes).  Counter (k, 0, t, 2) keys the
+// uniform of pair k after t sweeps.
+__global__ void __launch_bounds__(256) k_exchange(ExchangeLaunch L)
+{
+    const uint32_t rnd = *L.round, t = *L.tctr_dev;
+    __syncthreads();
+    for (uint32_t k = 2u * threadIdx.x + (rnd & 1u); k + 1u < L.n; k += 2u * blockDim.x) {
+        const uint32_t i = L.rep_at[k], j = L.rep_at[k + 1u];
+        const double *ri = L.records + (size_t)i * NR, *rj = L.records + (size_t)j * NR;
+        const double Ei = ri[R_EEX] + ri[R_EAN], Ej = rj[R_EEX] + rj[R_EAN];
+        const double delta = (L.beta[k] - L.beta[k + 1u]) * (Ei - Ej);
+        bool acc = delta >= 0.0;
+        if (!acc) {
+            const Words w = philox10(k, 0u, t, 2u, L.seed_lo, L.seed_hi);
+            acc = uniform23<double>(w.w0) < exp(delta);
+        }
+        L.attempted[k] += 1u;
+        if (acc) {
+            L.accepted[k] += 1u;
+            L.rep_at[k] = j;
+            L.rep_at[k + 1u] = i;
+            L.reps_dev[i].beta = L.beta[k + 1u];
+            L.reps_dev[j].beta = L.beta[k];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) *L.round = rnd + 1u;
+}
+
+hipError_t launch_exchange(const ExchangeLaunch &L, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_exchange, dim3(1), dim3(256), 0, st, L);
+    return hipGetLastError();
+}
+
 __global__ void k_xcd_probe(uint32_t *out, uint32_t n)
 {
     if (threadIdx.x == 0 && blockIdx.x < n) out[blockIdx.x] = xcd_id();

@@ -97,6 +97,23 @@ hipError_t lds_allow(int kind, bool f64, uint32_t bytes);
 // The HBM streams of a colour pass without its arithmetic (see mc_stream_probe).
 hipError_t launch_stream_probe(bool f64, void *x, void *y, void *z, uint64_t P, uint32_t grid,
                                hipStream_t st);
+// Replica exchange between neighbouring temperature slots (one workgroup):
+// slot k holds replica rep_at[k] at inverse temperature beta[k]; the round's
+// pairs (k, k+1), k = round mod 2 + 2m, compare the total energies of the
+// records at `records` ([n_reps][NR], the last measured sweep) and, when
+// accepted, swap rep_at[k], rep_at[k+1] and the two replicas' beta in reps_dev.
+struct ExchangeLaunch {
+    RepDev *reps_dev;
+    const double *records;
+    const double *beta;       // [n] per slot
+    uint32_t *rep_at;         // [n]
+    uint32_t *round;          // rounds done (incremented by the launch)
+    uint64_t *attempted, *accepted; // [n] per pair (k, k+1)
+    const uint32_t *tctr_dev; // sweeps done
+    uint32_t n, seed_lo, seed_hi;
+};
+hipError_t launch_exchange(const ExchangeLaunch &L, hipStream_t st);
+
 // XCC_ID of workgroups 0..n-1 (thread 0 of each writes one word).
 hipError_t launch_xcd_probe(uint32_t *out, uint32_t n, hipStream_t st);
 hipError_t launch_advance(uint32_t *tctr_dev, uint32_t n, hipStream_t st);

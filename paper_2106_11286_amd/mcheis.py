@@ -106,6 +106,14 @@ _SIGNATURES = {
                                        ctypes.c_double, ctypes.POINTER(Stats)]),
     "mc_set_watchdog": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32]),
     "mc_set_persistent_mode": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "mc_exchange_init": (ctypes.c_int, [ctypes.c_void_p]),
+    "mc_exchange_sweep": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
+                                         ctypes.c_uint32]),
+    "mc_exchange_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_uint64),
+                                         ctypes.POINTER(ctypes.c_uint64),
+                                         ctypes.POINTER(ctypes.c_uint64)]),
     "mc_get_persistent_queues": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
     "mc_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_char_p,
                                    ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
@@ -309,6 +317,32 @@ class Simulation:
 
     def set_watchdog(self, spins: int):
         _check("mc_set_watchdog", LIB.mc_set_watchdog(self.handle, int(spins)))
+
+    def exchange_init(self):
+        """``mc_exchange_init``: start replica exchange over the current
+        temperatures (identical lattices)."""
+        _check("mc_exchange_init", LIB.mc_exchange_init(self.handle))
+
+    def exchange_sweep(self, n_rounds: int, sweeps_per_round: int, persistent: bool = False):
+        """``mc_exchange_sweep``: rounds of sweeps, each followed by one
+        exchange step between neighbouring temperatures."""
+        _check("mc_exchange_sweep", LIB.mc_exchange_sweep(self.handle, int(n_rounds),
+                                                          int(sweeps_per_round),
+                                                          PERSISTENT if persistent else 0))
+
+    def exchange_state(self):
+        """``mc_exchange_state``: dict(replica_at_slot, T_slot, attempted,
+        accepted, rounds); attempted/accepted per slot pair (k, k+1)."""
+        n = self.n_reps
+        ra = (ctypes.c_int32 * n)()
+        T = (ctypes.c_double * n)()
+        att = (ctypes.c_uint64 * max(n - 1, 1))()
+        acc = (ctypes.c_uint64 * max(n - 1, 1))()
+        rounds = ctypes.c_uint64()
+        _check("mc_exchange_state", LIB.mc_exchange_state(self.handle, ra, T, att, acc,
+                                                          ctypes.byref(rounds)))
+        return {"replica_at_slot": list(ra), "T_slot": list(T), "attempted": list(att)[:n - 1],
+                "accepted": list(acc)[:n - 1], "rounds": int(rounds.value)}
 
     PERSIST_MODES = {"auto": 0, "global": 1, "xcd": 2}
 

@@ -43,6 +43,13 @@ BCC_368_1E8 = dict(
     name="bcc-L368-1e8-spins", kind="bcc", L=(368, 368, 368), periodic_mask=7,
     J=1.0, K=0.02, e=(0.0, 0.0, 1.0), T=1.9, seed=6, sweeps=200)
 
+# replica exchange across the critical region: 32 copies of one sc 64^3
+# lattice at temperatures evenly spaced over 1.41 .. 1.48 (about 0.0023 apart)
+EXCHANGE_SC64 = dict(
+    name="sc-L64-exchange-32-replicas", kind="sc", L=(64, 64, 64), periodic_mask=7,
+    J=1.0, K=0.01, e=(0.0, 0.0, 1.0), T_range=(1.41, 1.48), n_reps=32, seed=7,
+    rounds=500, sweeps_per_round=4)
+
 REPLICA_KEYS = ("kind", "L", "periodic_mask", "sphere_radius", "J", "K", "e", "T", "replica_id")
 
 
