@@ -17,6 +17,7 @@ from scipy import integrate
 from oracle import oracle as O
 from oracle import stats as OS
 from oracle import tempering as PT
+from oracle import block_scheme as BS
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -619,3 +620,93 @@ def test_exchange_keeps_each_slot_boltzmann():
     for k in range(3):
         p = 1.0 / (1.0 + np.exp(1.0 / Ts[k]))
         assert abs(ones[k] / n - p) <= 5.0 * np.sqrt(p * (1 - p) / n), (k, ones[k] / n, p)
+
+
+# --------------------------------------------------------------------------
+# The paper's block scheme, synchronous form (oracle/block_scheme.py)
+# --------------------------------------------------------------------------
+def test_block_choice_is_uniform_within_each_block():
+    """Guards: a site outside its block, a biased offset, a wrong size of the
+    last (partial) block.  N = 100, n = 8: 12 full blocks and one of 4."""
+    counts = np.zeros(100)
+    for step in range(400):
+        for s, _ in BS.chosen_sites(100, 8, 2, step, 9):
+            counts[s] += 1
+    for k in range(13):
+        c = counts[k * 8:min(100, k * 8 + 8)]
+        assert c.sum() == 400
+        e = 400 / len(c)
+        assert np.sum((c - e) ** 2 / e) < 30.0, (k, c)  # chi-square, <= 7 dof
+
+
+def test_block_step_is_synchronous_and_counts_conflicts():
+    """Guards: moves applied in place (an attempt seeing a neighbour's new
+    value), a wrong conflict count.  Every attempt of a step is recomputed by
+    hand from the state before the step; conflicts are recounted from
+    coordinates."""
+    lat = O.Lattice(O.SC, 6, 6, 4)
+    p = O.Params(J=1.0, K=0.2, e=(0.0, 0.6, 0.8), T=1.1, seed=4)
+    spins = O.init(lat, p)
+    before = [a.copy() for a in spins]
+    att, acc, conf = BS.block_step(lat, p, spins, 4, 17)
+    chosen = BS.chosen_sites(lat.n_box, 4, 0, 17, 4)
+    picked = {s for s, _ in chosen}
+
+    def coords(s):
+        return s % 6, (s // 6) % 6, s // 36
+
+    def nbrs(s):
+        x, y, z = coords(s)
+        return [((x + dx) % 6) + 6 * ((y + dy) % 6) + 36 * ((z + dz) % 4)
+                for dx, dy, dz in ((1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1))]
+
+    n_conf = n_acc = 0
+    for s, w in chosen:
+        nb = nbrs(s)
+        n_conf += any(q in picked for q in nb)
+        h = np.array([sum(before[a][q] for q in nb) for a in range(3)])
+        S = np.array([before[a][s] for a in range(3)])
+        Sn = O.sphere_point(O.uniform(w[0]), O.uniform(w[1]))
+        dH = O.delta_h(h, S, Sn, p.K, p.e_unit)
+        ok = dH <= 0 or O.uniform(w[2]) <= np.exp(-dH / p.T)
+        n_acc += ok
+        want = Sn / np.linalg.norm(Sn) if ok else S
+        assert np.allclose([spins[a][s] for a in range(3)], want, atol=1e-15), s
+    assert att == 36 and acc == n_acc and conf == n_conf and conf > 0
+    untouched = np.ones(lat.n_box, bool)
+    untouched[list(picked)] = False
+    for a in range(3):
+        assert np.array_equal(spins[a][untouched], before[a][untouched])
+
+
+def test_one_block_is_exact_metropolis():
+    """Guards: a wrong attempt (field, proposal or acceptance) in the block
+    step.  With one block (n = N) a step is one single-site Metropolis
+    attempt at a random site, no concurrency: its equilibrium <e> and <|m|>
+    on sc 4^3 must agree with the colour sweep's (the C oracle) within the
+    blocked errors."""
+    lat = O.Lattice(O.SC, 4, 4, 4)
+    T = 1.6
+    p = O.Params(J=1.0, K=0.1, T=T, seed=21)
+    spins = O.init(lat, p, O.INIT_ALIGNED)
+    tables = lat.tables()
+    n_mcs, N = 1500, lat.n_box
+    e_b, m_b = [], []
+    for t in range(n_mcs):
+        for j in range(N):
+            _, _, conf = BS.block_step(lat, p, spins, N, t * N + j, tables)
+            assert conf == 0
+        if t >= 300:
+            o = O.observables(lat, p, spins)
+            e_b.append(o["E"] / N)
+            m_b.append(np.linalg.norm(o["m"]))
+    q = O.Params(J=1.0, K=0.1, T=T, seed=22)
+    s2 = O.init(lat, q, O.INIT_ALIGNED)
+    O.run(lat, q, 0, 2000, s2, record=False)
+    rec = O.run(lat, q, 2000, 40000, s2)
+    e_c = (rec[:, 3] + rec[:, 4]) / N
+    m_c = np.linalg.norm(rec[:, 0:3], axis=1) / N
+    for a, b in ((np.array(e_b), e_c), (np.array(m_b), m_c)):
+        ea, eb = OS.blocking_error(a), OS.blocking_error(b)
+        z = (a.mean() - b.mean()) / np.hypot(ea, eb)
+        assert abs(z) <= 4.0, (a.mean(), b.mean(), z)
