@@ -426,6 +426,62 @@ def run_exchange(M, W):
     return res
 
 
+def run_block(M, W):
+    """The paper's block scheme (synchronous form, blocks of n sites) against
+    the exact colour sweep on the Fig. 1 system: both from the aligned state,
+    n_equil sweeps (n steps each for the block scheme) then n_meas measured;
+    <|m|> and <e> with blocked errors and their difference in standard errors,
+    the fraction of attempts with a concurrently attempted neighbour, and the
+    update rate of each scheme."""
+    import numpy as np
+
+    w = W.BLOCK_SC128
+    rep = M.Replica(**W.replica_fields(w))
+    n, ne, nm, T = w["n_block"], w["n_equil"], w["n_meas"], w["T"]
+    res = {"workload": w["name"], "n_block": n, "n_equil": ne, "n_meas": nm, "T": T}
+    col = M.Simulation([rep], precision="f32", seed=w["seed"], init="aligned")
+    N = col.n_occ[0]
+    col.autotune(trial_sweeps=3, measure=True)
+    rec = col.run_schedule([T], n_equil=ne, n_meas=nm)[0, :, 0, :]
+    _, dt = _timed(lambda: col.sweep(nm, measure=True))
+    sc = M.series_stats(rec, N, T)
+    blk = M.Simulation([rep], precision="f32", seed=w["seed"], init="aligned")
+    blk.block_steps(n, 0, ne * n, conflicts=False, reset=True)
+    blk.block_counts()  # zero the counters: the measured phase counts conflicts
+    e, m = [], []
+    for t in range(nm):
+        blk.block_steps(n, (ne + t) * n, n, conflicts=True)
+        o = blk.measure_state()[0]
+        e.append(o["E"] / N)
+        m.append(o["absM"])
+    att, acc, conf = blk.block_counts()
+    _, dtb = _timed(lambda: blk.block_steps(n, (ne + nm) * n, 200 * n, conflicts=False))
+    e, m = np.array(e), np.array(m)
+
+    def blocked(x):
+        # Flyvbjerg-Petersen: the largest error over halvings with >= 32 blocks
+        best = x.std(ddof=1) / np.sqrt(len(x))
+        while len(x) >= 64:
+            x = 0.5 * (x[: len(x) // 2 * 2:2] + x[1: len(x) // 2 * 2:2])
+            best = max(best, x.std(ddof=1) / np.sqrt(len(x)))
+        return best
+
+    be, bm = blocked(e), blocked(m)
+    res["colour_sweep"] = {"abs_m": sc["abs_m"], "abs_m_err": sc["abs_m_err"], "e": sc["e"],
+                           "e_err": sc["e_err"], "updates_per_ns": N * nm / dt / 1e9}
+    res["block_scheme"] = {"abs_m": float(m.mean()), "abs_m_err": float(bm), "e": float(e.mean()),
+                           "e_err": float(be), "acceptance": acc / max(att, 1),
+                           "conflict_fraction": conf / max(att, 1),
+                           "updates_per_ns": N * 200 / dtb / 1e9}
+    res["bias_sigma"] = {
+        "abs_m": (m.mean() - sc["abs_m"]) / np.hypot(bm, sc["abs_m_err"]),
+        "e": (e.mean() - sc["e"]) / np.hypot(be, sc["e_err"])}
+    log(f"[bench] block: <|m|> {m.mean():.5f}+-{bm:.5f} vs colour {sc['abs_m']:.5f}+-"
+        f"{sc['abs_m_err']:.5f}; <e> {e.mean():.5f} vs {sc['e']:.5f}; conflicts "
+        f"{conf / max(att, 1):.3f}")
+    return res
+
+
 F1_TEMPERATURES = (1.30, 1.32, 1.34, 1.36, 1.38, 1.40, 1.41, 1.42, 1.43, 1.44, 1.45, 1.46,
                    1.48, 1.50)
 
@@ -528,7 +584,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--workload", default="c5",
-                    choices=["c5", "c1", "c2", "c3", "c4", "f1", "big", "bcc", "exchange"],
+                    choices=["c5", "c1", "c2", "c3", "c4", "f1", "big", "bcc", "exchange", "block"],
                     help="c5 (default): the 10^8-spin headline; others print their own line "
                          "(f1: the paper's M(T) accuracy experiment)")
     ap.add_argument("--f1-sizes", default="128,256,512")
@@ -570,6 +626,8 @@ def main():
             out = run_bcc(M, W, W.BCC_368_1E8["sweeps"])
         elif args.workload == "exchange":
             out = run_exchange(M, W)
+        elif args.workload == "block":
+            out = run_block(M, W)
         elif args.workload == "f1":
             out = run_f1(M, [int(v) for v in args.f1_sizes.split(",")], args.f1_sweeps,
                          args.f1_sweeps, K=args.f1_K)

@@ -332,6 +332,31 @@ mc_status mc_exchange_sweep(mc_sim *h, uint32_t n_rounds, uint32_t sweeps_per_ro
 mc_status mc_exchange_state(mc_sim *h, int32_t *replica_at_slot, double *T_slot,
                             uint64_t *attempted, uint64_t *accepted, uint64_t *rounds);
 
+/* The paper's block scheme (implementation paragraph), for comparison with
+ * the colour sweep; simple cubic lattices only (else MC_E_UNSUPPORTED).  The
+ * canonical sites s = (z Ly + y) Lx + x are cut into blocks of n consecutive
+ * sites (the last one shorter); in step j block k makes one Metropolis attempt
+ * at site k n + floor(w3 m_k / 2^32), m_k its size, with w the Philox block of
+ * counter (k, replica_id, j, 3) under the handle's seed (proposal from w0, w1,
+ * acceptance uniform from w2, as in a colour pass).  Concurrent blocks read
+ * each other's neighbours; this form makes that definite: every attempt of a
+ * step sees the state before the step and the accepted moves are written
+ * together (two launches per step and replica).  n steps are one sweep's
+ * worth of attempts; the sweep counter does not move.  Every replica of the
+ * handle takes the steps step0 .. step0 + n_steps - 1.
+ * The caller supplies a device workspace of mc_block_workspace bytes
+ * (256-byte aligned; else MC_E_BUFFER) whose first three 64-bit words count
+ * attempts (occupied chosen sites), accepted moves and conflicts (attempts
+ * with an attempted nearest neighbour in the same step, counted with
+ * MC_BLOCK_CONFLICTS only); MC_BLOCK_RESET zeroes them first.
+ * mc_block_counts synchronises, returns the three counts and zeroes them. */
+#define MC_BLOCK_CONFLICTS 4u
+#define MC_BLOCK_RESET 8u
+mc_status mc_block_workspace(const mc_sim *h, uint32_t n, uint64_t *bytes);
+mc_status mc_block_steps(mc_sim *h, uint32_t n, uint32_t step0, uint32_t n_steps, uint32_t flags,
+                         void *work, uint64_t work_bytes);
+mc_status mc_block_counts(mc_sim *h, void *work, uint64_t counts[3]);
+
 /* Work queues of persistent launches (MC_PERSISTENT).  The replicas of a
  * handle are independent Markov chains, so a launch may serve each replica
  * from one XCD:

@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmcheis.so")
 # device code: one translation unit per launch family (compiled in parallel)
 KERNEL_SOURCES = ["kernels_pass.hip", "kernels_basis_pair.hip", "kernels_persistent.hip",
-                  "kernels_lds.hip", "kernels_util.hip"]
+                  "kernels_lds.hip", "kernels_util.hip", "kernels_block.hip"]
 SOURCES = KERNEL_SOURCES + ["abi.cpp"]
 ARCH = os.environ.get("MCHEIS_ARCH", "gfx950")
 

@@ -1388,6 +1388,68 @@ mc_status mc_exchange_state(mc_sim *h, int32_t *replica_at_slot, double *T_slot,
     return xchg_pull(h);
 }
 
+mc_status mc_block_workspace(const mc_sim *h, uint32_t n, uint64_t *bytes)
+{
+    if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
+    if (!bytes) return fail(MC_E_ARG, "bytes is NULL");
+    if (n < 1) return fail(MC_E_ARG, "n (sites per block) must be >= 1");
+    uint64_t nb = 0;
+    for (const RepDev &R : h->reps) nb = std::max<uint64_t>(nb, (R.n_box + n - 1) / n);
+    const uint64_t esz = h->prec == MC_F64 ? 8 : 4;
+    *bytes = 256 + align_up(4 * nb, 256) + 3 * esz * nb;
+    return MC_OK;
+}
+
+mc_status mc_block_steps(mc_sim *h, uint32_t n, uint32_t step0, uint32_t n_steps, uint32_t flags,
+                         void *work, uint64_t work_bytes)
+{
+    if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
+    if (h->kind != MC_SC) return fail(MC_E_UNSUPPORTED, "the block scheme is built for sc lattices");
+    if (flags & ~(MC_BLOCK_CONFLICTS | MC_BLOCK_RESET))
+        return fail(MC_E_ARG, "unknown flags 0x%x", flags);
+    uint64_t need = 0;
+    mc_status st = mc_block_workspace(h, n, &need);
+    if (st != MC_OK) return st;
+    if (!work || reinterpret_cast<uintptr_t>(work) % 256)
+        return fail(MC_E_BUFFER, "block workspace is NULL or not 256-byte aligned");
+    if (work_bytes < need)
+        return fail(MC_E_BUFFER, "block workspace has %llu bytes, %llu needed",
+                    (unsigned long long)work_bytes, (unsigned long long)need);
+    if ((uint64_t)step0 + n_steps > 0xFFFFFFFFull) return fail(MC_E_ARG, "step counter would exceed 2^32-1");
+    uint64_t nb_max = 0;
+    for (const RepDev &R : h->reps) nb_max = std::max<uint64_t>(nb_max, (R.n_box + n - 1) / n);
+    char *w = (char *)work;
+    BlockLaunch B;
+    B.n = n;
+    B.seed_lo = (uint32_t)h->seed;
+    B.seed_hi = (uint32_t)(h->seed >> 32);
+    B.count_conflicts = (flags & MC_BLOCK_CONFLICTS) ? 1 : 0;
+    B.counts = (unsigned long long *)w;
+    B.stage_idx = (uint32_t *)(w + 256);
+    B.stage_spin = w + 256 + align_up(4 * nb_max, 256);
+    if ((st = xchg_pull(h)) != MC_OK) return st; // current temperatures into h->reps
+    if (flags & MC_BLOCK_RESET) HIP_TRY(launch_zero_u32((uint32_t *)w, 6, h->stream));
+    for (uint32_t j = 0; j < n_steps; ++j)
+        for (int r = 0; r < h->n_reps; ++r) {
+            B.rep = h->reps[r];
+            B.n_blocks = (uint32_t)((h->reps[r].n_box + n - 1) / n);
+            B.step = step0 + j;
+            HIP_TRY(launch_block_step(h->prec == MC_F64, B, h->stream));
+        }
+    return MC_OK;
+}
+
+mc_status mc_block_counts(mc_sim *h, void *work, uint64_t counts[3])
+{
+    if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
+    if (!work || !counts) return fail(MC_E_ARG, "work or counts is NULL");
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    HIP_TRY(hipMemcpy(counts, work, 3 * sizeof(uint64_t), hipMemcpyDeviceToHost));
+    HIP_TRY(launch_zero_u32((uint32_t *)work, 6, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return MC_OK;
+}
+
 mc_status mc_set_persistent_mode(mc_sim *h, mc_persist_mode mode)
 {
     if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");

@@ -197,14 +197,14 @@ __device__ __forceinline__ void block_store_partials(double (&a)[Q_N], double *d
     if (threadIdx.x >= Q_N && threadIdx.x < NQ) dst[threadIdx.x] = 0.0;
 }
 
-// One Metropolis attempt at a site with local field h (J already applied).
-// Returns the final spin in (sx, sy, sz).  Canonical site s keys the stream.
+// One Metropolis attempt with local field h (J already applied) from the
+// words w of its Philox block: proposal from w0, w1, acceptance uniform from
+// w2.  Returns the final spin in (sx, sy, sz).
 template <typename T>
-__device__ __forceinline__ bool metropolis(T &sx, T &sy, T &sz, T hx, T hy, T hz, uint32_t s,
-                                           uint32_t rid, uint32_t t, uint32_t k0, uint32_t k1,
-                                           T K, T ex, T ey, T ez, T beta, bool greedy, T &dH)
+__device__ __forceinline__ bool metropolis_words(const Words &w, T &sx, T &sy, T &sz, T hx, T hy,
+                                                 T hz, T K, T ex, T ey, T ez, T beta, bool greedy,
+                                                 T &dH)
 {
-    const Words w = philox10(s, rid, t, 0u, k0, k1);
     T nx, ny, nz;
     sphere_point(uniform23<T>(w.w0), uniform23<T>(w.w1), nx, ny, nz);
     const T P = uniform23<T>(w.w2);
@@ -221,6 +221,17 @@ __device__ __forceinline__ bool metropolis(T &sx, T &sy, T &sz, T hx, T hy, T hz
         sz = nz * inv;
     }
     return acc;
+}
+
+// The attempt of a colour pass: canonical site s, replica rid and sweep t key
+// the stream (counter (s, rid, t, 0)).
+template <typename T>
+__device__ __forceinline__ bool metropolis(T &sx, T &sy, T &sz, T hx, T hy, T hz, uint32_t s,
+                                           uint32_t rid, uint32_t t, uint32_t k0, uint32_t k1,
+                                           T K, T ex, T ey, T ez, T beta, bool greedy, T &dH)
+{
+    const Words w = philox10(s, rid, t, 0u, k0, k1);
+    return metropolis_words<T>(w, sx, sy, sz, hx, hy, hz, K, ex, ey, ez, beta, greedy, dH);
 }
 
 // FP64 accumulation of the observables of one final spin.  sh is the spin

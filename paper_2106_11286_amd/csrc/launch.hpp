@@ -114,6 +114,19 @@ struct ExchangeLaunch {
 };
 hipError_t launch_exchange(const ExchangeLaunch &L, hipStream_t st);
 
+// One synchronous step of the block scheme on one sc replica: block k of n
+// consecutive canonical sites picks a site from Philox counter
+// (k, rid, step, 3); staged moves are written by a second launch.
+struct BlockLaunch {
+    RepDev rep;
+    uint32_t n, n_blocks, step, seed_lo, seed_hi;
+    int count_conflicts;
+    uint32_t *stage_idx;            // [n_blocks] storage index of the accepted move, or ~0
+    void *stage_spin;               // [n_blocks][3] of the precision's type
+    unsigned long long *counts;     // attempts, accepted, conflicts (accumulated)
+};
+hipError_t launch_block_step(bool f64, const BlockLaunch &B, hipStream_t st);
+
 // XCC_ID of workgroups 0..n-1 (thread 0 of each writes one word).
 hipError_t launch_xcd_probe(uint32_t *out, uint32_t n, hipStream_t st);
 hipError_t launch_advance(uint32_t *tctr_dev, uint32_t n, hipStream_t st);

@@ -27,6 +27,8 @@ F32, F64 = 0, 1
 INIT_RANDOM, INIT_ALIGNED, INIT_USER = 0, 1, 2
 MEASURE = 1
 PERSISTENT = 2
+BLOCK_CONFLICTS = 4
+BLOCK_RESET = 8
 STATUS = {0: "MC_OK", -1: "MC_E_ARG", -2: "MC_E_UNSUPPORTED", -3: "MC_E_BUFFER",
           -4: "MC_E_DEVICE", -5: "MC_E_STATE"}
 KINDS = {"sc": SC, "bcc": BCC, "fcc": FCC}
@@ -106,6 +108,13 @@ _SIGNATURES = {
                                        ctypes.c_double, ctypes.POINTER(Stats)]),
     "mc_set_watchdog": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32]),
     "mc_set_persistent_mode": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "mc_block_workspace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32,
+                                          ctypes.POINTER(ctypes.c_uint64)]),
+    "mc_block_steps": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
+                                      ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p,
+                                      ctypes.c_uint64]),
+    "mc_block_counts": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.POINTER(ctypes.c_uint64)]),
     "mc_exchange_init": (ctypes.c_int, [ctypes.c_void_p]),
     "mc_exchange_sweep": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
                                          ctypes.c_uint32]),
@@ -317,6 +326,30 @@ class Simulation:
 
     def set_watchdog(self, spins: int):
         _check("mc_set_watchdog", LIB.mc_set_watchdog(self.handle, int(spins)))
+
+    def block_steps(self, n: int, step0: int, n_steps: int, conflicts: bool = True,
+                    reset: bool = False):
+        """``mc_block_steps``: n_steps synchronous steps of the paper's block
+        scheme (blocks of n sites) from step index step0; the workspace is
+        kept on the object (its counters are zeroed when it is created or
+        with reset)."""
+        need = ctypes.c_uint64()
+        _check("mc_block_workspace", LIB.mc_block_workspace(self.handle, int(n), ctypes.byref(need)))
+        ws = getattr(self, "_block_ws", None)
+        if ws is None or ws.numel() < need.value:
+            self._block_ws = torch.empty(int(need.value), dtype=torch.uint8, device=self.device)
+            reset = True
+        flags = (BLOCK_CONFLICTS if conflicts else 0) | (BLOCK_RESET if reset else 0)
+        _check("mc_block_steps", LIB.mc_block_steps(self.handle, int(n), int(step0), int(n_steps),
+                                                    flags, self._block_ws.data_ptr(),
+                                                    self._block_ws.numel()))
+
+    def block_counts(self):
+        """``mc_block_counts``: (attempts, accepted, conflicts) since the last
+        call, then zeroed."""
+        c = (ctypes.c_uint64 * 3)()
+        _check("mc_block_counts", LIB.mc_block_counts(self.handle, self._block_ws.data_ptr(), c))
+        return int(c[0]), int(c[1]), int(c[2])
 
     def exchange_init(self):
         """``mc_exchange_init``: start replica exchange over the current

@@ -50,6 +50,12 @@ EXCHANGE_SC64 = dict(
     J=1.0, K=0.01, e=(0.0, 0.0, 1.0), T_range=(1.41, 1.48), n_reps=32, seed=7,
     rounds=500, sweeps_per_round=4)
 
+# the paper's block scheme against the colour sweep on its Fig. 1 system:
+# sc 128^3, T = 0.9 T_C (T_C = 1.445 as printed), blocks of 8 sites
+BLOCK_SC128 = dict(
+    name="sc-L128-block-scheme-vs-colour-sweep", kind="sc", L=(128, 128, 128), periodic_mask=7,
+    J=1.0, K=0.01, e=(0.0, 0.0, 1.0), T=1.3, seed=8, n_block=8, n_equil=1000, n_meas=2000)
+
 REPLICA_KEYS = ("kind", "L", "periodic_mask", "sphere_radius", "J", "K", "e", "T", "replica_id")
 
 
