@@ -352,17 +352,20 @@ def run_big(M, L=1000, sweeps=20):
             "fused_vs_recomputed": {"E_rel": dE, "M_abs": dM, "ok": dE <= 1e-9 and dM <= 1e-12}}
 
 
-def run_bcc(M, W, sweeps):
-    """bcc at the 10^8 scale (2 x 368^3 = 99,672,064 spins, periodic): FP32 and
-    FP64 throughput on autotuned tiles, algorithmic bandwidth of a basis pass
-    (own basis read and written, the other basis read: 36 B per update FP32,
-    72 B FP64), and the fused FP64 observables against a recomputation."""
+def run_bcc(M, W, sweeps, w=None):
+    """bcc at the 10^8 scale (2 x 368^3 = 99,672,064 spins, periodic; or the
+    fcc workload passed as w): FP32 and FP64 throughput on autotuned tiles,
+    algorithmic bandwidth of a basis pass (own basis read and written, every
+    other basis read once: 36 B per update FP32 and 72 B FP64 for bcc, 60 and
+    120 B for fcc), and the fused FP64 observables against a recomputation."""
     import torch
 
-    w = W.BCC_368_1E8
+    w = w or W.BCC_368_1E8
     rep = M.Replica(**W.replica_fields(w))
     res = {"workload": w["name"], "sweeps": sweeps}
-    for prec, bpu in (("f32", 36), ("f64", 72)):
+    n_basis = 2 if w["kind"] == "bcc" else 4
+    b32 = 12 * (n_basis + 1)
+    for prec, bpu in (("f32", b32), ("f64", 2 * b32)):
         sim = M.Simulation([rep], precision=prec, seed=w["seed"],
                            scratch=torch.empty(64 << 20, dtype=torch.uint8, device="cuda"))
         N = sim.n_occ[0]
@@ -374,7 +377,7 @@ def run_bcc(M, W, sweeps):
         full = sim.measure_state()[0]
         dE = abs(fused["E"] - full["E"]) / abs(full["E"])
         dM = float(max(abs(a - b) for a, b in zip(fused["M"], full["M"])))
-        gbps = bpu * N / 2 / (pass_ms * 1e-3) / 1e9
+        gbps = bpu * N / n_basis / (pass_ms * 1e-3) / 1e9
         res["spins"] = N
         res[prec] = {"default_tile": list(default), "tile": list(tile),
                      "updates_per_ns": N * sweeps / (total_ms * 1e6), "pass_ms": pass_ms,
@@ -382,7 +385,7 @@ def run_bcc(M, W, sweeps):
                      "acceptance": fused["n_accepted"] / N,
                      "fused_vs_recomputed": {"E_rel": dE, "M_abs": dM,
                                              "ok": dE <= 1e-9 and dM <= 1e-12}}
-        log(f"[bench] bcc {prec}: {res[prec]['updates_per_ns']:.1f} updates/ns, tile {tile}, "
+        log(f"[bench] {w['kind']} {prec}: {res[prec]['updates_per_ns']:.1f} updates/ns, tile {tile}, "
             f"pass {pass_ms * 1e3:.1f} us, {gbps:.0f} GB/s algorithmic")
         sim.close()
         del sim
@@ -584,7 +587,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--workload", default="c5",
-                    choices=["c5", "c1", "c2", "c3", "c4", "f1", "big", "bcc", "exchange", "block"],
+                    choices=["c5", "c1", "c2", "c3", "c4", "f1", "big", "bcc", "fcc", "exchange",
+                             "block"],
                     help="c5 (default): the 10^8-spin headline; others print their own line "
                          "(f1: the paper's M(T) accuracy experiment)")
     ap.add_argument("--f1-sizes", default="128,256,512")
@@ -624,6 +628,8 @@ def main():
             out = run_big(M)
         elif args.workload == "bcc":
             out = run_bcc(M, W, W.BCC_368_1E8["sweeps"])
+        elif args.workload == "fcc":
+            out = run_bcc(M, W, W.FCC_292_1E8["sweeps"], W.FCC_292_1E8)
         elif args.workload == "exchange":
             out = run_exchange(M, W)
         elif args.workload == "block":

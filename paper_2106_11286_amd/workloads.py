@@ -43,6 +43,11 @@ BCC_368_1E8 = dict(
     name="bcc-L368-1e8-spins", kind="bcc", L=(368, 368, 368), periodic_mask=7,
     J=1.0, K=0.02, e=(0.0, 0.0, 1.0), T=1.9, seed=6, sweeps=200)
 
+# fcc at the same scale: 4 x 292^3 = 99,588,352 spins, periodic
+FCC_292_1E8 = dict(
+    name="fcc-L292-1e8-spins", kind="fcc", L=(292, 292, 292), periodic_mask=7,
+    J=1.0, K=0.02, e=(0.0, 0.0, 1.0), T=2.8, seed=9, sweeps=100)
+
 # replica exchange across the critical region: 32 copies of one sc 64^3
 # lattice at temperatures evenly spaced over 1.41 .. 1.48 (about 0.0023 apart)
 EXCHANGE_SC64 = dict(

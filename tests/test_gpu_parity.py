@@ -715,6 +715,55 @@ def test_full_size_fcc_particle_sampled(M):
         assert checked >= 1500
 
 
+def test_full_size_fcc_sampled(M):
+    """fcc at the benchmark's scale (4 x 292^3 = 99,588,352 spins, FP32, the
+    autotuned tile): after the tuning sweeps and 5 more, all four colour
+    passes of the next sweep at 1000 sampled sites each against the oracle,
+    and the fused observables against a recomputation."""
+    import torch
+
+    w = W.FCC_292_1E8
+    rep = M.Replica(**W.replica_fields(w))
+    sim = M.Simulation([rep], precision="f32", seed=w["seed"],
+                       scratch=torch.empty(64 << 20, dtype=torch.uint8, device="cuda"))
+    tile = sim.autotune(trial_sweeps=2, measure=True)
+    print("autotuned tile", tile)
+    sim.sweep(4)
+    sim.sweep(1, measure=True)
+    fused = sim.observables()[0]
+    full = sim.measure_state()[0]
+    assert fused["n_sites"] == 4 * 292**3
+    assert abs(fused["E"] - full["E"]) <= 1e-9 * abs(full["E"])
+    assert np.max(np.abs(fused["M"] - full["M"])) <= 1e-12
+    geo = O.Geometry(O.FCC, *rep.L, periodic_mask=rep.periodic_mask)
+    p = oracle_params(rep, w["seed"])
+    rng = np.random.default_rng(292)
+    t = sim.get_sweep()
+    cells_n = 292**3
+    n_flip = 0
+    for colour in range(4):
+        before = natural(sim)
+        dh, acc = sim.debug_pass(colour)
+        after = natural(sim)
+        cells = rng.integers(0, cells_n, size=1000)
+        k = torch_index(colour * cells_n + cells)
+        dhs = dh[0][k].double().cpu().numpy()
+        accs = acc[0][k].cpu().numpy()
+        del dh, acc
+        for j, cell in enumerate(cells):
+            site = int(cell) * 4 + colour
+            r = geo.site_attempt(p, t, before, site)
+            assert abs(dhs[j] - r["dH"]) <= 1e-5 * max(abs(r["dH"]), 1.0), (site, dhs[j], r)
+            if bool(accs[j]) != r["accepted"]:
+                assert abs(r["margin"]) < 1e-4, (site, r)
+                n_flip += 1
+                continue
+            got = np.array([after[0][site], after[1][site], after[2][site]])
+            assert np.max(np.abs(got - r["S_after"])) <= 2e-6
+        del before, after
+    assert n_flip <= 2
+
+
 def test_full_size_bcc_sampled(M):
     """bcc at the benchmark's scale (2 x 368^3 = 99,672,064 spins, FP32, the
     autotuned tile): after the tuning sweeps and 10 more, both colour passes of
