@@ -279,10 +279,10 @@ def run_c2(M, W, init="random"):
 
 
 def run_c3(M, W, sweeps):
-    """64 sc replicas (L in {32, 48, 64, 96}, T 0.8 .. 2.0), FP32, all advanced
-    by one persistent launch per call, with one work queue per XCD and with a
-    single queue; also the same sweeps as per-pass launches.  Each mode runs
-    on its own autotuned tile."""
+    """64 sc replicas (L in {32, 48, 64, 96}, T 0.8 .. 2.0), FP32: the sweeps as
+    graph-replayed per-pass launches, and as one persistent launch per call
+    with one work queue per XCD and with a single queue.  Each mode runs on
+    its own autotuned tile."""
     import torch
 
     w = W.C3_BATCHED

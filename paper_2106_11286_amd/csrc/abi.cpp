@@ -317,7 +317,7 @@ void make_work(const mc_replica_desc *reps, int n, const Tile &t, std::vector<Wo
 }
 
 struct ScratchLayout {
-    uint64_t off_ctr, off_reps, off_work, off_partials, off_records, off_stage, off_count,
+    uint64_t off_ctr, off_reps, off_work, off_partials, off_records, off_stage,
         off_persist, off_queues, off_exchange, total;
 };
 
@@ -347,8 +347,6 @@ ScratchLayout scratch_layout(int n_reps, uint64_t n_items, int n_colours)
     o = align_up(o + sizeof(double) * NR * n_reps * (kRing + 1), 256);
     L.off_stage = o;
     o = align_up(o + sizeof(double) * NQ * FIN_BLOCKS * n_reps, 256);
-    L.off_count = o;
-    o = align_up(o + sizeof(uint32_t) * n_reps, 256);
     L.off_persist = o;
     o = align_up(o + sizeof(uint32_t) * persist_state_words(n_reps), 256);
     L.off_queues = o;
@@ -409,7 +407,6 @@ struct mc_sim {
     double *partials = nullptr;
     double *records = nullptr;
     double *stage = nullptr;    // finalise stage slots
-    uint32_t *fin_count = nullptr;
     uint32_t *pstate = nullptr; // persistent-launch counters
     uint32_t *queues_dev = nullptr; // queue offsets [16], then queue items
     // replica exchange (mc_exchange_*): device table in scratch, host ladder
@@ -505,7 +502,7 @@ mc_status enqueue_sweeps(mc_sim *h, uint32_t n, bool measure, uint32_t slot0)
             const uint32_t slot = (slot0 + i) % kRing;
             HIP_TRY(launch_finalize(h->reps_dev, h->n_reps, h->n_colours, h->partials, n_items,
                                     h->tctr, i, h->records + (size_t)slot * h->n_reps * NR,
-                                    h->stage, h->fin_count, h->stream));
+                                    h->stage, h->stream));
         }
     }
     HIP_TRY(launch_advance(h->tctr, n, h->stream));
@@ -987,7 +984,6 @@ mc_status mc_init_lattice(const mc_replica_desc *reps, int32_t n_reps, mc_precis
     h->partials = (double *)(h->scratch + h->lay.off_partials);
     h->records = (double *)(h->scratch + h->lay.off_records);
     h->stage = (double *)(h->scratch + h->lay.off_stage);
-    h->fin_count = (uint32_t *)(h->scratch + h->lay.off_count);
     h->pstate = (uint32_t *)(h->scratch + h->lay.off_persist);
     h->queues_dev = (uint32_t *)(h->scratch + h->lay.off_queues);
 
@@ -1033,7 +1029,6 @@ mc_status mc_init_lattice(const mc_replica_desc *reps, int32_t n_reps, mc_precis
     if (hipMemcpyAsync(h->work_dev, h->work.data(), sizeof(WorkItem) * h->work.size(),
                        hipMemcpyHostToDevice, h->stream) != hipSuccess ||
         launch_set_counter(h->tctr, 0u, h->stream) != hipSuccess ||
-        launch_zero_u32(h->fin_count, (uint32_t)n_reps, h->stream) != hipSuccess ||
         launch_zero_u32(h->pstate, persist_state_words(n_reps), h->stream) != hipSuccess)
         return cleanup(fail(MC_E_DEVICE, "upload failed: %s", hipGetErrorString(hipGetLastError())));
     if (init != MC_INIT_USER) {
@@ -1141,7 +1136,7 @@ mc_status mc_sweep_timed(mc_sim *h, uint32_t n_sweeps, uint32_t flags, double *p
             err = launch_finalize(h->reps_dev, h->n_reps, h->n_colours, h->partials, n_items,
                                   h->tctr, i,
                                   h->records + (size_t)((slot0 + i) % kRing) * h->n_reps * NR,
-                                  h->stage, h->fin_count, h->stream);
+                                  h->stage, h->stream);
     }
     if (err == hipSuccess) err = launch_advance(h->tctr, n_sweeps, h->stream);
     if (err == hipSuccess) err = hipEventRecord(ev[2 * n_pass + 1], h->stream);
@@ -1200,7 +1195,7 @@ mc_status mc_measure_state(mc_sim *h, mc_obs *out, int32_t n_reps)
     for (int c = 0; c < h->n_colours; ++c) HIP_TRY(launch_pass(h->kind, f64, c, true, 1, p, h->stream));
     double *dst = h->records + (size_t)kRing * h->n_reps * NR;
     HIP_TRY(launch_finalize(h->reps_dev, h->n_reps, h->n_colours, h->partials, n_items, h->tctr,
-                            0, dst, h->stage, h->fin_count, h->stream));
+                            0, dst, h->stage, h->stream));
     HIP_TRY(hipMemcpyAsync(h->host_rec, dst, sizeof(double) * NR * h->n_reps,
                            hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
@@ -1586,11 +1581,9 @@ mc_status mc_set_tile(mc_sim *h, int32_t kernel, int32_t tx, int32_t ty, int32_t
     h->partials = (double *)(h->scratch + lay.off_partials);
     h->records = (double *)(h->scratch + lay.off_records);
     h->stage = (double *)(h->scratch + lay.off_stage);
-    h->fin_count = (uint32_t *)(h->scratch + lay.off_count);
     h->pstate = (uint32_t *)(h->scratch + lay.off_persist);
     h->queues_dev = (uint32_t *)(h->scratch + lay.off_queues);
     h->last_slot = -1;
-    HIP_TRY(launch_zero_u32(h->fin_count, (uint32_t)h->n_reps, h->stream));
     HIP_TRY(launch_zero_u32(h->pstate, persist_state_words(h->n_reps), h->stream));
     for (int r = 0; r < h->n_reps; ++r) {
         h->reps[r].item_begin = b[r];

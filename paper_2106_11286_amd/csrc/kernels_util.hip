@@ -91,16 +91,17 @@ k_layout(RepDev R, int kind, int to_natural, T *nx, T *ny, T *nz)
 }
 
 // ---------------------------------------------------------------------------
-// Finalise: FIN_BLOCKS blocks per replica each sum a contiguous share of the
-// replica's partial slots (all passes) into a stage slot; the last block to
-// finish (counted with an agent-scope atomic) sums the stage slots in index
-// order and writes the FP64 record, then re-arms the counter.  The result
-// depends only on the work list, not on block timing.
+// Finalise, two launches: FIN_BLOCKS blocks per replica each sum a contiguous
+// share of the replica's partial slots (all passes) into a stage slot; then
+// one workgroup per replica sums the stage slots in index order and writes
+// the FP64 record.  The launch boundary orders the two steps, so no block
+// waits for, or publishes to, another; the result depends only on the work
+// list.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256)
-k_finalize(const RepDev *__restrict__ reps, int n_colours, const double *__restrict__ partials,
-           uint32_t n_items, const uint32_t *__restrict__ tctr, uint32_t t_off,
-           double *__restrict__ records, double *__restrict__ stage, uint32_t *__restrict__ count)
+k_finalize_stage(const RepDev *__restrict__ reps, int n_colours,
+                 const double *__restrict__ partials, uint32_t n_items,
+                 double *__restrict__ stage)
 {
     const uint32_t r = blockIdx.x / FIN_BLOCKS, j = blockIdx.x % FIN_BLOCKS;
     const RepDev &R = reps[r];
@@ -114,38 +115,29 @@ k_finalize(const RepDev *__restrict__ reps, int n_colours, const double *__restr
 #pragma unroll
             for (int q = 0; q < Q_N; ++q) a[q] += p[q];
         }
-    double *slot = stage + ((size_t)r * FIN_BLOCKS + j) * NQ;
-    block_store_partials(a, slot);
-    __shared__ uint32_t last;
-    __threadfence(); // the stage slot is visible device-wide before it is counted
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const uint32_t done = __hip_atomic_fetch_add(&count[r], 1u, __ATOMIC_ACQ_REL,
-                                                     __HIP_MEMORY_SCOPE_AGENT);
-        last = done == FIN_BLOCKS - 1;
-    }
-    __syncthreads();
-    if (!last) return;
-    if (threadIdx.x == 0) {
-        __atomic_thread_fence(__ATOMIC_ACQUIRE);
-        double out[Q_N] = {0, 0, 0, 0, 0, 0};
-        const double *st = stage + (size_t)r * FIN_BLOCKS * NQ;
-        for (uint32_t b = 0; b < FIN_BLOCKS; ++b)
+    block_store_partials(a, stage + ((size_t)r * FIN_BLOCKS + j) * NQ);
+}
+
+__global__ void __launch_bounds__(64)
+k_finalize_record(const RepDev *__restrict__ reps, const uint32_t *__restrict__ tctr,
+                  uint32_t t_off, const double *__restrict__ stage, double *__restrict__ records)
+{
+    if (threadIdx.x != 0) return;
+    const uint32_t r = blockIdx.x;
+    double out[Q_N] = {0, 0, 0, 0, 0, 0};
+    const double *st = stage + (size_t)r * FIN_BLOCKS * NQ;
+    for (uint32_t b = 0; b < FIN_BLOCKS; ++b)
 #pragma unroll
-            for (int q = 0; q < Q_N; ++q)
-                out[q] += __hip_atomic_load(&st[b * NQ + q], __ATOMIC_RELAXED,
-                                            __HIP_MEMORY_SCOPE_AGENT);
-        double *rec = records + (size_t)r * NR;
-        rec[R_MX] = out[Q_MX];
-        rec[R_MY] = out[Q_MY];
-        rec[R_MZ] = out[Q_MZ];
-        rec[R_EEX] = -out[Q_SH];
-        rec[R_EAN] = -R.K * out[Q_PE2];
-        rec[R_NACC] = out[Q_NACC];
-        rec[R_SWEEP] = (double)(*tctr + t_off) + 1.0;
-        rec[7] = 0.0;
-        __hip_atomic_store(&count[r], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+        for (int q = 0; q < Q_N; ++q) out[q] += st[b * NQ + q];
+    double *rec = records + (size_t)r * NR;
+    rec[R_MX] = out[Q_MX];
+    rec[R_MY] = out[Q_MY];
+    rec[R_MZ] = out[Q_MZ];
+    rec[R_EEX] = -out[Q_SH];
+    rec[R_EAN] = -reps[r].K * out[Q_PE2];
+    rec[R_NACC] = out[Q_NACC];
+    rec[R_SWEEP] = (double)(*tctr + t_off) + 1.0;
+    rec[7] = 0.0;
 }
 
 __global__ void k_advance(uint32_t *tctr, uint32_t n)
@@ -225,11 +217,12 @@ hipError_t launch_layout(bool f64, int kind, const RepDev *rep_host, bool to_nat
 hipError_t launch_finalize(const RepDev *reps_dev, int n_reps, int n_colours,
                            const double *partials_dev, uint32_t n_items,
                            const uint32_t *tctr_dev, uint32_t t_off, double *records_dev,
-                           double *stage_dev, uint32_t *count_dev, hipStream_t st)
+                           double *stage_dev, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_finalize, dim3(n_reps * FIN_BLOCKS), dim3(256), 0, st, reps_dev,
-                       n_colours, partials_dev, n_items, tctr_dev, t_off, records_dev, stage_dev,
-                       count_dev);
+    hipLaunchKernelGGL(k_finalize_stage, dim3(n_reps * FIN_BLOCKS), dim3(256), 0, st, reps_dev,
+                       n_colours, partials_dev, n_items, stage_dev);
+    hipLaunchKernelGGL(k_finalize_record, dim3(n_reps), dim3(64), 0, st, reps_dev, tctr_dev, t_off,
+                       stage_dev, records_dev);
     return hipGetLastError();
 }
 

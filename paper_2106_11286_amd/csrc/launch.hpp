@@ -38,13 +38,12 @@ hipError_t launch_init(bool f64, int kind, const RepDev *rep_host, int mode, uin
 hipError_t launch_layout(bool f64, int kind, const RepDev *rep_host, bool to_natural, void *nx,
                          void *ny, void *nz, hipStream_t st);
 
-// Reduce partials of every pass into one record per replica.  stage_dev holds
-// n_reps * FIN_BLOCKS * NQ doubles; count_dev n_reps counters that must be zero
-// before the first call (each call leaves them zero).
+// Reduce partials of every pass into one record per replica (two launches).
+// stage_dev holds n_reps * FIN_BLOCKS * NQ doubles.
 hipError_t launch_finalize(const RepDev *reps_dev, int n_reps, int n_colours,
                            const double *partials_dev, uint32_t n_items,
                            const uint32_t *tctr_dev, uint32_t t_off, double *records_dev,
-                           double *stage_dev, uint32_t *count_dev, hipStream_t st);
+                           double *stage_dev, hipStream_t st);
 hipError_t launch_zero_u32(uint32_t *p, uint32_t n, hipStream_t st);
 
 // One persistent launch that runs n_sweeps sweeps of every replica.  Work units
