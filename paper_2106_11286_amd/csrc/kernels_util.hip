@@ -122,13 +122,22 @@ __global__ void __launch_bounds__(64)
 k_finalize_record(const RepDev *__restrict__ reps, const uint32_t *__restrict__ tctr,
                   uint32_t t_off, const double *__restrict__ stage, double *__restrict__ records)
 {
-    if (threadIdx.x != 0) return;
-    const uint32_t r = blockIdx.x;
-    double out[Q_N] = {0, 0, 0, 0, 0, 0};
+    // lane q sums observable q over the stage slots in slot order; all its
+    // loads are issued before the first add
+    __shared__ double out[Q_N];
+    const uint32_t r = blockIdx.x, q = threadIdx.x;
     const double *st = stage + (size_t)r * FIN_BLOCKS * NQ;
-    for (uint32_t b = 0; b < FIN_BLOCKS; ++b)
+    if (q < (uint32_t)Q_N) {
+        double v[FIN_BLOCKS];
 #pragma unroll
-        for (int q = 0; q < Q_N; ++q) out[q] += st[b * NQ + q];
+        for (uint32_t b = 0; b < FIN_BLOCKS; ++b) v[b] = st[b * NQ + q];
+        double sum = 0.0;
+#pragma unroll
+        for (uint32_t b = 0; b < FIN_BLOCKS; ++b) sum += v[b];
+        out[q] = sum;
+    }
+    __syncthreads();
+    if (q != 0) return;
     double *rec = records + (size_t)r * NR;
     rec[R_MX] = out[Q_MX];
     rec[R_MY] = out[Q_MY];
