@@ -607,8 +607,8 @@ def main():
         if len(tile) != 4:
             ap.error("--tile takes kernel,tx,ty,zc")
     if args.gpus != 1:
-        print(f"bench.py: --gpus {args.gpus} is not supported: this build runs the sweep on one "
-              "GPU (multi-GPU slab decomposition is a design note only)", file=sys.stderr)
+        print(f"bench.py: --gpus {args.gpus} is not supported: the sweep runs on one GPU "
+              "(the multi-GPU slab decomposition is described, not implemented)", file=sys.stderr)
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
     import torch
