@@ -961,6 +961,11 @@ def test_xcd_queue_auto_and_retile(M):
     if q != 8:
         pytest.skip("device does not deal workgroups to eight XCDs in turn")
     assert M.Simulation(reps[:2], precision="f32", seed=43).persistent_queues() == 1
+    # eight replicas, one of them far larger than the rest: the best deal
+    # leaves one queue with most of the work, so auto mode keeps one queue
+    skew = [M.Replica(kind="sc", L=(64, 64, 64) if r == 0 else (8, 8, 8), T=1.0, replica_id=r)
+            for r in range(8)]
+    assert M.Simulation(skew, precision="f32", seed=43).persistent_queues() == 1
     a.sweep(3, persistent=True)
     a.set_tile(32, 8, 4, kernel=0)
     assert a.persistent_queues() == 8
