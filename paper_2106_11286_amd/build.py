@@ -17,7 +17,9 @@ LIB = os.path.join(HERE, "libmcheis.so")
 # device code: one translation unit per launch family (compiled in parallel)
 KERNEL_SOURCES = ["kernels_pass.hip", "kernels_basis_pair.hip", "kernels_persistent.hip",
                   "kernels_lds.hip", "kernels_util.hip", "kernels_block.hip"]
-SOURCES = KERNEL_SOURCES + ["abi.cpp"]
+# host runtime behind the C ABI
+HOST_SOURCES = ["abi.cpp", "abi_tune.cpp", "abi_stats.cpp", "abi_extensions.cpp"]
+SOURCES = KERNEL_SOURCES + HOST_SOURCES
 ARCH = os.environ.get("MCHEIS_ARCH", "gfx950")
 
 

@@ -1,6 +1,9 @@
 // abi.cpp -- host runtime behind the C ABI (include/mcheis.h): argument and
 // buffer validation, the colouring/tiling plan, the scratch layout, sweep
-// scheduling with HIP graph replay, observable records and series statistics.
+// scheduling with HIP graph replay and persistent launches, observable
+// records and the temperature schedule.  The autotuner, the series
+// statistics and the extensions (replica exchange, block scheme) live in
+// abi_tune.cpp, abi_stats.cpp and abi_extensions.cpp.
 //
 // The library allocates no spin or scratch memory: the caller owns both (in
 // practice as framework tensors) and the stream.  The only allocation it makes
@@ -20,13 +23,9 @@
 #include <string>
 #include <vector>
 
-#include "launch.hpp"
-#include "mc_internal.hpp"
-#include "mcheis.h"
+#include "abi_internal.h"
 
-using namespace mc;
-
-namespace {
+namespace mcabi {
 
 thread_local std::string g_err;
 
@@ -40,21 +39,6 @@ mc_status fail(mc_status s, const char *fmt, ...)
     g_err = buf;
     return s;
 }
-
-#define HIP_TRY(expr)                                                                    \
-    do {                                                                                 \
-        hipError_t e_ = (expr);                                                          \
-        if (e_ != hipSuccess)                                                            \
-            return fail(MC_E_DEVICE, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_),     \
-                        __FILE__, __LINE__);                                             \
-    } while (0)
-
-constexpr uint32_t kRing = 256;       // observable records kept per replica
-// LDS kept back from the dynamic allocation of the LDS kernel for its static
-// arrays (reduction slots).
-constexpr uint32_t kLdsReserve = 2048;
-constexpr uint32_t kTargetItems = 8192; // work items aimed for per pass
-constexpr uint32_t kGraphChunk = 64;  // sweeps per captured graph
 
 int n_basis(int kind) { return kind == SC ? 1 : (kind == BCC ? 2 : 4); }
 int n_colours_of(int kind) { return kind == SC ? 2 : n_basis(kind); }
@@ -316,15 +300,6 @@ void make_work(const mc_replica_desc *reps, int n, const Tile &t, std::vector<Wo
     }
 }
 
-struct ScratchLayout {
-    uint64_t off_ctr, off_reps, off_work, off_partials, off_records, off_stage,
-        off_persist, off_queues, off_exchange, total;
-};
-
-// Words of the persistent-queue region: 16 queue offsets, then every item
-// index once (at least 64 words: it also takes the XCD probe's output).
-inline uint64_t queue_words(uint64_t n_items) { return 16 + std::max<uint64_t>(n_items, 64); }
-
 ScratchLayout scratch_layout(int n_reps, uint64_t n_items, int n_colours)
 {
     ScratchLayout L;
@@ -384,50 +359,10 @@ mc_status check_device_buffer(const void *p, uint64_t bytes, const char *what, i
     return MC_OK;
 }
 
-} // namespace
+} // namespace mcabi
 
-struct mc_sim {
-    int32_t n_reps = 0, kind = 0, n_colours = 0;
-    mc_precision prec = MC_F32;
-    uint64_t seed = 0;
-    std::vector<mc_replica_desc> desc;
-    std::vector<RepDev> reps;
-    std::vector<uint64_t> n_occ;
-    std::vector<WorkItem> work;
-    Tile tile{};      // kernel of whole sweeps
-    Tile pass_tile{}; // kernel of single passes (= tile unless tile is the LDS kernel)
-    uint32_t lds_max = 0; // dynamic LDS a workgroup may use on this device (bytes)
-    hipStream_t stream = nullptr;
-    char *scratch = nullptr;
-    uint64_t scratch_bytes = 0;
-    ScratchLayout lay{};
-    uint32_t *tctr = nullptr;
-    RepDev *reps_dev = nullptr;
-    WorkItem *work_dev = nullptr;
-    double *partials = nullptr;
-    double *records = nullptr;
-    double *stage = nullptr;    // finalise stage slots
-    uint32_t *pstate = nullptr; // persistent-launch counters
-    uint32_t *queues_dev = nullptr; // queue offsets [16], then queue items
-    // replica exchange (mc_exchange_*): device table in scratch, host ladder
-    bool xchg_active = false;
-    std::vector<double> xchg_T, xchg_beta; // per slot
-    std::vector<uint32_t> xchg_rep_host;   // upload staging
-    uint32_t spin_limit = 1u << 24;
-    bool persist_used = false;
-    int persist_mode = MC_PERSIST_AUTO;
-    bool xcd_ok = false;            // workgroups are dealt to 8 XCDs in turn
-    uint32_t n_queues = 1, max_queue_items = 0;
-    std::vector<uint32_t> q_host;   // queue table as uploaded (offsets [16], items)
-    double *host_rec = nullptr; // pinned, (kRing + 1) * n_reps * NR
-    uint64_t t = 0;             // sweeps done
-    uint64_t n_measured = 0;
-    int64_t last_slot = -1;
-    std::map<std::pair<uint32_t, uint32_t>, hipGraphExec_t> graphs;
-    uint32_t magic = 0x4d434831u;
-};
 
-namespace {
+namespace mcabi {
 
 bool alive(const mc_sim *h) { return h && h->magic == 0x4d434831u; }
 
@@ -677,46 +612,6 @@ void set_temperature(RepDev &R, double T)
     R.beta = (T > 0.0 && std::isfinite(T)) ? 1.0 / T : 0.0;
 }
 
-// Device pointers of the replica-exchange table (scratch, off_exchange).
-struct XchgPtrs {
-    double *beta;
-    uint64_t *attempted, *accepted;
-    uint32_t *rep_at, *round;
-};
-XchgPtrs xchg_ptrs(const mc_sim *h)
-{
-    char *b = h->scratch + h->lay.off_exchange;
-    const size_t n = (size_t)h->n_reps;
-    return {(double *)b, (uint64_t *)(b + 8 * n), (uint64_t *)(b + 16 * n),
-            (uint32_t *)(b + 24 * n), (uint32_t *)(b + 28 * n)};
-}
-
-// While exchange is active the device descriptors hold each replica's current
-// temperature; copy it into the host descriptors (before they are uploaded).
-mc_status xchg_pull(mc_sim *h)
-{
-    if (!h->xchg_active) return MC_OK;
-    std::vector<uint32_t> rep_at(h->n_reps);
-    HIP_TRY(hipStreamSynchronize(h->stream));
-    HIP_TRY(hipMemcpy(rep_at.data(), xchg_ptrs(h).rep_at, sizeof(uint32_t) * h->n_reps,
-                      hipMemcpyDeviceToHost));
-    for (int k = 0; k < h->n_reps; ++k) {
-        const uint32_t r = rep_at[k];
-        if (r >= (uint32_t)h->n_reps) return fail(MC_E_DEVICE, "exchange table corrupted");
-        h->desc[r].T = h->xchg_T[k];
-        set_temperature(h->reps[r], h->xchg_T[k]);
-    }
-    return MC_OK;
-}
-
-// Identical lattices and couplings (all but T and replica_id).
-bool same_system(const mc_replica_desc &a, const mc_replica_desc &b)
-{
-    return a.kind == b.kind && a.Lx == b.Lx && a.Ly == b.Ly && a.Lz == b.Lz &&
-           a.periodic_mask == b.periodic_mask && a.sphere_radius == b.sphere_radius &&
-           a.J == b.J && a.K == b.K && a.e[0] == b.e[0] && a.e[1] == b.e[1] && a.e[2] == b.e[2];
-}
-
 mc_status upload_reps(mc_sim *h)
 {
     {
@@ -764,71 +659,9 @@ mc_status run_chunk(mc_sim *h, uint32_t n, bool measure, uint32_t slot0, bool pe
     return MC_OK;
 }
 
-// ---- statistics (product side) ------------------------------------------
-double mean_of(const std::vector<double> &x)
-{
-    double s = 0.0;
-    for (double v : x) s += v;
-    return x.empty() ? 0.0 : s / (double)x.size();
-}
+} // namespace mcabi
 
-// Standard error of the mean of a correlated series: repeated pairwise
-// blocking (Flyvbjerg & Petersen 1989), maximum over levels with >= 32 blocks.
-double blocked_error(std::vector<double> x)
-{
-    double best = 0.0;
-    while (x.size() >= 32) {
-        const double m = mean_of(x);
-        double v = 0.0;
-        for (double a : x) v += (a - m) * (a - m);
-        v /= (double)(x.size() - 1);
-        best = std::max(best, std::sqrt(v / (double)x.size()));
-        std::vector<double> y(x.size() / 2);
-        for (size_t i = 0; i < y.size(); ++i) y[i] = 0.5 * (x[2 * i] + x[2 * i + 1]);
-        x.swap(y);
-    }
-    if (best == 0.0 && x.size() > 1) {
-        const double m = mean_of(x);
-        double v = 0.0;
-        for (double a : x) v += (a - m) * (a - m);
-        best = std::sqrt(v / (double)(x.size() - 1) / (double)x.size());
-    }
-    return best;
-}
-
-// Error of the Binder cumulant U4 = 1 - <m^4>/(3 <m^2>^2): delete-one-block
-// jackknife over B = min(32, n) contiguous blocks, record i in block
-// floor(B i / n).
-double binder_jackknife(const std::vector<double> &m2, const std::vector<double> &m4)
-{
-    const size_t n = m2.size();
-    const size_t B = std::min<size_t>(32, n);
-    if (B < 2) return 0.0;
-    std::vector<double> s2(B, 0.0), s4(B, 0.0), cnt(B, 0.0);
-    double t2 = 0.0, t4 = 0.0;
-    for (size_t i = 0; i < n; ++i) {
-        const size_t b = (size_t)(((unsigned __int128)i * B) / n);
-        s2[b] += m2[i];
-        s4[b] += m4[i];
-        cnt[b] += 1.0;
-        t2 += m2[i];
-        t4 += m4[i];
-    }
-    std::vector<double> u(B);
-    double mu = 0.0;
-    for (size_t b = 0; b < B; ++b) {
-        const double rest = (double)n - cnt[b];
-        const double q2 = (t2 - s2[b]) / rest, q4 = (t4 - s4[b]) / rest;
-        u[b] = 1.0 - q4 / (3.0 * q2 * q2);
-        mu += u[b];
-    }
-    mu /= (double)B;
-    double v = 0.0;
-    for (double x : u) v += (x - mu) * (x - mu);
-    return std::sqrt(v * (double)(B - 1) / (double)B);
-}
-
-} // namespace
+using namespace mcabi;
 
 extern "C" {
 
@@ -1278,173 +1111,6 @@ mc_status mc_run_schedule(mc_sim *h, const mc_schedule *s, mc_obs *series, uint6
     return MC_OK;
 }
 
-mc_status mc_exchange_init(mc_sim *h)
-{
-    if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
-    const int n = h->n_reps;
-    if (n < 2) return fail(MC_E_ARG, "replica exchange needs at least 2 replicas");
-    for (int r = 0; r < n; ++r) {
-        if (!same_system(h->desc[r], h->desc[0]))
-            return fail(MC_E_ARG, "replica %d: exchange needs replicas that differ only in T and "
-                                  "replica_id", r);
-        const double T = h->desc[r].T;
-        if (!(T > 0.0) || !std::isfinite(T))
-            return fail(MC_E_ARG, "replica %d: exchange needs 0 < T < inf (T = %g)", r, T);
-    }
-    HIP_TRY(hipStreamSynchronize(h->stream));
-    std::vector<int> order(n);
-    for (int r = 0; r < n; ++r) order[r] = r;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int b) { return h->desc[a].T < h->desc[b].T; });
-    h->xchg_T.resize(n);
-    h->xchg_beta.resize(n);
-    h->xchg_rep_host.resize(n);
-    for (int k = 0; k < n; ++k) {
-        h->xchg_T[k] = h->desc[order[k]].T;
-        h->xchg_beta[k] = 1.0 / h->xchg_T[k];
-        h->xchg_rep_host[k] = (uint32_t)order[k];
-    }
-    const XchgPtrs x = xchg_ptrs(h);
-    HIP_TRY(hipMemcpyAsync(x.beta, h->xchg_beta.data(), sizeof(double) * n, hipMemcpyHostToDevice,
-                           h->stream));
-    HIP_TRY(hipMemcpyAsync(x.rep_at, h->xchg_rep_host.data(), sizeof(uint32_t) * n,
-                           hipMemcpyHostToDevice, h->stream));
-    HIP_TRY(launch_zero_u32((uint32_t *)x.attempted, 4u * (uint32_t)n, h->stream));
-    HIP_TRY(launch_zero_u32(x.round, 1u, h->stream));
-    HIP_TRY(hipStreamSynchronize(h->stream));
-    h->xchg_active = true;
-    return MC_OK;
-}
-
-mc_status mc_exchange_sweep(mc_sim *h, uint32_t n_rounds, uint32_t sweeps_per_round,
-                            uint32_t flags)
-{
-    if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
-    if (!h->xchg_active) return fail(MC_E_STATE, "replica exchange not initialised (mc_exchange_init)");
-    if (flags & ~MC_PERSISTENT) return fail(MC_E_ARG, "unknown flags 0x%x", flags);
-    if (sweeps_per_round < 1) return fail(MC_E_ARG, "sweeps_per_round must be >= 1");
-    if (h->t + (uint64_t)n_rounds * sweeps_per_round > 0xFFFFFFFFull)
-        return fail(MC_E_STATE, "sweep counter would exceed 2^32-1");
-    const XchgPtrs x = xchg_ptrs(h);
-    for (uint32_t k = 0; k < n_rounds; ++k) {
-        mc_status st;
-        if (flags & MC_PERSISTENT) {
-            // one launch per round: every sweep measured (the records are a
-            // by-product; the chain does not depend on them)
-            if ((st = mc_sweep(h, sweeps_per_round, MC_MEASURE | flags)) != MC_OK) return st;
-        } else {
-            if (sweeps_per_round > 1 && (st = mc_sweep(h, sweeps_per_round - 1, flags)) != MC_OK)
-                return st;
-            if ((st = mc_sweep(h, 1, MC_MEASURE | flags)) != MC_OK) return st;
-        }
-        ExchangeLaunch L;
-        L.reps_dev = h->reps_dev;
-        L.records = h->records + (size_t)h->last_slot * h->n_reps * NR;
-        L.beta = x.beta;
-        L.rep_at = x.rep_at;
-        L.round = x.round;
-        L.attempted = x.attempted;
-        L.accepted = x.accepted;
-        L.tctr_dev = h->tctr;
-        L.n = (uint32_t)h->n_reps;
-        L.seed_lo = (uint32_t)h->seed;
-        L.seed_hi = (uint32_t)(h->seed >> 32);
-        HIP_TRY(launch_exchange(L, h->stream));
-    }
-    return MC_OK;
-}
-
-mc_status mc_exchange_state(mc_sim *h, int32_t *replica_at_slot, double *T_slot,
-                            uint64_t *attempted, uint64_t *accepted, uint64_t *rounds)
-{
-    if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
-    if (!h->xchg_active) return fail(MC_E_STATE, "replica exchange not initialised (mc_exchange_init)");
-    HIP_TRY(hipStreamSynchronize(h->stream));
-    mc_status st = check_persistent(h);
-    if (st != MC_OK) return st;
-    const int n = h->n_reps;
-    const XchgPtrs x = xchg_ptrs(h);
-    std::vector<uint32_t> rep_at(n);
-    std::vector<uint64_t> att(n), acc(n);
-    uint32_t rnd = 0;
-    HIP_TRY(hipMemcpy(rep_at.data(), x.rep_at, sizeof(uint32_t) * n, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(att.data(), x.attempted, sizeof(uint64_t) * n, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(acc.data(), x.accepted, sizeof(uint64_t) * n, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(&rnd, x.round, sizeof rnd, hipMemcpyDeviceToHost));
-    for (int k = 0; k < n; ++k) {
-        if (replica_at_slot) replica_at_slot[k] = (int32_t)rep_at[k];
-        if (T_slot) T_slot[k] = h->xchg_T[k];
-        if (k + 1 < n) {
-            if (attempted) attempted[k] = att[k];
-            if (accepted) accepted[k] = acc[k];
-        }
-    }
-    if (rounds) *rounds = rnd;
-    return xchg_pull(h);
-}
-
-mc_status mc_block_workspace(const mc_sim *h, uint32_t n, uint64_t *bytes)
-{
-    if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
-    if (!bytes) return fail(MC_E_ARG, "bytes is NULL");
-    if (n < 1) return fail(MC_E_ARG, "n (sites per block) must be >= 1");
-    uint64_t nb = 0;
-    for (const RepDev &R : h->reps) nb = std::max<uint64_t>(nb, (R.n_box + n - 1) / n);
-    const uint64_t esz = h->prec == MC_F64 ? 8 : 4;
-    *bytes = 256 + align_up(4 * nb, 256) + 3 * esz * nb;
-    return MC_OK;
-}
-
-mc_status mc_block_steps(mc_sim *h, uint32_t n, uint32_t step0, uint32_t n_steps, uint32_t flags,
-                         void *work, uint64_t work_bytes)
-{
-    if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
-    if (h->kind != MC_SC) return fail(MC_E_UNSUPPORTED, "the block scheme is built for sc lattices");
-    if (flags & ~(MC_BLOCK_CONFLICTS | MC_BLOCK_RESET))
-        return fail(MC_E_ARG, "unknown flags 0x%x", flags);
-    uint64_t need = 0;
-    mc_status st = mc_block_workspace(h, n, &need);
-    if (st != MC_OK) return st;
-    if (!work || reinterpret_cast<uintptr_t>(work) % 256)
-        return fail(MC_E_BUFFER, "block workspace is NULL or not 256-byte aligned");
-    if (work_bytes < need)
-        return fail(MC_E_BUFFER, "block workspace has %llu bytes, %llu needed",
-                    (unsigned long long)work_bytes, (unsigned long long)need);
-    if ((uint64_t)step0 + n_steps > 0xFFFFFFFFull) return fail(MC_E_ARG, "step counter would exceed 2^32-1");
-    uint64_t nb_max = 0;
-    for (const RepDev &R : h->reps) nb_max = std::max<uint64_t>(nb_max, (R.n_box + n - 1) / n);
-    char *w = (char *)work;
-    BlockLaunch B;
-    B.n = n;
-    B.seed_lo = (uint32_t)h->seed;
-    B.seed_hi = (uint32_t)(h->seed >> 32);
-    B.count_conflicts = (flags & MC_BLOCK_CONFLICTS) ? 1 : 0;
-    B.counts = (unsigned long long *)w;
-    B.stage_idx = (uint32_t *)(w + 256);
-    B.stage_spin = w + 256 + align_up(4 * nb_max, 256);
-    if ((st = xchg_pull(h)) != MC_OK) return st; // current temperatures into h->reps
-    if (flags & MC_BLOCK_RESET) HIP_TRY(launch_zero_u32((uint32_t *)w, 6, h->stream));
-    for (uint32_t j = 0; j < n_steps; ++j)
-        for (int r = 0; r < h->n_reps; ++r) {
-            B.rep = h->reps[r];
-            B.n_blocks = (uint32_t)((h->reps[r].n_box + n - 1) / n);
-            B.step = step0 + j;
-            HIP_TRY(launch_block_step(h->prec == MC_F64, B, h->stream));
-        }
-    return MC_OK;
-}
-
-mc_status mc_block_counts(mc_sim *h, void *work, uint64_t counts[3])
-{
-    if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
-    if (!work || !counts) return fail(MC_E_ARG, "work or counts is NULL");
-    HIP_TRY(hipStreamSynchronize(h->stream));
-    HIP_TRY(hipMemcpy(counts, work, 3 * sizeof(uint64_t), hipMemcpyDeviceToHost));
-    HIP_TRY(launch_zero_u32((uint32_t *)work, 6, h->stream));
-    HIP_TRY(hipStreamSynchronize(h->stream));
-    return MC_OK;
-}
-
 mc_status mc_set_persistent_mode(mc_sim *h, mc_persist_mode mode)
 {
     if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
@@ -1595,181 +1261,6 @@ mc_status mc_set_tile(mc_sim *h, int32_t kernel, int32_t tx, int32_t ty, int32_t
     return upload_reps(h);
 }
 
-} // extern "C"
-
-namespace {
-
-// Candidate shapes for the autotuner: each kernel family with a few tile
-// widths, rows per thread and plane chunks aimed at 2k .. 16k workgroups.
-std::vector<Tile> tile_candidates(const mc_sim *h)
-{
-    int W = 1, Ly = 1;
-    for (const auto &d : h->desc) {
-        W = std::max(W, row_len(d));
-        Ly = std::max(Ly, d.Ly);
-    }
-    std::vector<Tile> base;
-    if (h->kind == MC_SC) {
-        const int whole = std::min(256, (W + 63) / 64 * 64);
-        for (int ry : {1, 2, 4}) {
-            base.push_back(Tile{KERNEL_STRIP, whole, ry, 1});
-            if (whole > 64) base.push_back(Tile{KERNEL_STRIP, 64, ry, 1});
-        }
-        for (int ry : {2, 4}) base.push_back(Tile{KERNEL_BAND, 256, ry, 1});
-        bool even = true;
-        for (const auto &d : h->desc) even &= row_len(d) % 2 == 0;
-        if (even) {
-            const int pairs = std::min(256, ((W + 1) / 2 + 63) / 64 * 64);
-            for (int ry : {1, 2, 4}) base.push_back(Tile{KERNEL_PAIR, pairs, ry, 1});
-            for (int ry : {2, 4}) base.push_back(Tile{KERNEL_PBAND, 256, ry, 1});
-            base.push_back(Tile{KERNEL_PBAND, 128, 2, 1});
-        }
-    }
-    for (int tx : {64, 32, 16, 8}) {
-        if (tx > 2 * pow2_at_least(W) && tx > 8) continue;
-        const int ty = std::min(256 / tx, pow2_at_least(Ly));
-        base.push_back(Tile{KERNEL_TILE, tx, ty, 1});
-    }
-    if (h->kind != MC_SC) {
-        for (int tx : {64, 128, 256}) {
-            if (tx > 64 && tx / 2 >= W) continue;
-            base.push_back(Tile{KERNEL_BSTRIP, tx, 256 / tx, 1});
-            if (tx <= 128) base.push_back(Tile{KERNEL_BSTRIP, tx, 1, 1});
-        }
-        bool even = true;
-        for (const auto &d : h->desc) even &= d.Lx % 2 == 0;
-        if (even)
-            for (int ry : {1, 2}) {
-                base.push_back(Tile{KERNEL_BPAIR, 256, ry, 1});
-                base.push_back(Tile{KERNEL_BPAIR, 128, ry, 1});
-            }
-    }
-    std::vector<Tile> out;
-    if (lds_fits(h))
-        for (int threads : {256, 512, 1024}) out.push_back(Tile{KERNEL_LDS, threads, 1, 1});
-    for (Tile t : base) {
-        uint64_t cols = 0;
-        int planes = 1;
-        for (const auto &d : h->desc) {
-            cols += xy_tiles(d, t) * d.Lz;
-            planes = std::max(planes, d.Lz);
-        }
-        int last = -1;
-        for (uint64_t target : {2048ull, 4096ull, 8192ull, 16384ull}) {
-            const int zc = (int)std::max<uint64_t>(1, std::min<uint64_t>((cols + target - 1) / target, planes));
-            if (zc == last) continue;
-            last = zc;
-            t.zc = zc;
-            out.push_back(t);
-        }
-    }
-    return out;
-}
-
-std::string tune_key(const mc_sim *h, uint32_t flags)
-{
-    uint64_t hash = 1469598103934665603ull; // FNV-1a over the lattice shapes
-    for (const auto &d : h->desc) {
-        const int32_t v[5] = {d.kind, d.Lx, d.Ly, d.Lz, (int32_t)d.periodic_mask};
-        for (int i = 0; i < 5; ++i)
-            for (int b = 0; b < 4; ++b) {
-                hash ^= (uint64_t)((v[i] >> (8 * b)) & 0xff);
-                hash *= 1099511628211ull;
-            }
-        const uint64_t r = (uint64_t)std::llround(d.sphere_radius * 1024.0);
-        for (int b = 0; b < 8; ++b) {
-            hash ^= (r >> (8 * b)) & 0xff;
-            hash *= 1099511628211ull;
-        }
-    }
-    std::ostringstream k;
-    k << "gfx950/kind" << h->kind << "/prec" << (int)h->prec << "/flags" << flags << "/reps"
-      << h->n_reps;
-    if (flags & MC_PERSISTENT) k << "/queues" << h->persist_mode;
-    k << "/" << std::hex << hash;
-    return k.str();
-}
-
-} // namespace
-
-extern "C" {
-
-mc_status mc_autotune(mc_sim *h, uint32_t trial_sweeps, uint32_t flags, const char *cache_path,
-                      int32_t *kernel, int32_t *tx, int32_t *ty, int32_t *zc)
-{
-    if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
-    if (flags & ~(MC_MEASURE | MC_PERSISTENT)) return fail(MC_E_ARG, "unknown flags 0x%x", flags);
-    if (trial_sweeps < 1) return fail(MC_E_ARG, "trial_sweeps must be >= 1");
-    const std::string key = tune_key(h, flags);
-    Tile best = h->tile;
-    bool found = false;
-    if (cache_path) {
-        std::ifstream in(cache_path);
-        std::string line;
-        while (std::getline(in, line)) {
-            std::istringstream ls(line);
-            std::string k;
-            Tile t;
-            double ms;
-            if (ls >> k >> t.kernel >> t.tx >> t.ty >> t.zc >> ms && k == key) {
-                best = t;
-                found = true;
-            }
-        }
-    }
-    if (found) {
-        mc_status st = mc_set_tile(h, best.kernel, best.tx, best.ty, best.zc);
-        if (st != MC_OK) found = false; // stale entry: tune again
-    }
-    if (!found) {
-        hipEvent_t e0, e1;
-        HIP_TRY(hipEventCreate(&e0));
-        HIP_TRY(hipEventCreate(&e1));
-        double best_ms = 1e300;
-        for (const Tile &t : tile_candidates(h)) {
-            if ((flags & MC_PERSISTENT) && !persistent_supported(t)) continue;
-            if (mc_set_tile(h, t.kernel, t.tx, t.ty, t.zc) != MC_OK) continue; // e.g. too big
-            mc_status st = mc_sweep(h, 1, flags);
-            if (st == MC_OK) st = mc_synchronize(h);
-            if (st != MC_OK) {
-                (void)hipEventDestroy(e0);
-                (void)hipEventDestroy(e1);
-                return st;
-            }
-            (void)hipEventRecord(e0, h->stream);
-            st = mc_sweep(h, trial_sweeps, flags);
-            (void)hipEventRecord(e1, h->stream);
-            if (st == MC_OK) st = mc_synchronize(h);
-            if (st != MC_OK) {
-                (void)hipEventDestroy(e0);
-                (void)hipEventDestroy(e1);
-                return st;
-            }
-            float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            if (ms < best_ms) {
-                best_ms = ms;
-                best = t;
-            }
-        }
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        mc_status st = mc_set_tile(h, best.kernel, best.tx, best.ty, best.zc);
-        if (st != MC_OK) return st;
-        if (cache_path) {
-            std::ofstream out(cache_path, std::ios::app);
-            if (out)
-                out << key << " " << best.kernel << " " << best.tx << " " << best.ty << " "
-                    << best.zc << " " << best_ms / trial_sweeps << "\n";
-        }
-    }
-    if (kernel) *kernel = h->tile.kernel;
-    if (tx) *tx = h->tile.tx;
-    if (ty) *ty = h->tile.ty;
-    if (zc) *zc = h->tile.zc;
-    return MC_OK;
-}
-
 mc_status mc_get_tile(const mc_sim *h, int32_t *kernel, int32_t *tx, int32_t *ty, int32_t *zc,
                       uint64_t *n_items)
 {
@@ -1805,51 +1296,6 @@ mc_status mc_num_colours(const mc_sim *h, int32_t *n)
     if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
     if (!n) return fail(MC_E_ARG, "NULL argument");
     *n = h->n_colours;
-    return MC_OK;
-}
-
-mc_status mc_series_stats(const mc_obs *series, uint64_t n, uint64_t stride, double T,
-                          mc_stats *out)
-{
-    if (!series || !out) return fail(MC_E_ARG, "NULL argument");
-    if (n < 2 || stride < 1) return fail(MC_E_ARG, "need n >= 2 records and stride >= 1");
-    std::vector<double> am(n), m2(n), m4(n), e(n), E(n);
-    double acc = 0.0;
-    const double N = (double)series[0].n_sites;
-    for (uint64_t i = 0; i < n; ++i) {
-        const mc_obs &o = series[i * stride];
-        const double q = o.M[0] * o.M[0] + o.M[1] * o.M[1] + o.M[2] * o.M[2];
-        am[i] = std::sqrt(q);
-        m2[i] = q;
-        m4[i] = q * q;
-        E[i] = o.E;
-        e[i] = o.E / N;
-        acc += (double)o.n_accepted / N;
-    }
-    std::memset(out, 0, sizeof *out);
-    out->n = n;
-    out->abs_m = mean_of(am);
-    out->abs_m_err = blocked_error(am);
-    out->m2 = mean_of(m2);
-    out->m2_err = blocked_error(m2);
-    out->m4 = mean_of(m4);
-    out->m4_err = blocked_error(m4);
-    out->e = mean_of(e);
-    out->e_err = blocked_error(e);
-    out->U4 = 1.0 - out->m4 / (3.0 * out->m2 * out->m2);
-    out->U4_err = binder_jackknife(m2, m4);
-    out->acceptance = acc / (double)n;
-    if (T > 0.0 && std::isfinite(T)) {
-        const double mE = mean_of(E);
-        double vE = 0.0;
-        for (double v : E) vE += (v - mE) * (v - mE);
-        vE /= (double)n;
-        out->C = vE / (N * T * T);
-        out->chi = N * (out->m2 - out->abs_m * out->abs_m) / T;
-    } else {
-        out->C = NAN;
-        out->chi = NAN;
-    }
     return MC_OK;
 }
 
