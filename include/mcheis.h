@@ -207,7 +207,8 @@ mc_status mc_measure_state(mc_sim *h, mc_obs *out, int32_t n_reps);
 mc_status mc_run_schedule(mc_sim *h, const mc_schedule *s, mc_obs *series, uint64_t capacity,
                           uint64_t *n_written);
 
-/* Change the temperatures (T[n_reps], same rules as the descriptor). */
+/* Change the temperatures (T[n_reps], same rules as the descriptor).  Ends a
+ * replica exchange started with mc_exchange_init.  Synchronises. */
 mc_status mc_set_temperatures(mc_sim *h, const double *T, int32_t n_reps);
 
 /* One colour pass of every replica at the current sweep counter, without
@@ -269,7 +270,8 @@ mc_status mc_set_sweep(mc_sim *h, uint64_t t);
  * The spins do not depend on the choice (only the FP64 summation order of the
  * observables does).  A shape whose work list does not fit the handle's
  * scratch gives MC_E_BUFFER.  Choosing kernel 0-2 discards the record of the
- * last measured sweep.  Synchronises. */
+ * last measured sweep.  Synchronises; a deferred error of an earlier
+ * persistent launch (watchdog, undrained queue) is returned first. */
 mc_status mc_set_tile(mc_sim *h, int32_t kernel, int32_t tx, int32_t ty, int32_t zc);
 mc_status mc_get_tile(const mc_sim *h, int32_t *kernel, int32_t *tx, int32_t *ty, int32_t *zc,
                       uint64_t *n_items);
