@@ -269,7 +269,7 @@ mc_status mc_set_sweep(mc_sim *h, uint64_t t);
  *    larger array or an odd Lx gives MC_E_UNSUPPORTED.
  * The spins do not depend on the choice (only the FP64 summation order of the
  * observables does).  A shape whose work list does not fit the handle's
- * scratch gives MC_E_BUFFER.  Choosing kernel 0-2 discards the record of the
+ * scratch gives MC_E_BUFFER.  Choosing any kernel but 3 discards the record of the
  * last measured sweep.  Synchronises; a deferred error of an earlier
  * persistent launch (watchdog, undrained queue) is returned first. */
 mc_status mc_set_tile(mc_sim *h, int32_t kernel, int32_t tx, int32_t ty, int32_t zc);
