@@ -388,6 +388,56 @@ def test_two_spin_langevin_and_histogram():
     assert np.all(np.abs(frac - pexp) < 6 * sd + 1e-4), (frac, pexp)
 
 
+def _block_spread(fn, cols, n_blocks=40):
+    """Standard error of a statistic of a series from the spread of its value
+    over contiguous blocks (blocks much longer than the correlation time)."""
+    idx = np.array_split(np.arange(len(cols[0])), n_blocks)
+    v = np.array([fn(*[c[i] for c in cols]) for i in idx])
+    return float(v.std(ddof=1) / np.sqrt(n_blocks))
+
+
+def test_two_spin_specific_heat_and_susceptibility():
+    """Fluctuation formulas of the series summary (specific heat
+    C = (<E^2> - <E>^2)/(N T^2), susceptibility chi = N (<m^2> - <|m|>^2)/T,
+    k_B = 1) on one bond (2x1x1 open sc, K = 0), where x = S1.S2 has density
+    proportional to exp(bJx) on [-1, 1]: E = -J x, m^2 = (1 + x)/2 and
+    |m| = sqrt((1 + x)/2), so every moment is a 1-D quadrature.  T = 0.5 and
+    N = 2 make a dropped N or T^2, or <m>^2 in place of <|m|>^2, miss by far
+    more than the error bar."""
+    lat = O.Lattice(O.SC, 2, 1, 1, periodic_mask=0)
+    J, T = 1.0, 0.5
+    N = lat.n_occ
+    assert N == 2 and lat.n_bonds == 1
+    p = O.Params(J=J, K=0.0, T=T, seed=59)
+    s = O.init(lat, p)
+    rec = O.run(lat, p, 0, 400000, s)
+    got = OS.series_summary(rec[:, 0:5], N, T)
+
+    b = J / T
+    def mom(f):
+        num = integrate.quad(lambda x: f(x) * np.exp(b * (x - 1.0)), -1, 1, epsabs=1e-13)[0]
+        den = integrate.quad(lambda x: np.exp(b * (x - 1.0)), -1, 1, epsabs=1e-13)[0]
+        return num / den
+    x1, x2 = mom(lambda x: x), mom(lambda x: x * x)
+    am = mom(lambda x: np.sqrt((1.0 + x) / 2.0))
+    C_want = J * J * (x2 - x1 * x1) / (N * T * T)
+    chi_want = N * ((1.0 + x1) / 2.0 - am * am) / T
+    assert x1 == pytest.approx(_langevin(b), abs=1e-12)  # the quadrature itself
+
+    E = rec[:, 3] + rec[:, 4]
+    m = rec[:, 0:3] / N
+    m2 = (m * m).sum(1)
+    C_err = _block_spread(lambda e: e.var() / (N * T * T), [E])
+    chi_err = _block_spread(lambda q: N * (q.mean() - np.sqrt(q).mean() ** 2) / T, [m2])
+    assert abs(got["C"] - C_want) < 5 * C_err, (got["C"], C_want, C_err)
+    assert abs(got["chi"] - chi_want) < 5 * chi_err, (got["chi"], chi_want, chi_err)
+    # the pin separates the plausible mistakes by many error bars
+    assert C_want * (N - 1) > 20 * C_err          # N dropped: C x N
+    assert C_want * (1 / T**2 - 1) > 20 * C_err  # T^2 dropped
+    mvec2 = float((m.mean(0) ** 2).sum())        # <m>^2 for <|m|>^2
+    assert N * (am * am - mvec2) / T > 20 * chi_err
+
+
 def _two_spin_energy_quadrature(beta, J, K):
     def w(dphi, z2, z1, moment):
         c = z1 * z2 + np.sqrt(max(0.0, 1 - z1 * z1)) * np.sqrt(max(0.0, 1 - z2 * z2)) * np.cos(dphi)
