@@ -24,7 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0           # MI355X HBM3E
-KERNEL_NAMES = ["tile", "strip", "band", "lds", "pair", "pband", "bstrip", "bpair"]  # mc_set_tile ids
+KERNEL_NAMES = ["tile", "strip", "band", "lds", "pair", "pband", "bstrip", "bpair", "lband"]  # mc_set_tile ids
 BYTES_PER_UPDATE = {"f32": 36, "f64": 72}  # two-pass colour-packed: read own + other, write own
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sc_pass_f32_L464_traffic.json")
 
@@ -135,25 +135,68 @@ def pattern_probe(M, n_box, grids=(1024, 2048, 8192, 32768), reps=10):
     return 36.0 * half / (best * 1e-3) / 1e9, best
 
 
+def host_cpu():
+    """Model name and logical CPU count of the host (and how many this
+    process may use)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count() or 0
+    return {"model": model, "logical_cpus": os.cpu_count() or 0, "usable_cpus": usable}
+
+
 def cpu_baseline(W, sweeps):
-    """The FP64 CPU oracle, untuned, on the same lattice: `sweeps` full sweeps
-    from the random start (lattice tables and initial state not timed)."""
+    """The FP64 CPU oracle, untuned, beside the GPU: `sweeps` full sweeps of
+    the same sc L=464 lattice from the random start on all the oracle's
+    threads (the reported value), one sweep of it on one thread, and the
+    1000-sweep sc L=16 trajectory on one and on all threads (lattice tables
+    and initial states not timed)."""
     from oracle import oracle as O
 
+    n_all = O.num_threads()
+
+    def timed_run(w, n_sweeps, threads):
+        lat = O.Lattice(O.SC, *w["L"], periodic_mask=w["periodic_mask"])
+        p = O.Params(J=w["J"], K=w["K"], e=w["e"], T=w["T"], seed=w["seed"])
+        s = O.init(lat, p)
+        O.set_num_threads(threads)
+        try:
+            t0 = time.perf_counter()
+            for t in range(n_sweeps):
+                O.sweep(lat, p, t, s)
+            dt = time.perf_counter() - t0
+        finally:
+            O.set_num_threads(n_all)
+        return lat.n_occ * n_sweeps / (dt * 1e9), dt
+
     w = W.C5_SC464_ROOFLINE
-    log(f"[bench] cpu oracle: building L={w['L'][0]} tables")
-    lat = O.Lattice(O.SC, *w["L"], periodic_mask=w["periodic_mask"])
-    p = O.Params(J=w["J"], K=w["K"], e=w["e"], T=w["T"], seed=w["seed"])
-    s = O.init(lat, p)
-    log(f"[bench] cpu oracle: timing {sweeps} sweeps on {O.num_threads()} threads")
-    t0 = time.perf_counter()
-    for t in range(sweeps):
-        O.sweep(lat, p, t, s)
-    dt = time.perf_counter() - t0
-    return {"value": lat.n_occ * sweeps / (dt * 1e9), "unit": "updates/ns",
-            "cores": O.num_threads(), "kind": "oracle",
+    log(f"[bench] cpu oracle: L={w['L'][0]}, {sweeps} sweeps on {n_all} threads")
+    rate, dt = timed_run(w, sweeps, n_all)
+    log("[bench] cpu oracle: L=464, 1 sweep on 1 thread")
+    rate1, dt1 = timed_run(w, 1, 1)
+    c1 = W.C1_SC16_TRAJECTORY
+    log("[bench] cpu oracle: sc L=16, 1000 sweeps on 1 and on all threads")
+    c1_rate1, c1_dt1 = timed_run(c1, c1["sweeps"], 1)
+    c1_rate, c1_dt = timed_run(c1, c1["sweeps"], n_all)
+    return {"value": rate, "unit": "updates/ns", "cores": n_all, "kind": "oracle",
             "sample": f"{sweeps} full sweeps of the sc L=464 lattice (FP64, OpenMP over one "
-                      f"colour), {dt:.1f} s; table build and initial state not timed"}
+                      f"colour), {dt:.1f} s; table build and initial state not timed",
+            "host": host_cpu(),
+            "single_thread": {"value": rate1, "unit": "updates/ns", "cores": 1,
+                              "sample": f"1 full sweep of the sc L=464 lattice, {dt1:.1f} s"},
+            "c1_trajectory": {"workload": c1["name"], "sweeps": c1["sweeps"],
+                              "s_1_thread": c1_dt1, "updates_per_ns_1_thread": c1_rate1,
+                              f"s_{n_all}_threads": c1_dt,
+                              f"updates_per_ns_{n_all}_threads": c1_rate}}
 
 
 def copy_probe(gib=2.0, reps=20, emit=True):

@@ -72,7 +72,9 @@ typedef enum { MC_INIT_RANDOM = 0, MC_INIT_ALIGNED = 1, MC_INIT_USER = 2 } mc_in
  *  sphere_radius <= 0: every site of the box is occupied.  > 0: a site at
  *                position r (cells) is occupied iff |r - (Lx,Ly,Lz)/2| <= R.
  *                Unoccupied sites hold S = 0, are never updated and have no
- *                bonds.
+ *                bonds.  A simple-cubic replica cut to a sphere runs on the
+ *                tile (0) and LDS (3) kernels only (mc_set_tile gives
+ *                MC_E_UNSUPPORTED for the others); bcc and fcc on every kernel.
  *  J, K          exchange and anisotropy (units of energy, k_B = 1).
  *  e             easy axis, normalised by the library (must be nonzero).
  *  T             temperature: 0 = greedy (accept iff dH <= 0), +inf = every
@@ -192,9 +194,34 @@ mc_status mc_sweep_timed(mc_sim *h, uint32_t n_sweeps, uint32_t flags, double *p
  * been measured since the handle was created. */
 mc_status mc_observables(mc_sim *h, mc_obs *out, int32_t n_reps);
 
-/* Observables of the current state recomputed from scratch (full energy over
- * all bonds, FP64), independent of the fused reduction.  Synchronises. */
+/* Observables of the current state recomputed from scratch: Eq. (2)'s
+ * magnetisation sum and both terms of Eq. (1), every nearest-neighbour bond
+ * counted once from a table of bond vectors, every product and sum in FP64.
+ * A separate kernel that shares no code with the pass kernels, so it checks
+ * their fused reduction independently.  n_accepted is 0; MC_E_DEVICE if the
+ * kernel visits a number of occupied sites other than the lattice's.  Uses
+ * the handle's scratch; synchronises. */
 mc_status mc_measure_state(mc_sim *h, mc_obs *out, int32_t n_reps);
+
+/* Bytes of device workspace a from-scratch measurement of caller buffers
+ * needs (mc_measure_buffers): FP64 partial sums of up to 1024 workgroups. */
+#define MC_MEASURE_WORKSPACE_BYTES 65536u
+
+/* Observables of one replica's spins, held in caller buffers in the library
+ * layout, computed from scratch as by mc_measure_state (Eq. (2)'s
+ * magnetisation sum and both terms of Eq. (1); every bond once; FP64
+ * products and sums) without a handle.  Enqueued on hip_stream (0: the null
+ * stream) and asynchronous: record_dev (device memory, 8 doubles) receives
+ * {M_x, M_y, M_z (sums), E_exch, E_anis, occupied sites, 0, 0} when the
+ * stream reaches it.  workspace: caller-owned device memory of at least
+ * MC_MEASURE_WORKSPACE_BYTES bytes, 256-byte aligned; it must not be used by
+ * another call until this one has run.  Nothing is allocated; no argument is
+ * kept after the call.  Errors: MC_E_ARG (descriptor, precision, NULL),
+ * MC_E_UNSUPPORTED (descriptor), MC_E_BUFFER (too small, misaligned or not
+ * device memory), MC_E_DEVICE (launch). */
+mc_status mc_measure_buffers(const mc_replica_desc *d, mc_precision prec,
+                             const mc_spin_buffers *bufs, void *workspace,
+                             uint64_t workspace_bytes, double *record_dev, void *hip_stream);
 
 /* Run a temperature schedule: at each temperature thermalise, then average
  * (the paper's Monte Carlo and simulation-setup paragraphs: equilibration
@@ -256,7 +283,7 @@ mc_status mc_set_sweep(mc_sim *h, uint64_t t);
  *    columns, ty rows per thread (1, 2 or 4; persistent sweeps: 1 or 2);
  *  kernel 5 (sc only, even packed rows): as kernel 2 with two adjacent
  *    columns per thread: tx (64 .. 256) (band, pair) positions per workgroup,
- *    bands of ty rows (2 or 4; persistent sweeps: 2);
+ *    bands of ty rows (2 or 4; FP64 and persistent sweeps: 2);
  *  kernel 6 (bcc and fcc): tx lanes along x (64, 128, 192 or 256) times ty
  *    rows (tx*ty <= 256), zc planes walked in z with the other basis sites'
  *    planes kept in registers and the x neighbour taken from the adjacent
@@ -266,7 +293,14 @@ mc_status mc_set_sweep(mc_sim *h, uint64_t t);
  *    thread (one 8-byte FP32 / 16-byte FP64 access per component), bands of
  *    ty rows (1 or 2), tx (64 .. 256) (band, pair) positions per workgroup,
  *    zc planes walked in z with the other bases' rows kept in registers.  A
- *    larger array or an odd Lx gives MC_E_UNSUPPORTED.
+ *    larger array or an odd Lx gives MC_E_UNSUPPORTED;
+ *  kernel 8 (sc only, rows a multiple of 16 bytes: Lx/2 a multiple of 4 in
+ *    FP32, of 2 in FP64): tiles of ty whole rows (at most two (row, pair)
+ *    positions per thread) walked over zc planes by tx = 256 threads; each
+ *    plane's rows (other colour y0-1 .. y0+ty, own colour y0 .. y0+ty-1) are
+ *    copied into LDS by asynchronous global-to-LDS loads one plane ahead of
+ *    the arithmetic (double buffered, at most 60 KiB per workgroup), and the
+ *    neighbour field is read from LDS.  No persistent sweeps.
  * The spins do not depend on the choice (only the FP64 summation order of the
  * observables does).  A shape whose work list does not fit the handle's
  * scratch gives MC_E_BUFFER.  Choosing any kernel but 3 discards the record of the
@@ -277,15 +311,26 @@ mc_status mc_get_tile(const mc_sim *h, int32_t *kernel, int32_t *tx, int32_t *ty
                       uint64_t *n_items);
 
 /* Autotuner (a property of this implementation, not of the method): time
- * candidate kernels and tile shapes on the handle's own lattices (trial_sweeps sweeps each, with `flags` as for mc_sweep) and keep
- * the fastest.  The trial sweeps are ordinary sweeps of the chain: they
- * advance the state and the sweep counter (results stay bitwise independent
- * of the shape).  cache_path (may be NULL) names a text file of earlier
- * choices keyed by device, lattices, precision and flags; a matching entry
- * skips the trials, a new choice is appended.  The chosen shape is returned
- * through the out pointers (each may be NULL).  Synchronises. */
+ * candidate kernels and tile shapes on the handle's own lattices
+ * (trial_sweeps sweeps each, with `flags` as for mc_sweep) and keep the
+ * fastest.  The trial sweeps are ordinary sweeps of the chain: they advance
+ * the state and the sweep counter (results stay bitwise independent of the
+ * shape).  cache_path (may be NULL) names a text file of earlier choices
+ * keyed by device (mc_tune_device_key of the handle's device), lattices,
+ * precision and flags; a matching entry skips the trials, a new choice is
+ * appended.  The chosen shape is returned through the out pointers (each may
+ * be NULL).  Synchronises. */
 mc_status mc_autotune(mc_sim *h, uint32_t trial_sweeps, uint32_t flags, const char *cache_path,
                       int32_t *kernel, int32_t *tx, int32_t *ty, int32_t *zc);
+
+/* The device part of the autotuner's cache key: architecture name (the
+ * device's gcnArchName), compute units and XCDs (both change with the
+ * partition mode), as "<arch>-cu<n_cu>-xcd<n_xcd>" with separators of the
+ * cache's text format replaced.  Writes a NUL-terminated string of at most
+ * `capacity` bytes to out; MC_E_ARG for NULL pointers, negative counts or a
+ * too small buffer.  Host only (no device access). */
+mc_status mc_tune_device_key(const char *arch, int32_t n_cu, int32_t n_xcd, char *out,
+                             uint64_t capacity);
 
 /* Number of colours (passes per sweep) of the handle's lattice kind. */
 mc_status mc_num_colours(const mc_sim *h, int32_t *n_colours);

@@ -9,8 +9,8 @@ consecutive entries; at every step each block picks one of its spins at random
 and makes one Metropolis attempt there (propose a new orientation uniformly on
 the sphere, accept if dH <= 0 or P <= exp(-dH/T)), the field coming from the
 neighbours' values in global memory, which other blocks update at the same
-time.  With few spins per block this concurrency breaks the Markov chain (the
-paper's "loss of continuity").  Which value of a concurrently updated
+time.  With few spins per block this concurrency breaks the Markov chain, as
+the implementation paragraph itself notes.  Which value of a concurrently updated
 neighbour an attempt sees depends on hardware timing; the form written here
 makes it definite and extreme: every attempt of a step sees the state from
 before the step, and all accepted moves are written together.

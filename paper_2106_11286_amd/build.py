@@ -16,7 +16,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmcheis.so")
 # device code: one translation unit per launch family (compiled in parallel)
 KERNEL_SOURCES = ["kernels_pass.hip", "kernels_basis_pair.hip", "kernels_persistent.hip",
-                  "kernels_lds.hip", "kernels_util.hip", "kernels_block.hip"]
+                  "kernels_lds.hip", "kernels_util.hip", "kernels_block.hip",
+                  "kernels_measure.hip"]
 # host runtime behind the C ABI
 HOST_SOURCES = ["abi.cpp", "abi_tune.cpp", "abi_stats.cpp", "abi_extensions.cpp"]
 SOURCES = KERNEL_SOURCES + HOST_SOURCES

@@ -124,6 +124,7 @@ uint64_t xy_tiles(const mc_replica_desc &d, const Tile &t)
         const uint64_t F = (uint64_t)((d.Ly + t.ty - 1) / t.ty) * cols;
         return (F + t.tx - 1) / t.tx;
     }
+    if (t.kernel == KERNEL_LBAND) return (uint64_t)((d.Ly + t.ty - 1) / t.ty);
     const int wx = t.kernel == KERNEL_PAIR ? 2 * t.tx : t.tx; // packed columns per tile
     return (uint64_t)((row_len(d) + wx - 1) / wx) * ((d.Ly + t.ty - 1) / t.ty);
 }
@@ -140,6 +141,18 @@ int z_chunk(const mc_replica_desc *reps, int n, const Tile &t)
     return (int)std::max<uint64_t>(1, std::min<uint64_t>(zc, planes));
 }
 
+// Whether the LDS-staged band kernel takes every replica (rows a multiple of
+// 16 bytes, a workgroup's rows within two positions per thread, its LDS and
+// copy slots within the limits) with tiles that fill one workgroup.
+bool lband_default(const mc_replica_desc *reps, int n, size_t esz, int W)
+{
+    for (int r = 0; r < n; ++r)
+        if ((uint64_t)row_len(reps[r]) * esz % 16u) return false;
+    const int ty = std::max(1, std::min(64, 256 / std::max(1, W / 2)));
+    return (ty * (W / 2) + 255) / 256 <= 2 && lband_lds_bytes(ty, W, (int)esz) <= 61440u &&
+           lband_slots_needed(ty + 2, W, (int)esz, 4) <= LBAND_SLOTS;
+}
+
 // Default pass kernel and tile for replicas whose spins have `esz`-byte
 // elements.
 Tile default_tile(const mc_replica_desc *reps, int n, size_t esz)
@@ -151,7 +164,9 @@ Tile default_tile(const mc_replica_desc *reps, int n, size_t esz)
         Ly = std::max(Ly, reps[r].Ly);
     }
     Tile t;
-    bool fits = true; // the strip kernel addresses each component array with 32-bit offsets
+    bool sphere = false; // only the tile kernel masks unoccupied simple-cubic sites
+    for (int r = 0; r < n; ++r) sphere |= reps[r].kind == MC_SC && reps[r].sphere_radius > 0.0;
+    bool fits = !sphere; // the strip kernel addresses each component array with 32-bit offsets
     for (int r = 0; r < n; ++r) fits &= box_sites(reps[r]) * esz <= 0xFFFFFFFFull;
     bool even = true; // every row holds an even number of packed columns (sc) or cells
     for (int r = 0; r < n; ++r) even &= row_len(reps[r]) % 2 == 0;
@@ -166,6 +181,12 @@ Tile default_tile(const mc_replica_desc *reps, int n, size_t esz)
         t.kernel = KERNEL_BAND;
         t.tx = 256;
         t.ty = 2;
+    } else if (reps[0].kind == MC_SC && !sphere && lband_default(reps, n, esz, W)) {
+        // arrays beyond the 32-bit offsets of the buffer kernels: whole rows
+        // staged through LDS, 64-bit addresses
+        t.kernel = KERNEL_LBAND;
+        t.tx = 256;
+        t.ty = std::max(1, std::min(64, 256 / std::max(1, W / 2)));
     } else if (reps[0].kind != MC_SC && fits && even) {
         // bcc / fcc: bands of cell pairs (fcc keeps one row per band: three
         // other bases' rows in registers)
@@ -181,7 +202,7 @@ Tile default_tile(const mc_replica_desc *reps, int n, size_t esz)
     return t;
 }
 
-mc_status check_tile(const Tile &t, int kind, uint64_t max_component_bytes)
+mc_status check_tile(const Tile &t, int kind, uint64_t max_component_bytes, bool f64)
 {
     if (t.kernel == KERNEL_BAND) {
         if (kind != MC_SC) return fail(MC_E_ARG, "the band kernel is for simple cubic lattices");
@@ -199,6 +220,9 @@ mc_status check_tile(const Tile &t, int kind, uint64_t max_component_bytes)
             return fail(MC_E_ARG, "band-pair tile: tx must be 64, 128, 192 or 256 (got %d)", t.tx);
         if (t.ty != 2 && t.ty != 4)
             return fail(MC_E_ARG, "band-pair tile: ty (rows per band) must be 2 or 4");
+        if (f64 && t.ty == 4)
+            return fail(MC_E_UNSUPPORTED, "band-pair tile: FP64 takes bands of 2 rows (4-row bands "
+                                          "need more than the 256 registers of a lane)");
     } else if (t.kernel == KERNEL_PAIR) {
         if (kind != MC_SC) return fail(MC_E_ARG, "the pair kernel is for simple cubic lattices");
         if (max_component_bytes > 0xFFFFFFFFull)
@@ -227,6 +251,12 @@ mc_status check_tile(const Tile &t, int kind, uint64_t max_component_bytes)
         if (kind == MC_SC) return fail(MC_E_ARG, "the basis strip kernel is for bcc and fcc lattices");
         if (t.tx < 64 || t.tx > 256 || t.tx % 64 || t.ty < 1 || t.tx * t.ty > 256)
             return fail(MC_E_ARG, "basis strip tile: tx must be 64, 128, 192 or 256 and tx*ty <= 256");
+    } else if (t.kernel == KERNEL_LBAND) {
+        if (kind != MC_SC) return fail(MC_E_ARG, "the LDS-staged band kernel is for simple cubic lattices");
+        if (t.tx != 256) return fail(MC_E_ARG, "LDS-staged band tile: tx must be 256 (got %d)", t.tx);
+        if (t.ty < 1 || t.ty > 64)
+            return fail(MC_E_ARG, "LDS-staged band tile: ty (rows per tile) must be in [1, 64]");
+        (void)max_component_bytes;
     } else if (t.kernel == KERNEL_TILE) {
         if (t.tx < 1 || t.ty < 1 || t.tx * t.ty > 256)
             return fail(MC_E_ARG, "tile %d x %d invalid (need >= 1 and tx*ty <= 256)", t.tx, t.ty);
@@ -278,6 +308,12 @@ void make_work(const mc_replica_desc *reps, int n, const Tile &t, std::vector<Wo
             end[r] = (uint32_t)work.size();
             continue;
         }
+        if (t.kernel == KERNEL_LBAND) { // whole rows: tiles of ty rows
+            for (int z0 = 0; z0 < d.Lz; z0 += t.zc)
+                for (int y0 = 0; y0 < d.Ly; y0 += t.ty) work.push_back(WorkItem{(uint32_t)r, 0, y0, z0});
+            end[r] = (uint32_t)work.size();
+            continue;
+        }
         const int wx = t.kernel == KERNEL_PAIR ? 2 * t.tx : t.tx; // packed columns per tile
         for (int z0 = 0; z0 < d.Lz; z0 += t.zc)
             for (int x0 = 0; x0 < W; x0 += wx)
@@ -326,6 +362,9 @@ ScratchLayout scratch_layout(int n_reps, uint64_t n_items, int n_colours)
     o = align_up(o + sizeof(uint32_t) * persist_state_words(n_reps), 256);
     L.off_queues = o;
     o = align_up(o + sizeof(uint32_t) * queue_words(n_items), 256);
+    // partials of the from-scratch measurement (mc_measure_state)
+    L.off_measure = o;
+    o = align_up(o + sizeof(double) * 8 * MEASURE_BLOCKS, 256);
     L.total = o;
     return L;
 }
@@ -382,6 +421,15 @@ PassLaunch pass_args(mc_sim *h, uint32_t item_base, uint32_t n_blocks, uint32_t 
     p.partials_dev = h->partials;
     p.dbg_dh = nullptr;
     p.dbg_acc = nullptr;
+    p.lds_bytes = 0;
+    p.lds_positions = 0;
+    if (p.tile.kernel == KERNEL_LBAND) {
+        int w = 1;
+        for (const auto &d : h->desc) w = std::max(w, row_len(d));
+        const int esz = h->prec == MC_F64 ? 8 : 4;
+        p.lds_bytes = lband_lds_bytes(p.tile.ty, w, esz);
+        p.lds_positions = (p.tile.ty * (w / 2) + p.tile.tx - 1) / p.tile.tx;
+    }
     return p;
 }
 
@@ -392,6 +440,14 @@ uint64_t lds_need(const mc_sim *h)
     uint64_t m = 0;
     for (const RepDev &R : h->reps) m = std::max<uint64_t>(m, 3ull * R.n_box * esz);
     return m;
+}
+
+bool sc_sphere(const mc_sim *h)
+{
+    if (h->kind != MC_SC) return false;
+    for (const auto &d : h->desc)
+        if (d.sphere_radius > 0.0) return true;
+    return false;
 }
 
 bool lds_fits(const mc_sim *h) { return h->lds_max > 0 && lds_need(h) <= h->lds_max; }
@@ -525,6 +581,7 @@ mc_status plan_queues(mc_sim *h)
 // Tile shapes the persistent kernel is instantiated for.
 bool persistent_supported(const Tile &t)
 {
+    if (t.kernel == KERNEL_LBAND) return false;
     if (t.kernel == KERNEL_PAIR) return t.ty == 1 || t.ty == 2;
     if (t.kernel == KERNEL_PBAND) return t.ty == 2;
     if (t.kernel == KERNEL_BPAIR) return t.ty == 1 || t.ty == 2;
@@ -610,6 +667,59 @@ void set_temperature(RepDev &R, double T)
 {
     R.greedy = T == 0.0;
     R.beta = (T > 0.0 && std::isfinite(T)) ? 1.0 / T : 0.0;
+}
+
+void fill_repdev(const mc_replica_desc &d, const mc_spin_buffers &b, RepDev &R)
+{
+    std::memset(&R, 0, sizeof R);
+    R.sx = b.sx;
+    R.sy = b.sy;
+    R.sz = b.sz;
+    R.Lx = d.Lx;
+    R.Ly = d.Ly;
+    R.Lz = d.Lz;
+    R.Lxh = row_len(d);
+    R.pmask = d.periodic_mask;
+    R.rid = d.replica_id;
+    R.n_box = (uint32_t)box_sites(d);
+    R.plane = d.kind == MC_SC ? R.n_box / 2 : (uint32_t)d.Lx * d.Ly * d.Lz;
+    R.J = d.J;
+    R.K = d.K;
+    const double en = std::sqrt(d.e[0] * d.e[0] + d.e[1] * d.e[1] + d.e[2] * d.e[2]);
+    for (int a = 0; a < 3; ++a) R.e[a] = d.e[a] / en;
+    set_temperature(R, d.T);
+    R.sphere = d.sphere_radius > 0.0;
+    R.r2x4 = 4.0 * d.sphere_radius * d.sphere_radius;
+}
+
+static_assert(sizeof(double) * 8 * MEASURE_BLOCKS <= MC_MEASURE_WORKSPACE_BYTES,
+              "measurement partials exceed the documented workspace");
+
+uint32_t measure_blocks(const RepDev &R)
+{
+    const uint64_t want = (R.n_box + 2047ull) / 2048ull;
+    return (uint32_t)std::min<uint64_t>(MEASURE_BLOCKS, std::max<uint64_t>(1, want));
+}
+
+mc_status check_measure_args(const mc_replica_desc *d, mc_precision prec,
+                             const mc_spin_buffers *bufs, const double *record_dev)
+{
+    if (!d || !bufs || !record_dev) return fail(MC_E_ARG, "NULL argument");
+    if (prec != MC_F32 && prec != MC_F64) return fail(MC_E_ARG, "unknown precision %d", (int)prec);
+    mc_status s = check_desc(*d, 0);
+    if (s != MC_OK) return s;
+    const uint64_t need = box_sites(*d);
+    if (bufs->capacity_sites < need)
+        return fail(MC_E_BUFFER, "capacity %llu < %llu sites",
+                    (unsigned long long)bufs->capacity_sites, (unsigned long long)need);
+    const size_t esz = prec == MC_F64 ? sizeof(double) : sizeof(float);
+    const void *pl[3] = {bufs->sx, bufs->sy, bufs->sz};
+    const char *nm[3] = {"sx", "sy", "sz"};
+    for (int a = 0; a < 3; ++a)
+        if ((s = check_device_buffer(pl[a], need * esz, nm[a], 0)) != MC_OK) return s;
+    if (reinterpret_cast<uintptr_t>(record_dev) % 8)
+        return fail(MC_E_BUFFER, "record is not 8-byte aligned");
+    return check_device_buffer(record_dev, sizeof(double) * NR, "record", 0);
 }
 
 mc_status upload_reps(mc_sim *h)
@@ -825,25 +935,7 @@ mc_status mc_init_lattice(const mc_replica_desc *reps, int32_t n_reps, mc_precis
     for (int r = 0; r < n_reps; ++r) {
         const mc_replica_desc &d = reps[r];
         RepDev &R = h->reps[r];
-        std::memset(&R, 0, sizeof R);
-        R.sx = bufs[r].sx;
-        R.sy = bufs[r].sy;
-        R.sz = bufs[r].sz;
-        R.Lx = d.Lx;
-        R.Ly = d.Ly;
-        R.Lz = d.Lz;
-        R.Lxh = row_len(d);
-        R.pmask = d.periodic_mask;
-        R.rid = d.replica_id;
-        R.n_box = (uint32_t)box_sites(d);
-        R.plane = d.kind == MC_SC ? R.n_box / 2 : (uint32_t)d.Lx * d.Ly * d.Lz;
-        R.J = d.J;
-        R.K = d.K;
-        const double en = std::sqrt(d.e[0] * d.e[0] + d.e[1] * d.e[1] + d.e[2] * d.e[2]);
-        for (int a = 0; a < 3; ++a) R.e[a] = d.e[a] / en;
-        set_temperature(R, d.T);
-        R.sphere = d.sphere_radius > 0.0;
-        R.r2x4 = 4.0 * d.sphere_radius * d.sphere_radius;
+        fill_repdev(d, bufs[r], R);
         R.item_begin = b[r];
         R.item_end = e[r];
         h->n_occ[r] = count_occupied(d);
@@ -875,6 +967,23 @@ mc_status mc_init_lattice(const mc_replica_desc *reps, int32_t n_reps, mc_precis
     }
     if (hipStreamSynchronize(h->stream) != hipSuccess)
         return cleanup(fail(MC_E_DEVICE, "init: %s", hipGetErrorString(hipGetLastError())));
+    // the device as the autotuner's cache sees it (architecture, compute
+    // units, XCDs: a partition mode changes the last two)
+    {
+        int dev = 0, n_xcd = 0;
+        hipDeviceProp_t prop;
+        std::memset(&prop, 0, sizeof prop);
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+            if (hipDeviceGetAttribute(&n_xcd, hipDeviceAttributeNumberOfXccs, dev) != hipSuccess)
+                n_xcd = 0;
+            char key[160];
+            if (mc_tune_device_key(prop.gcnArchName, prop.multiProcessorCount, n_xcd, key,
+                                   sizeof key) == MC_OK)
+                h->device_key = key;
+        }
+        (void)hipGetLastError();
+        if (h->device_key.empty()) h->device_key = "unknown-device";
+    }
     // lattices whose state fits one workgroup's LDS run whole sweeps there
     {
         int dev = 0, lds = 0;
@@ -1023,20 +1132,50 @@ mc_status mc_measure_state(mc_sim *h, mc_obs *out, int32_t n_reps)
     mc_status ps = check_persistent(h);
     if (ps != MC_OK) return ps;
     const bool f64 = h->prec == MC_F64;
-    const uint32_t n_items = (uint32_t)h->work.size();
-    const PassLaunch p = pass_args(h, 0, n_items, 0);
-    for (int c = 0; c < h->n_colours; ++c) HIP_TRY(launch_pass(h->kind, f64, c, true, 1, p, h->stream));
+    double *partials = (double *)(h->scratch + h->lay.off_measure);
     double *dst = h->records + (size_t)kRing * h->n_reps * NR;
-    HIP_TRY(launch_finalize(h->reps_dev, h->n_reps, h->n_colours, h->partials, n_items, h->tctr,
-                            0, dst, h->stage, h->stream));
+    for (int r = 0; r < h->n_reps; ++r) {
+        HIP_TRY(launch_measure_direct(f64, h->kind, &h->reps[r], partials,
+                                      measure_blocks(h->reps[r]), (double)h->t,
+                                      dst + (size_t)r * NR, h->stream));
+    }
     HIP_TRY(hipMemcpyAsync(h->host_rec, dst, sizeof(double) * NR * h->n_reps,
                            hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
     for (int r = 0; r < h->n_reps; ++r) {
+        const double counted = h->host_rec[(size_t)r * NR + R_NACC];
+        if (counted != (double)h->n_occ[r])
+            return fail(MC_E_DEVICE, "replica %d: the measurement visited %.0f occupied sites, "
+                                     "the lattice has %llu", r, counted,
+                        (unsigned long long)h->n_occ[r]);
         record_to_obs(h, h->host_rec + (size_t)r * NR, r, &out[r]);
         out[r].sweep = h->t;
         out[r].n_accepted = 0;
     }
+    return MC_OK;
+}
+
+mc_status mc_measure_buffers(const mc_replica_desc *d, mc_precision prec,
+                             const mc_spin_buffers *bufs, void *workspace,
+                             uint64_t workspace_bytes, double *record_dev, void *hip_stream)
+{
+    mc_status s = check_measure_args(d, prec, bufs, record_dev);
+    if (s != MC_OK) return s;
+    if (!workspace) return fail(MC_E_BUFFER, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256)
+        return fail(MC_E_BUFFER, "workspace must be 256-byte aligned");
+    if (workspace_bytes < MC_MEASURE_WORKSPACE_BYTES)
+        return fail(MC_E_BUFFER, "workspace has %llu bytes, %llu needed",
+                    (unsigned long long)workspace_bytes,
+                    (unsigned long long)MC_MEASURE_WORKSPACE_BYTES);
+    if ((s = check_device_buffer(workspace, MC_MEASURE_WORKSPACE_BYTES, "workspace", 0)) != MC_OK)
+        return s;
+    RepDev R;
+    fill_repdev(*d, *bufs, R);
+    const hipError_t e = launch_measure_direct(prec == MC_F64, d->kind, &R, (double *)workspace,
+                                               measure_blocks(R), 0.0, record_dev,
+                                               (hipStream_t)hip_stream);
+    if (e != hipSuccess) return fail(MC_E_DEVICE, "measure launch: %s", hipGetErrorString(e));
     return MC_OK;
 }
 
@@ -1218,8 +1357,32 @@ mc_status mc_set_tile(mc_sim *h, int32_t kernel, int32_t tx, int32_t ty, int32_t
     for (const RepDev &R : h->reps)
         max_bytes = std::max<uint64_t>(max_bytes, (uint64_t)R.n_box *
                                                       (h->prec == MC_F64 ? 8u : 4u));
-    mc_status st = check_tile(t, h->kind, max_bytes);
+    mc_status st = check_tile(t, h->kind, max_bytes, h->prec == MC_F64);
     if (st != MC_OK) return st;
+    if (kernel == KERNEL_LBAND) {
+        const uint32_t esz = h->prec == MC_F64 ? 8u : 4u;
+        int w = 1;
+        for (int r = 0; r < h->n_reps; ++r) {
+            const int lxh = row_len(h->desc[r]);
+            if ((uint32_t)lxh * esz % 16u)
+                return fail(MC_E_UNSUPPORTED, "LDS-staged band kernel: replica %d has rows of %u "
+                                              "bytes, not a multiple of 16", r, (uint32_t)lxh * esz);
+            w = std::max(w, lxh);
+        }
+        if ((ty * (w / 2) + tx - 1) / tx > 2)
+            return fail(MC_E_UNSUPPORTED, "LDS-staged band kernel: %d rows of %d pairs exceed two "
+                                          "positions per thread", ty, w / 2);
+        const uint64_t lds = lband_lds_bytes(ty, w, (int)esz);
+        if (lds > 61440) // 60 KiB of dynamic LDS, the rest of 64 KiB for the reductions
+            return fail(MC_E_UNSUPPORTED, "LDS-staged band kernel: %d rows of %d columns need %llu "
+                                          "bytes of LDS (limit 61440)", ty, w, (unsigned long long)lds);
+        if (lband_slots_needed(ty + 2, w, (int)esz, tx / 64) > LBAND_SLOTS)
+            return fail(MC_E_UNSUPPORTED, "LDS-staged band kernel: %d rows of %d columns need more "
+                                          "than %d copies per lane", ty + 2, w, LBAND_SLOTS);
+    }
+    if (kernel != KERNEL_TILE && sc_sphere(h))
+        return fail(MC_E_UNSUPPORTED, "a simple-cubic lattice cut to a sphere runs on the tile "
+                                      "kernel (0) or the LDS kernel (3) only");
     if (kernel == KERNEL_PAIR || kernel == KERNEL_PBAND || kernel == KERNEL_BPAIR)
         for (int r = 0; r < h->n_reps; ++r)
             if (row_len(h->desc[r]) % 2)

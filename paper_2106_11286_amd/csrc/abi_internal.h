@@ -42,7 +42,7 @@ constexpr uint32_t kGraphChunk = 64;  // sweeps per captured graph
 
 struct ScratchLayout {
     uint64_t off_ctr, off_reps, off_work, off_partials, off_records, off_stage,
-        off_persist, off_queues, off_exchange, total;
+        off_persist, off_queues, off_exchange, off_measure, total;
 };
 
 // Words of the persistent-queue region: 16 queue offsets, then every item
@@ -69,6 +69,7 @@ struct mc_sim {
     Tile tile{};      // kernel of whole sweeps
     Tile pass_tile{}; // kernel of single passes (= tile unless tile is the LDS kernel)
     uint32_t lds_max = 0; // dynamic LDS a workgroup may use on this device (bytes)
+    std::string device_key; // the device as the autotuner's cache sees it
     hipStream_t stream = nullptr;
     char *scratch = nullptr;
     uint64_t scratch_bytes = 0;
@@ -102,7 +103,15 @@ struct mc_sim {
 namespace mcabi {
 
 bool alive(const mc_sim *h);
+void fill_repdev(const mc_replica_desc &d, const mc_spin_buffers &b, RepDev &R);
+// Workgroups of a from-scratch measurement of one replica (<= MEASURE_BLOCKS).
+uint32_t measure_blocks(const RepDev &R);
+// Arguments of a from-scratch measurement of caller buffers.
+mc_status check_measure_args(const mc_replica_desc *d, mc_precision prec,
+                             const mc_spin_buffers *bufs, const double *record_dev);
 bool lds_fits(const mc_sim *h);
+// A simple-cubic handle with a replica cut to a sphere (tile and LDS kernels only).
+bool sc_sphere(const mc_sim *h);
 mc_status check_persistent(mc_sim *h);
 // While replica exchange is active the device descriptors hold each
 // replica's current temperature; copy it into the host descriptors.

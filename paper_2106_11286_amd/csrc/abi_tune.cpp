@@ -2,6 +2,7 @@
 // the handle's own lattices, with a text cache keyed by the lattice shapes.
 #include <algorithm>
 #include <cstdint>
+#include <cstring>
 #include <fstream>
 #include <sstream>
 #include <string>
@@ -23,7 +24,7 @@ std::vector<Tile> tile_candidates(const mc_sim *h)
         Ly = std::max(Ly, d.Ly);
     }
     std::vector<Tile> base;
-    if (h->kind == MC_SC) {
+    if (h->kind == MC_SC && !sc_sphere(h)) {
         const int whole = std::min(256, (W + 63) / 64 * 64);
         for (int ry : {1, 2, 4}) {
             base.push_back(Tile{KERNEL_STRIP, whole, ry, 1});
@@ -35,7 +36,13 @@ std::vector<Tile> tile_candidates(const mc_sim *h)
         if (even) {
             const int pairs = std::min(256, ((W + 1) / 2 + 63) / 64 * 64);
             for (int ry : {1, 2, 4}) base.push_back(Tile{KERNEL_PAIR, pairs, ry, 1});
-            for (int ry : {2, 4}) base.push_back(Tile{KERNEL_PBAND, 256, ry, 1});
+            base.push_back(Tile{KERNEL_PBAND, 256, 2, 1});
+            if (h->prec != MC_F64) base.push_back(Tile{KERNEL_PBAND, 256, 4, 1});
+            // LDS-staged rows: tiles of whole rows that fill a workgroup once or
+            // twice (mc_set_tile refuses the shapes that do not fit)
+            const int np = std::max(1, W / 2);
+            for (int rows : {256 / np, 512 / np})
+                if (rows >= 1) base.push_back(Tile{KERNEL_LBAND, 256, std::min(rows, 64), 1});
             base.push_back(Tile{KERNEL_PBAND, 128, 2, 1});
         }
     }
@@ -97,8 +104,8 @@ std::string tune_key(const mc_sim *h, uint32_t flags)
         }
     }
     std::ostringstream k;
-    k << "gfx950/kind" << h->kind << "/prec" << (int)h->prec << "/flags" << flags << "/reps"
-      << h->n_reps;
+    k << h->device_key << "/kind" << h->kind << "/prec" << (int)h->prec << "/flags" << flags
+      << "/reps" << h->n_reps;
     if (flags & MC_PERSISTENT) k << "/queues" << h->persist_mode;
     k << "/" << std::hex << hash;
     return k.str();
@@ -107,6 +114,24 @@ std::string tune_key(const mc_sim *h, uint32_t flags)
 } // namespace
 
 extern "C" {
+
+mc_status mc_tune_device_key(const char *arch, int32_t n_cu, int32_t n_xcd, char *out,
+                             uint64_t capacity)
+{
+    if (!arch || !out) return fail(MC_E_ARG, "arch and out must not be NULL");
+    if (n_cu < 0 || n_xcd < 0) return fail(MC_E_ARG, "negative unit count");
+    std::string a;
+    for (const char *c = arch; *c; ++c) // no separators of the cache's text format
+        a.push_back((*c == ' ' || *c == '/' || *c == '\t' || *c == '\n') ? '_' : *c);
+    std::ostringstream k;
+    k << (a.empty() ? "unknown" : a) << "-cu" << n_cu << "-xcd" << n_xcd;
+    const std::string s = k.str();
+    if (capacity < s.size() + 1)
+        return fail(MC_E_ARG, "key needs %llu bytes, capacity %llu",
+                    (unsigned long long)(s.size() + 1), (unsigned long long)capacity);
+    std::memcpy(out, s.c_str(), s.size() + 1);
+    return MC_OK;
+}
 
 mc_status mc_autotune(mc_sim *h, uint32_t trial_sweeps, uint32_t flags, const char *cache_path,
                       int32_t *kernel, int32_t *tx, int32_t *ty, int32_t *zc)

@@ -28,6 +28,7 @@ __device__ __forceinline__ void basis_body(const PassLaunch &P, uint32_t item, u
     const uint32_t plane = R.plane;
     const gptr<T> gx = as_global<T>(R.sx), gy = as_global<T>(R.sy), gz = as_global<T>(R.sz);
     const T J = (T)R.J, K = (T)R.K, ex = (T)R.e[0], ey = (T)R.e[1], ez = (T)R.e[2];
+    const double Jd = R.J;
     const T beta = (T)R.beta;
     const bool greedy = R.greedy != 0;
     const bool pxm = R.pmask & 1u, pym = R.pmask & 2u, pzm = R.pmask & 4u;
@@ -64,9 +65,10 @@ __device__ __forceinline__ void basis_body(const PassLaunch &P, uint32_t item, u
                 }
             }
             // bonds to lower colours, whose spins are final after their pass
-            if (MEASURE)
-                accumulate<T>(acc, sx, sy, sz, ex, ey, ez, J * (sx * lx_ + sy * ly_ + sz * lz_),
-                              a);
+            if (MEASURE) {
+                observe<T>(acc, sx, sy, sz, ex, ey, ez, true, lx_, ly_, lz_, Jd);
+                acc[Q_NACC] += a ? 1.0 : 0.0;
+            }
         }
     }
     if (MEASURE)
@@ -102,6 +104,7 @@ __device__ __forceinline__ void basis_strip_body(const PassLaunch &P, uint32_t i
     const uint32_t plane = R.plane;
     const gptr<T> gx = as_global<T>(R.sx), gy = as_global<T>(R.sy), gz = as_global<T>(R.sz);
     const T J = (T)R.J, K = (T)R.K, ex = (T)R.e[0], ey = (T)R.e[1], ez = (T)R.e[2];
+    const double Jd = R.J;
     const T beta = (T)R.beta;
     const bool greedy = R.greedy != 0;
     const bool pxm = R.pmask & 1u, pym = R.pmask & 2u, pzm = R.pmask & 4u;
@@ -236,8 +239,10 @@ __device__ __forceinline__ void basis_strip_body(const PassLaunch &P, uint32_t i
                 gz[i] = sz;
             }
         }
-        if (MEASURE)
-            accumulate<T>(acc, sx, sy, sz, ex, ey, ez, J * (sx * lx_ + sy * ly_ + sz * lz_), a);
+        if (MEASURE) {
+            observe<T>(acc, sx, sy, sz, ex, ey, ez, true, lx_, ly_, lz_, Jd);
+            acc[Q_NACC] += a ? 1.0 : 0.0;
+        }
     }
     if (MEASURE)
         block_store_partials(acc, P.partials_dev + ((size_t)B * P.n_items + item) * NQ);
@@ -272,6 +277,7 @@ __device__ __forceinline__ void basis_pair_body(const PassLaunch &P, uint32_t it
     void *const base_x = R.sx, *const base_y = R.sy, *const base_z = R.sz;
     const uint32_t n_box = R.n_box, plane = R.plane, rid = R.rid;
     const T J = (T)R.J, K = (T)R.K, ex = (T)R.e[0], ey = (T)R.e[1], ez = (T)R.e[2];
+    const double Jd = R.J;
     const T beta = (T)R.beta;
     const bool greedy = R.greedy != 0;
     const bool px = R.pmask & 1u, py = R.pmask & 2u, pz = R.pmask & 4u;
@@ -387,8 +393,10 @@ __device__ __forceinline__ void basis_pair_body(const PassLaunch &P, uint32_t it
                 P.dbg_acc[i] = a ? 1 : 0;
             }
         }
-        if (MEASURE && live)
-            accumulate<T>(acc, sx, sy, sz, ex, ey, ez, J * (sx * lx_ + sy * ly_ + sz * lz_), a);
+        if (MEASURE && live) {
+            observe<T>(acc, sx, sy, sz, ex, ey, ez, true, lx_, ly_, lz_, Jd);
+            acc[Q_NACC] += a ? 1.0 : 0.0;
+        }
         return a;
     };
 

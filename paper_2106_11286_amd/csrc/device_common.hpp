@@ -234,20 +234,23 @@ __device__ __forceinline__ bool metropolis(T &sx, T &sy, T &sz, T hx, T hy, T hz
     return metropolis_words<T>(w, sx, sy, sz, hx, hy, hz, K, ex, ey, ez, beta, greedy, dH);
 }
 
-// FP64 accumulation of the observables of one final spin.  sh is the spin
-// dotted with the field of its already-final neighbours (J applied); pass 0
-// of a bipartite lattice contributes none.
+// FP64 observables of one final spin: its components (Eq. (2)), (S.e)^2 and,
+// for a site that closes bonds, S dotted with the field h of its
+// already-final neighbours scaled by jscale (1 when h has J applied, J when
+// it has not).  The products are formed from FP64 operands, so every kernel
+// adds the same per-site values and records differ between kernels only by
+// the FP64 summation order.
 template <typename T>
-__device__ __forceinline__ void accumulate(double (&acc)[Q_N], T sx, T sy, T sz, T ex, T ey, T ez,
-                                           T sh, bool accepted)
+__device__ __forceinline__ void observe(double (&acc)[Q_N], T sx, T sy, T sz, T ex, T ey, T ez,
+                                        bool bonds, T hx, T hy, T hz, double jscale)
 {
-    acc[Q_MX] += (double)sx;
-    acc[Q_MY] += (double)sy;
-    acc[Q_MZ] += (double)sz;
-    const double pe = (double)sx * (double)ex + (double)sy * (double)ey + (double)sz * (double)ez;
+    const double dx = (double)sx, dy = (double)sy, dz = (double)sz;
+    acc[Q_MX] += dx;
+    acc[Q_MY] += dy;
+    acc[Q_MZ] += dz;
+    const double pe = dx * (double)ex + dy * (double)ey + dz * (double)ez;
     acc[Q_PE2] += pe * pe;
-    acc[Q_SH] += (double)sh;
-    acc[Q_NACC] += accepted ? 1.0 : 0.0;
+    if (bonds) acc[Q_SH] += jscale * (dx * (double)hx + dy * (double)hy + dz * (double)hz);
 }
 
 // Field of the six neighbours of a simple-cubic site (J not applied), summed
@@ -298,11 +301,18 @@ template <typename T> struct Vec3 {
 using rsrc_t = __amdgpu_buffer_rsrc_t;
 constexpr int kRsrcWord3 = 0x00020000; // raw dword access, gfx9-family descriptor
 
+// The descriptor is uniform by construction; its fields are passed through
+// readfirstlane so the compiler keeps it in scalar registers on every path
+// (a descriptor it believes divergent turns each access into a loop).
 template <typename T>
 __device__ __forceinline__ rsrc_t plane_rsrc(void *comp, uint32_t elem_off, uint32_t n_elems)
 {
-    return __builtin_amdgcn_make_buffer_rsrc((char *)comp + (size_t)elem_off * sizeof(T), (short)0,
-                                             (int)(n_elems * (uint32_t)sizeof(T)), kRsrcWord3);
+    const uint64_t a = (uint64_t)(uintptr_t)comp + (uint64_t)elem_off * sizeof(T);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    const uint32_t bytes = __builtin_amdgcn_readfirstlane(n_elems * (uint32_t)sizeof(T));
+    return __builtin_amdgcn_make_buffer_rsrc((void *)(uintptr_t)(((uint64_t)hi << 32) | lo),
+                                             (short)0, (int)bytes, kRsrcWord3);
 }
 __device__ __forceinline__ float buf_load(rsrc_t r, uint32_t voff, uint32_t soff, float)
 {

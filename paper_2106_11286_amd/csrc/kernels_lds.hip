@@ -56,7 +56,7 @@ __global__ void __launch_bounds__(1024) k_lds_sweeps(LdsLaunch L)
     const T beta = (T)R.beta;
     const bool greedy = R.greedy != 0;
     const bool px = R.pmask & 1u, py = R.pmask & 2u, pz = R.pmask & 4u;
-    const double Kd = R.K;
+    const double Kd = R.K, Jd = R.J;
     const uint32_t t0 = *L.tctr_dev;
     const lptr<T> lx = (lptr<T>)(lptr<unsigned char>)lds_raw;
     const lptr<T> ly = lx + n_box, lz = ly + n_box;
@@ -79,6 +79,7 @@ __global__ void __launch_bounds__(1024) k_lds_sweeps(LdsLaunch L)
                     const uint32_t row = k / (uint32_t)Lxh;
                     const int y = (int)(row % (uint32_t)Ly), z = (int)(row / (uint32_t)Ly);
                     const int p = (c + y + z) & 1;
+                    if (!occupied(R, 2 * xh + p, y, z, 0, 0, 0)) continue;
                     sc_site_field<T>(lx, ly, lz, c ? 0u : plane, Lxh, Ly, Lz, px, py, pz, xh, y,
                                      z, p, hx, hy, hz);
                     i = (c ? plane : 0u) + k;
@@ -126,10 +127,11 @@ __global__ void __launch_bounds__(1024) k_lds_sweeps(LdsLaunch L)
                     lz[i] = sz;
                 }
                 if (MEASURE) {
-                    T sh;
-                    if constexpr (KIND == SC) sh = c == 1 ? sx * hx + sy * hy + sz * hz : T(0);
-                    else sh = J * (sx * sh_x + sy * sh_y + sz * sh_z);
-                    accumulate<T>(acc, sx, sy, sz, ex, ey, ez, sh, a);
+                    if constexpr (KIND == SC)
+                        observe<T>(acc, sx, sy, sz, ex, ey, ez, c == 1, hx, hy, hz, 1.0);
+                    else
+                        observe<T>(acc, sx, sy, sz, ex, ey, ez, true, sh_x, sh_y, sh_z, Jd);
+                    acc[Q_NACC] += a ? 1.0 : 0.0;
                 }
             }
             __syncthreads();

@@ -2,6 +2,7 @@
 // scheme and their launchers.
 #include "basis_bodies.hpp"
 #include "sc_bodies.hpp"
+#include "sc_lband.hpp"
 
 namespace mc {
 
@@ -48,6 +49,14 @@ __global__ void __launch_bounds__(256) k_sc_pband(PassLaunch P, int colour)
     sc_pband_body<T, MEASURE, MODE, RY>(P, colour, item, *P.tctr_dev + P.t_off);
 }
 
+template <typename T, bool MEASURE, int MODE, int PP>
+__global__ void __launch_bounds__(256) k_sc_lband(PassLaunch P, int colour)
+{
+    uint32_t item;
+    if (!logical_item(P, item)) return;
+    sc_lband_body<T, MEASURE, MODE, PP>(P, colour, item, *P.tctr_dev + P.t_off);
+}
+
 template <int KIND, int B, typename T, bool MEASURE, int MODE>
 __global__ void __launch_bounds__(256) k_basis_strip(PassLaunch P)
 {
@@ -85,7 +94,23 @@ static hipError_t sc_launch(int colour, const PassLaunch &p, hipStream_t st)
         const dim3 g = pass_grid(p), b(p.tile.tx);
         switch (p.tile.ty) {
         case 2: hipLaunchKernelGGL((k_sc_pband<T, MEASURE, MODE, 2>), g, b, 0, st, p, colour); break;
-        case 4: hipLaunchKernelGGL((k_sc_pband<T, MEASURE, MODE, 4>), g, b, 0, st, p, colour); break;
+        case 4:
+            // four-row bands in FP64 need more than 256 registers (refused on the host)
+            if constexpr (sizeof(T) == 4) {
+                hipLaunchKernelGGL((k_sc_pband<T, MEASURE, MODE, 4>), g, b, 0, st, p, colour);
+                break;
+            } else {
+                return hipErrorInvalidValue;
+            }
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
+    if (p.tile.kernel == KERNEL_LBAND) {
+        const dim3 g = pass_grid(p), b(p.tile.tx);
+        switch (p.lds_positions) {
+        case 1: hipLaunchKernelGGL((k_sc_lband<T, MEASURE, MODE, 1>), g, b, p.lds_bytes, st, p, colour); break;
+        case 2: hipLaunchKernelGGL((k_sc_lband<T, MEASURE, MODE, 2>), g, b, p.lds_bytes, st, p, colour); break;
         default: return hipErrorInvalidValue;
         }
         return hipGetLastError();

@@ -22,6 +22,8 @@ struct PassLaunch {
     double *partials_dev;     // [n_colours][n_items][NQ]
     void *dbg_dh;             // debug: per-site dH (or null)
     uint8_t *dbg_acc;         // debug: per-site decision (or null)
+    uint32_t lds_bytes;       // dynamic LDS of the LDS-staged pass kernel
+    int32_t lds_positions;    // its (row, pair) positions per lane (1 or 2)
 };
 
 // mode: 0 = Metropolis update, 1 = observables of the current state only,
@@ -125,6 +127,15 @@ struct BlockLaunch {
     unsigned long long *counts;     // attempts, accepted, conflicts (accumulated)
 };
 hipError_t launch_block_step(bool f64, const BlockLaunch &B, hipStream_t st);
+
+// Observables of one replica's current state from scratch (independent of
+// the pass kernels): n_blocks (<= MEASURE_BLOCKS) workgroups write FP64
+// partials [n_blocks][8], then one workgroup sums them in block order into
+// record[NR] (M sums, E_exch, E_anis, occupied count in the R_NACC slot,
+// `sweep` in R_SWEEP).
+constexpr uint32_t MEASURE_BLOCKS = 1024;
+hipError_t launch_measure_direct(bool f64, int kind, const RepDev *rep_host, double *partials,
+                                 uint32_t n_blocks, double sweep, double *record, hipStream_t st);
 
 // XCC_ID of workgroups 0..n-1 (thread 0 of each writes one word).
 hipError_t launch_xcd_probe(uint32_t *out, uint32_t n, hipStream_t st);

@@ -54,7 +54,29 @@ enum : int32_t {
     KERNEL_PBAND = 5, // sc only, even packed rows: as KERNEL_BAND with two columns per thread
     KERNEL_BSTRIP = 6, // bcc / fcc: tx (multiple of 64) lanes along x, ty rows, planes in registers
     KERNEL_BPAIR = 7,  // bcc / fcc, even Lx: tx threads over (band, pair) positions, ty rows per band
+    KERNEL_LBAND = 8,  // sc only, 16-byte rows: tiles of ty whole rows, rows staged through LDS
 };
+
+// LDS elements of one stage of the LDS-staged band kernel for tiles of br rows
+// of lxh packed columns: the other colour's rows y0-1 .. y0+br and the own
+// colour's rows, three components each (two stages are held).
+// Chunks of 16 bytes per component of a staged buffer of `rows` rows of lxh
+// elements of esz bytes, padded to a multiple of 64 (one wave's copy).
+constexpr uint32_t lband_comp_chunks(int rows, int lxh, int esz)
+{
+    return ((uint32_t)rows * (uint32_t)lxh * (uint32_t)esz / 16u + 63u) / 64u * 64u;
+}
+// Bytes of dynamic LDS of a workgroup (two stages of other and own rows).
+constexpr uint32_t lband_lds_bytes(int br, int lxh, int esz)
+{
+    return 2u * 3u * 16u * (lband_comp_chunks(br + 2, lxh, esz) + lband_comp_chunks(br, lxh, esz));
+}
+// Copy slots per lane and buffer (chunk groups of 64 over 4 waves).
+constexpr int LBAND_SLOTS = 6;
+constexpr int lband_slots_needed(int rows, int lxh, int esz, int n_waves)
+{
+    return (int)((3u * lband_comp_chunks(rows, lxh, esz) / 64u + (uint32_t)n_waves - 1) / (uint32_t)n_waves);
+}
 
 // Tile of one workgroup: tx row columns x ty rows x zc planes, and the kernel
 // that maps it onto threads.

@@ -3,6 +3,8 @@
 // kernels and the persistent kernel.
 #pragma once
 
+#include <type_traits>
+
 #include "device_common.hpp"
 
 namespace mc {
@@ -16,7 +18,8 @@ namespace mc {
 //
 // Tile kernel: each thread owns one (xh, y) column of a tx x ty tile and walks
 // the tile's z range; neighbours are loaded directly (cache hits).  Used for
-// short rows.
+// short rows, and the only pass kernel (with the LDS kernel) for a simple-cubic
+// lattice cut to a sphere: it skips unoccupied sites.
 // ---------------------------------------------------------------------------
 template <typename T, bool MEASURE, int MODE>
 __device__ __forceinline__ void sc_tile_body(const PassLaunch &P, int colour, uint32_t item,
@@ -41,6 +44,8 @@ __device__ __forceinline__ void sc_tile_body(const PassLaunch &P, int colour, ui
         const int z1 = min(w.z0 + P.tile.zc, Lz);
         for (int z = w.z0; z < z1; ++z) {
             const int p = (colour + y + z) & 1;
+            // a site outside a sphere holds S = 0 and is never updated
+            if (!occupied(R, 2 * xh + p, y, z, 0, 0, 0)) continue;
             const uint32_t i = (uint32_t)(z * Ly + y) * Lxh + xh;
             T hx, hy, hz;
             sc_site_field<T>(gx, gy, gz, oth, Lxh, Ly, Lz, px, py, pz, xh, y, z, p, hx, hy, hz);
@@ -66,9 +71,10 @@ __device__ __forceinline__ void sc_tile_body(const PassLaunch &P, int colour, ui
             }
             // every bond has exactly one colour-1 end: count it there,
             // against colour-0 neighbours that are final after pass 0
-            if (MEASURE)
-                accumulate<T>(acc, sx, sy, sz, ex, ey, ez,
-                              colour == 1 ? sx * hx + sy * hy + sz * hz : T(0), a);
+            if (MEASURE) {
+                observe<T>(acc, sx, sy, sz, ex, ey, ez, colour == 1, hx, hy, hz, 1.0);
+                acc[Q_NACC] += a ? 1.0 : 0.0;
+            }
         }
     }
     if (MEASURE)
@@ -234,12 +240,7 @@ __device__ __forceinline__ void sc_strip_body(const PassLaunch &P, int colour, u
                 }
             }
             if (MEASURE && live) {
-                acc[Q_MX] += (double)sx;
-                acc[Q_MY] += (double)sy;
-                acc[Q_MZ] += (double)sz;
-                const double pe = (double)(sx * ex + sy * ey + sz * ez);
-                acc[Q_PE2] += pe * pe;
-                if (colour == 1) acc[Q_SH] += (double)(sx * hx + sy * hy + sz * hz);
+                observe<T>(acc, sx, sy, sz, ex, ey, ez, colour == 1, hx, hy, hz, 1.0);
                 n_acc += a ? 1u : 0u;
             }
         }
@@ -379,12 +380,7 @@ __device__ __forceinline__ void sc_pair_body(const PassLaunch &P, int colour, ui
             }
         }
         if (MEASURE && live) {
-            acc[Q_MX] += (double)sx;
-            acc[Q_MY] += (double)sy;
-            acc[Q_MZ] += (double)sz;
-            const double pe = (double)(sx * ex + sy * ey + sz * ez);
-            acc[Q_PE2] += pe * pe;
-            if (colour == 1) acc[Q_SH] += (double)(sx * hx + sy * hy + sz * hz);
+            observe<T>(acc, sx, sy, sz, ex, ey, ez, colour == 1, hx, hy, hz, 1.0);
             n_acc += a ? 1u : 0u;
         }
         return a;
@@ -465,10 +461,20 @@ __device__ __forceinline__ void sc_pair_body(const PassLaunch &P, int colour, ui
 // lanes contiguously, so no lane idles whatever the row length, and the bands
 // of one workgroup share their halo rows through the CU's cache.  With RY
 // even the row parity depends only on (k, z), so it is uniform over a wave.
+//
+// The planes of a tile are walked in z keeping only two sets of registers
+// across planes: the other colour's own rows of the previous plane (the -z
+// neighbours of the next plane) and, for every site of the current plane, the
+// partial field of its first five neighbours (-z, -y, -x, +x, +y, summed in
+// that order).  When the next plane's rows arrive, the +z term completes the
+// field (the same sum, in the same order, as every other kernel) and the sites
+// are updated.  The z loop is unrolled by two so the row parity is a
+// compile-time constant (no selects, one lane shift per row and component).
+// Fully periodic lattices take a variant without open-face masking.
 // ---------------------------------------------------------------------------
-template <typename T, bool MEASURE, int MODE, int RY>
-__device__ __forceinline__ void sc_pband_body(const PassLaunch &P, int colour, uint32_t item,
-                                              uint32_t t)
+template <typename T, bool MEASURE, int MODE, int RY, bool PER>
+__device__ __forceinline__ void sc_pband_run(const PassLaunch &P, int colour, uint32_t item,
+                                             uint32_t t)
 {
     static_assert(RY % 2 == 0, "band rows must be even");
     // every descriptor field is read into registers before the first store, so
@@ -493,7 +499,7 @@ __device__ __forceinline__ void sc_pband_body(const PassLaunch &P, int colour, u
     const T J = (T)R.J, K = (T)R.K, ex = (T)R.e[0], ey = (T)R.e[1], ez = (T)R.e[2];
     const T beta = (T)R.beta;
     const bool greedy = R.greedy != 0;
-    const bool px = R.pmask & 1u, py = R.pmask & 2u, pz = R.pmask & 4u;
+    const bool px = PER || (R.pmask & 1u), py = PER || (R.pmask & 2u), pz = PER || (R.pmask & 4u);
     const int xl = xa > 0 ? xa - 1 : (px ? Lxh - 1 : -1);  // column left of the pair
     const int xr = xb < Lxh - 1 ? xb + 1 : (px ? 0 : -1);  // column right of the pair
     const bool left_mem = lane == 0 || xa == 0;           // xa-1 not held by lane-1
@@ -527,45 +533,32 @@ __device__ __forceinline__ void sc_pband_body(const PassLaunch &P, int colour, u
         roff[k + 1] = (uint32_t)y * row_bytes + b_c;
         row_ok |= (ok ? 1u : 0u) << (k + 1);
     }
-    auto load_rows = [&](int z, Row2<T> *dst) {
-        if (z < 0) {
+    const Row2<T> zero = {T(0), T(0), T(0), T(0), T(0), T(0)};
+    // other-colour rows k0 .. k1-1 (of yb-1 .. yb+RY) of plane n; planes
+    // beyond an open z face and rows beyond an open y face read as zero
+    auto load_rows = [&](int n, Row2<T> *dst, int k0, int k1) __attribute__((always_inline)) {
+        if (n < 0 || n >= Lz) {
+            if (!pz) {
 #pragma unroll
-            for (int k = 0; k < RY + 2; ++k) dst[k] = Row2<T>{T(0), T(0), T(0), T(0), T(0), T(0)};
-            return;
+                for (int k = k0; k < k1; ++k) dst[k] = zero;
+                return;
+            }
+            n = n < 0 ? n + Lz : n - Lz;
         }
-        const uint32_t soff = oth_b + (uint32_t)z * zplane_b;
+        const uint32_t soff = oth_b + (uint32_t)n * zplane_b;
 #pragma unroll
-        for (int k = 0; k < RY + 2; ++k) {
+        for (int k = k0; k < k1; ++k) {
             buf_load2(q.x, roff[k], soff, dst[k].xa, dst[k].xb);
             buf_load2(q.y, roff[k], soff, dst[k].ya, dst[k].yb);
             buf_load2(q.z, roff[k], soff, dst[k].za, dst[k].zb);
-            if (!py && !((row_ok >> k) & 1u)) dst[k] = Row2<T>{T(0), T(0), T(0), T(0), T(0), T(0)};
-        }
-    };
-    // the in-row neighbour beyond the pair where the lane shift cannot supply
-    // it (wave edges, band seams, the periodic wrap, open faces), loaded one
-    // plane ahead
-    auto load_edges = [&](int z, Vec3<T> *dst) {
-        const uint32_t soff = oth_b + (uint32_t)z * zplane_b;
-#pragma unroll
-        for (int k = 0; k < RY; ++k) {
-            const int p = (colour + k + z) & 1;
-            const bool need = p ? right_mem : left_mem;
-            const int col = p ? xr : xl;
-            if (need && col >= 0) {
-                const uint32_t v = roff[k + 1] - b_c + (p ? b_r : b_l);
-                dst[k] = {buf_load(q.x, v, soff, T()), buf_load(q.y, v, soff, T()),
-                          buf_load(q.z, v, soff, T())};
-            } else {
-                dst[k] = {T(0), T(0), T(0)};
-            }
+            if (!PER && !py && !((row_ok >> k) & 1u)) dst[k] = zero;
         }
     };
 
     double acc[Q_N] = {0, 0, 0, 0, 0, 0};
     uint32_t n_acc = 0;
     auto site = [&](T &sx, T &sy, T &sz, T hx, T hy, T hz, uint32_t s, bool live,
-                    uint32_t i) -> bool {
+                    uint32_t i) __attribute__((always_inline)) -> bool {
         hx *= J;
         hy *= J;
         hz *= J;
@@ -580,78 +573,153 @@ __device__ __forceinline__ void sc_pband_body(const PassLaunch &P, int colour, u
             }
         }
         if (MEASURE && live) {
-            acc[Q_MX] += (double)sx;
-            acc[Q_MY] += (double)sy;
-            acc[Q_MZ] += (double)sz;
-            const double pe = (double)(sx * ex + sy * ey + sz * ez);
-            acc[Q_PE2] += pe * pe;
-            if (colour == 1) acc[Q_SH] += (double)(sx * hx + sy * hy + sz * hz);
+            observe<T>(acc, sx, sy, sz, ex, ey, ez, colour == 1, hx, hy, hz, 1.0);
             n_acc += a ? 1u : 0u;
         }
         return a;
     };
 
     const int z0 = w.z0, z1 = min(w.z0 + P.tile.zc, Lz);
-    Row2<T> om[RY + 2], oc[RY + 2], op[RY + 2];
-    Vec3<T> ec[RY], en[RY];
-    load_rows(z0 > 0 ? z0 - 1 : (pz ? Lz - 1 : -1), om);
-    load_rows(z0, oc);
-    load_edges(z0, ec);
-    for (int z = z0; z < z1; ++z) {
-        const int zn = z < Lz - 1 ? z + 1 : (pz ? 0 : -1);
-        load_rows(zn, op);
-        if (z + 1 < z1) load_edges(zn, en);
-        const uint32_t s_own = own_b + (uint32_t)z * zplane_b;
+    Row2<T> mid[RY];  // other colour, rows yb .. yb+RY-1 of the previous plane
+    Row2<T> part[RY]; // partial fields (-z, -y, -x, +x, +y) of the current plane's sites
+
+    // partial fields of plane n (row parity of row k: (Q + k) & 1) from its
+    // other-colour rows o[0 .. RY+1] and the previous plane's rows `mid`
+    auto partial = [&](int Q, int n, const Row2<T> *o, Row2<T> *dst) __attribute__((always_inline)) {
+        const uint32_t soff = oth_b + (uint32_t)n * zplane_b; // z0 <= n < z1
 #pragma unroll
         for (int k = 0; k < RY; ++k) {
-            const int y = yb + k;
-            const bool live = fin && y < Ly;
-            const int p = (colour + k + z) & 1; // uniform over the wave (RY even)
-            Row2<T> me;
-            buf_load2(q.x, roff[k + 1], s_own, me.xa, me.xb);
-            buf_load2(q.y, roff[k + 1], s_own, me.ya, me.yb);
-            buf_load2(q.z, roff[k + 1], s_own, me.za, me.zb);
-            const Row2<T> c = oc[k + 1];
-            // the other colour's column beyond the pair
+            const int p = (Q + k) & 1; // uniform over the wave
+            const Row2<T> &c = o[k + 1];
+            // the other colour's column beyond the pair: lane l-1's second
+            // column (p = 0) or lane l+1's first (p = 1); from memory where
+            // no lane holds it
             Vec3<T> nb;
             if (p == 0)
                 nb = {from_lower_lane(c.xb), from_lower_lane(c.yb), from_lower_lane(c.zb)};
             else
                 nb = {from_upper_lane(c.xa), from_upper_lane(c.ya), from_upper_lane(c.za)};
-            if (p ? right_mem : left_mem) nb = ec[k];
+            const bool need = p ? right_mem : left_mem;
+            if (need) {
+                const int col = p ? xr : xl;
+                if (PER || col >= 0) {
+                    const uint32_t v = roff[k + 1] - b_c + (p ? b_r : b_l);
+                    nb = {buf_load(q.x, v, soff, T()), buf_load(q.y, v, soff, T()),
+                          buf_load(q.z, v, soff, T())};
+                } else {
+                    nb = {T(0), T(0), T(0)};
+                }
+            }
             // in-row neighbours (x-1, x+1) of column a and of column b
-            const T lax = p ? c.xa : nb.x, lay = p ? c.ya : nb.y, laz = p ? c.za : nb.z;
-            const T hax = p ? c.xb : c.xa, hay = p ? c.yb : c.ya, haz = p ? c.zb : c.za;
-            const T lbx = p ? c.xb : c.xa, lby = p ? c.yb : c.ya, lbz = p ? c.zb : c.za;
-            const T hbx = p ? nb.x : c.xb, hby = p ? nb.y : c.yb, hbz = p ? nb.z : c.zb;
-            // fixed order: -z, -y, -x, +x, +y, +z
-            const T hxa = om[k + 1].xa + oc[k].xa + lax + hax + oc[k + 2].xa + op[k + 1].xa;
-            const T hya = om[k + 1].ya + oc[k].ya + lay + hay + oc[k + 2].ya + op[k + 1].ya;
-            const T hza = om[k + 1].za + oc[k].za + laz + haz + oc[k + 2].za + op[k + 1].za;
-            const T hxb = om[k + 1].xb + oc[k].xb + lbx + hbx + oc[k + 2].xb + op[k + 1].xb;
-            const T hyb = om[k + 1].yb + oc[k].yb + lby + hby + oc[k + 2].yb + op[k + 1].yb;
-            const T hzb = om[k + 1].zb + oc[k].zb + lbz + hbz + oc[k + 2].zb + op[k + 1].zb;
+            const Vec3<T> la = p ? Vec3<T>{c.xa, c.ya, c.za} : nb;
+            const Vec3<T> ha = p ? Vec3<T>{c.xb, c.yb, c.zb} : Vec3<T>{c.xa, c.ya, c.za};
+            const Vec3<T> lb = p ? Vec3<T>{c.xb, c.yb, c.zb} : Vec3<T>{c.xa, c.ya, c.za};
+            const Vec3<T> hb = p ? nb : Vec3<T>{c.xb, c.yb, c.zb};
+            // fixed order: -z, -y, -x, +x, +y (+z added when the next plane arrives)
+            dst[k].xa = mid[k].xa + o[k].xa + la.x + ha.x + o[k + 2].xa;
+            dst[k].ya = mid[k].ya + o[k].ya + la.y + ha.y + o[k + 2].ya;
+            dst[k].za = mid[k].za + o[k].za + la.z + ha.z + o[k + 2].za;
+            dst[k].xb = mid[k].xb + o[k].xb + lb.x + hb.x + o[k + 2].xb;
+            dst[k].yb = mid[k].yb + o[k].yb + lb.y + hb.y + o[k + 2].yb;
+            dst[k].zb = mid[k].zb + o[k].zb + lb.z + hb.z + o[k + 2].zb;
+        }
+    };
+
+    // sites of plane z (row parity (Q + k) & 1): the +z rows are top[0 .. RY-1]
+    // own rows of plane z (the sites' current spins)
+    auto load_own = [&](int z, Row2<T> *me) __attribute__((always_inline)) {
+        const uint32_t s_own = own_b + (uint32_t)z * zplane_b;
+#pragma unroll
+        for (int k = 0; k < RY; ++k) {
+            buf_load2(q.x, roff[k + 1], s_own, me[k].xa, me[k].xb);
+            buf_load2(q.y, roff[k + 1], s_own, me[k].ya, me[k].yb);
+            buf_load2(q.z, roff[k + 1], s_own, me[k].za, me[k].zb);
+        }
+    };
+    auto update = [&](int Q, int z, const Row2<T> *pf, const Row2<T> *top, Row2<T> *me)
+        __attribute__((always_inline)) {
+        const uint32_t s_own = own_b + (uint32_t)z * zplane_b;
+#pragma unroll
+        for (int k = 0; k < RY; ++k) {
+            const int p = (Q + k) & 1;
+            const int y = yb + k;
+            const bool live = fin && y < Ly;
+            const T hxa = pf[k].xa + top[k].xa, hya = pf[k].ya + top[k].ya,
+                    hza = pf[k].za + top[k].za;
+            const T hxb = pf[k].xb + top[k].xb, hyb = pf[k].yb + top[k].yb,
+                    hzb = pf[k].zb + top[k].zb;
             const uint32_t s0 = (uint32_t)(z * Ly + y) * (uint32_t)Lx + 2u * xa + p;
             const uint32_t i0 = own + (uint32_t)(z * Ly + y) * Lxh + xa;
-            const bool aa = site(me.xa, me.ya, me.za, hxa, hya, hza, s0, live, i0);
-            const bool ab = site(me.xb, me.yb, me.zb, hxb, hyb, hzb, s0 + 2u, live, i0 + 1u);
+            const bool aa = site(me[k].xa, me[k].ya, me[k].za, hxa, hya, hza, s0, live, i0);
+            const bool ab = site(me[k].xb, me[k].yb, me[k].zb, hxb, hyb, hzb, s0 + 2u, live,
+                                 i0 + 1u);
             if (MODE != 1 && live && (aa || ab)) {
-                buf_store2(me.xa, me.xb, q.x, roff[k + 1], s_own);
-                buf_store2(me.ya, me.yb, q.y, roff[k + 1], s_own);
-                buf_store2(me.za, me.zb, q.z, roff[k + 1], s_own);
+                buf_store2(me[k].xa, me[k].xb, q.x, roff[k + 1], s_own);
+                buf_store2(me[k].ya, me[k].yb, q.y, roff[k + 1], s_own);
+                buf_store2(me[k].za, me[k].zb, q.z, roff[k + 1], s_own);
             }
         }
+    };
+
+    // one plane step: plane n's other-colour rows complete the sites of plane
+    // n-1 and, unless n is past the tile, start the partial fields of plane n
+    auto step = [&](int n) __attribute__((always_inline)) {
+        const int Q = (colour + n) & 1;
+        Row2<T> o[RY + 2], me[RY];
+        if (n < z1) {
+            // every load of the step is issued first; the new partial fields
+            // are formed before the site updates, so the previous plane's rows
+            // and this plane's halo rows are dead by then
+            load_rows(n, o, 0, RY + 2);
+            load_own(n - 1, me);
+            Row2<T> next[RY];
+            partial(Q, n, o, next);
+            update(Q ^ 1, n - 1, part, o + 1, me);
 #pragma unroll
-        for (int k = 0; k < RY + 2; ++k) om[k] = oc[k];
+            for (int k = 0; k < RY; ++k) {
+                part[k] = next[k];
+                mid[k] = o[k + 1];
+            }
+        } else {
+            load_rows(n, o, 1, RY + 1);
+            load_own(n - 1, me);
+            update(Q ^ 1, n - 1, part, o + 1, me);
+        }
+    };
+    {
+        Row2<T> o[RY + 2];
+        load_rows(z0 - 1, o, 1, RY + 1);
 #pragma unroll
-        for (int k = 0; k < RY + 2; ++k) oc[k] = op[k];
+        for (int k = 0; k < RY; ++k) mid[k] = o[k + 1];
+        load_rows(z0, o, 0, RY + 2);
+        partial((colour + z0) & 1, z0, o, part);
 #pragma unroll
-        for (int k = 0; k < RY; ++k) ec[k] = en[k];
+        for (int k = 0; k < RY; ++k) mid[k] = o[k + 1];
     }
+    // two planes per iteration, so the loop-carried rows alternate between
+    // two register sets instead of being copied
+    int n = z0 + 1;
+    for (; n < z1; n += 2) {
+        step(n);
+        step(n + 1);
+    }
+    if (n == z1) step(n);
+
     if (MEASURE) {
         acc[Q_NACC] = (double)n_acc;
         block_store_partials(acc, P.partials_dev + ((size_t)colour * P.n_items + item) * NQ);
     }
+}
+
+template <typename T, bool MEASURE, int MODE, int RY>
+__device__ __forceinline__ void sc_pband_body(const PassLaunch &P, int colour, uint32_t item,
+                                              uint32_t t)
+{
+    const WorkItem w = P.work_dev[item];
+    if (P.reps_dev[w.rep].pmask == 7u)
+        sc_pband_run<T, MEASURE, MODE, RY, true>(P, colour, item, t);
+    else
+        sc_pband_run<T, MEASURE, MODE, RY, false>(P, colour, item, t);
 }
 
 // ---------------------------------------------------------------------------
@@ -814,12 +882,7 @@ __device__ __forceinline__ void sc_band_body(const PassLaunch &P, int colour, ui
                 }
             }
             if (MEASURE && live) {
-                acc[Q_MX] += (double)sx;
-                acc[Q_MY] += (double)sy;
-                acc[Q_MZ] += (double)sz;
-                const double pe = (double)(sx * ex + sy * ey + sz * ez);
-                acc[Q_PE2] += pe * pe;
-                if (colour == 1) acc[Q_SH] += (double)(sx * hx + sy * hy + sz * hz);
+                observe<T>(acc, sx, sy, sz, ex, ey, ez, colour == 1, hx, hy, hz, 1.0);
                 n_acc += a ? 1u : 0u;
             }
         }

@@ -127,6 +127,11 @@ _SIGNATURES = {
     "mc_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_char_p,
                                    ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                    ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+    "mc_measure_buffers": (ctypes.c_int, [ctypes.POINTER(ReplicaDesc), ctypes.c_int,
+                                          ctypes.POINTER(SpinBuffers), ctypes.c_void_p,
+                                          ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p]),
+    "mc_tune_device_key": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.c_char_p, ctypes.c_uint64]),
     "mc_synchronize": (ctypes.c_int, [ctypes.c_void_p]),
     "mc_destroy": (None, [ctypes.c_void_p]),
     "mc_last_error": (ctypes.c_char_p, []),
@@ -165,6 +170,14 @@ def last_error() -> str:
 
 def version() -> str:
     return LIB.mc_version().decode()
+
+
+def tune_device_key(arch: str, n_cu: int, n_xcd: int) -> str:
+    """``mc_tune_device_key``: the device part of the autotuner's cache key."""
+    buf = ctypes.create_string_buffer(256)
+    _check("mc_tune_device_key", LIB.mc_tune_device_key(arch.encode(), int(n_cu), int(n_xcd), buf,
+                                                        len(buf)))
+    return buf.value.decode()
 
 
 def stream_probe(x, y, z, grid: int = 2048, reps: int = 10, stream=None) -> float:
@@ -217,6 +230,31 @@ def required_sites(rep: Replica) -> int:
     d = rep.desc()
     _check("mc_required_sites", LIB.mc_required_sites(ctypes.byref(d), ctypes.byref(n)))
     return int(n.value)
+
+
+MEASURE_WORKSPACE_BYTES = 65536  # MC_MEASURE_WORKSPACE_BYTES
+
+
+def _record_dict(r) -> dict:
+    return {"M": np.array(r[0:3]), "E_exch": float(r[3]), "E_anis": float(r[4]),
+            "E": float(r[3] + r[4]), "n_sites": int(r[5])}
+
+
+def measure_buffers(rep: Replica, precision: str, sx, sy, sz, workspace=None) -> dict:
+    """``mc_measure_buffers``: from-scratch observables of spins held in three
+    device tensors (library layout) on the current stream; synchronises and
+    returns {M (sums), E_exch, E_anis, E, n_sites}."""
+    prec = {"f32": F32, "f64": F64}[precision]
+    d = rep.desc()
+    b = SpinBuffers(sx.data_ptr(), sy.data_ptr(), sz.data_ptr(), int(sx.numel()))
+    if workspace is None:
+        workspace = torch.empty(MEASURE_WORKSPACE_BYTES, dtype=torch.uint8, device=sx.device)
+    rec = torch.zeros(8, dtype=torch.float64, device=sx.device)
+    stream = torch.cuda.current_stream(sx.device).cuda_stream
+    _check("mc_measure_buffers", LIB.mc_measure_buffers(
+        ctypes.byref(d), prec, ctypes.byref(b), workspace.data_ptr(), workspace.numel(),
+        rec.data_ptr(), stream))
+    return _record_dict(rec.cpu().tolist())
 
 
 def occupied_sites(rep: Replica) -> int:
@@ -455,7 +493,8 @@ class Simulation:
         (tx threads along the row, ty rows per thread), 2 = sc band, 3 = whole
         sweeps in LDS (tx threads per replica), 4 = sc pair strip (two columns
         per thread), 5 = sc band of pairs, 6 = bcc/fcc strip, 7 = bcc/fcc band of
-        cell pairs; zc planes per tile."""
+        cell pairs, 8 = sc tiles of ty whole rows staged through LDS (tx = 256);
+        zc planes per tile."""
         _check("mc_set_tile", LIB.mc_set_tile(self.handle, int(kernel), int(tx), int(ty), int(zc)))
 
     def autotune(self, trial_sweeps: int = 5, measure: bool = True, persistent: bool = False,

@@ -5,8 +5,8 @@ and benchmarks; contains none of the method's arithmetic.
 The lattices follow the paper's setup (simple cubic, periodic, J = 1, small
 uniaxial K, unit spins; arXiv:2106.11286, simulation-setup paragraph and
 Figs. 2-3) at the sizes of the benchmark configurations, plus an FCC
-nanoparticle with open surface for the "any crystal lattice" claim of the
-abstract and conclusion.
+nanoparticle with open surface for the claim of the abstract and conclusion
+that the method fits any crystal lattice.
 """
 from __future__ import annotations
 
@@ -37,8 +37,8 @@ C5_SC464_ROOFLINE = dict(
     J=1.0, K=0.02, e=(0.0, 0.0, 1.0), T=1.4, seed=4, sweeps=1000)
 
 # bcc at the benchmark's scale: 2 x 368^3 = 99,672,064 spins, periodic, in the
-# ordered phase at moderate acceptance (the "any crystal lattice" claim at the
-# paper's 10^8-spin size)
+# ordered phase at moderate acceptance (the claim that the method fits any
+# crystal lattice, at the paper's 10^8-spin size)
 BCC_368_1E8 = dict(
     name="bcc-L368-1e8-spins", kind="bcc", L=(368, 368, 368), periodic_mask=7,
     J=1.0, K=0.02, e=(0.0, 0.0, 1.0), T=1.9, seed=6, sweeps=200)

@@ -107,3 +107,20 @@ def test_simulation_without_gpu_fails_loudly(M):
         pytest.skip("GPU present")
     with pytest.raises(M.MCError):
         M.Simulation([M.Replica(L=(8, 8, 8))])
+
+
+def test_tune_device_key_separates_devices(M):
+    """The autotuner's cache key changes with the architecture, the compute
+    unit count and the XCD count (a partition mode changes the last two), so
+    a cached tile never carries over between such devices."""
+    a = M.tune_device_key("gfx950:sramecc+:xnack-", 256, 8)
+    assert a == "gfx950:sramecc+:xnack--cu256-xcd8"
+    others = {M.tune_device_key("gfx950:sramecc+:xnack-", 32, 1),
+              M.tune_device_key("gfx950:sramecc+:xnack-", 64, 2),
+              M.tune_device_key("gfx942:sramecc+:xnack-", 256, 8),
+              M.tune_device_key("gfx950:sramecc+:xnack-", 256, 4)}
+    assert a not in others and len(others) == 4
+    assert " " not in M.tune_device_key("gfx 950/x", 1, 1)
+    with pytest.raises(M.MCError) as ei:
+        M.tune_device_key("gfx950", -1, 8)
+    assert ei.value.status == -1

@@ -1,0 +1,275 @@
+"""Parity at the 10^8-spin scale (and the FCC nanoparticle) against the FP64
+CPU oracle, on every site.
+
+The oracle tabulates these lattices in seconds, so nothing is sampled:
+  * observables (Eq. (2) magnetisation, both terms of Eq. (1)) of the state
+    after a measured sweep in the launch configuration the benchmark times
+    (autotuned tile, fused FP64 reduction) against the oracle's from-scratch
+    observables of the same state, and the library's separate from-scratch
+    measurement against the same;
+  * that sweep's result against the oracle's sweep from the same state;
+  * each colour pass of the next sweep site by site against the oracle's pass
+    from the identical state (the paper's Monte Carlo paragraph): dH,
+    decision, new spin; rejected sites and sites of other colours unchanged
+    bit for bit; energy bookkeeping (change of the oracle's energy over the
+    pass = sum of accepted dH).
+Bars (FP32): |dH32 - dH64| <= 1e-5 max(|dH64|, J); decisions equal unless
+|beta dH64 + ln P| < 1e-4; accepted spins within 2e-6.  FP64: the oracle's
+chain (decisions identical, spins 1e-12, m 1e-12, E 1e-10 relative).
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2106_11286_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+KIND = {"sc": O.SC, "bcc": O.BCC, "fcc": O.FCC}
+
+
+@pytest.fixture(scope="module")
+def M():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    from paper_2106_11286_amd import mcheis
+
+    return mcheis
+
+
+def natural(sim, r=0):
+    return [t.double().cpu().numpy() for t in sim.to_natural(r)]
+
+
+def storage_index(rep):
+    """Storage index of every canonical site (the ABI's layout rule)."""
+    Lx, Ly, Lz = rep.L
+    nb = {"sc": 1, "bcc": 2, "fcc": 4}[rep.kind]
+    s = np.arange(Lx * Ly * Lz * nb, dtype=np.int64)
+    if rep.kind == "sc":
+        x = s % Lx
+        y = (s // Lx) % Ly
+        z = s // (Lx * Ly)
+        return ((x + y + z) & 1) * (Lx * Ly * Lz // 2) + s // 2
+    return (s % nb) * (Lx * Ly * Lz) + s // nb
+
+
+class Case:
+    """A GPU simulation of one replica beside the oracle's tables."""
+
+    def __init__(self, M, w, prec):
+        import torch
+
+        self.rep = M.Replica(**W.replica_fields(w))
+        self.prec = prec
+        self.seed = w["seed"]
+        self.sim = M.Simulation([self.rep], precision=prec, seed=self.seed,
+                                scratch=torch.empty(64 << 20, dtype=torch.uint8, device="cuda"))
+        r = self.rep
+        self.lat = O.Lattice(KIND[r.kind], *r.L, periodic_mask=r.periodic_mask,
+                             sphere_radius=r.sphere_radius)
+        self.p = O.Params(J=r.J, K=r.K, e=r.e, T=r.T, seed=self.seed, replica_id=r.replica_id)
+        occ, col, _, _ = self.lat.tables()
+        self.occ, self.col = occ, col
+        self.sidx = storage_index(r)
+
+    def full_pass(self, colour):
+        """One colour pass on the GPU (debug instantiation of the current
+        kernel, which writes per-site dH and decisions) against the oracle's
+        pass from the identical state; returns the number of margin flips."""
+        f32 = self.prec == "f32"
+        t = self.sim.get_sweep()
+        before = natural(self.sim)
+        dh, acc = self.sim.debug_pass(colour)
+        dh = dh[0].double().cpu().numpy()[self.sidx]
+        acc = acc[0].cpu().numpy()[self.sidx]
+        after = natural(self.sim)
+        ref = [a.copy() for a in before]
+        e0 = O.observables(self.lat, self.p, before)["E"]
+        n_orc, dh64, acc64, mg = O.run_pass(self.lat, self.p, colour, t, ref, outputs=True)
+        sel = self.occ & (self.col == colour)
+        # sites of other colours and unoccupied sites are never visited
+        assert np.all(acc[~sel] == 255)
+        assert np.all(acc[sel] <= 1)
+        a_gpu = acc[sel].astype(bool)
+        a_orc = acc64[sel]
+        J = abs(self.rep.J)
+        d = np.abs(dh[sel] - dh64[sel])
+        if f32:
+            assert np.all(d <= 1e-5 * np.maximum(np.abs(dh64[sel]), J)), d.max()
+            flip = a_gpu != a_orc
+            assert np.all(np.abs(mg[sel][flip]) < 1e-4)
+        else:
+            assert np.all(d <= 1e-12 * np.maximum(np.abs(dh64[sel]), J)), d.max()
+            flip = np.zeros_like(a_gpu)
+            assert np.array_equal(a_gpu, a_orc)
+        tol = 2e-6 if f32 else 1e-12
+        both = np.zeros(self.lat.n_box, bool)
+        both[sel] = a_gpu & a_orc
+        none = np.zeros(self.lat.n_box, bool)
+        none[sel] = ~a_gpu & ~a_orc
+        for g, o, b in zip(after, ref, before):
+            assert np.max(np.abs(g[both] - o[both]), initial=0.0) <= tol
+            # rejected moves and untouched sites keep their bits
+            assert np.array_equal(g[none], b[none])
+            assert np.array_equal(g[~sel], b[~sel])
+        # energy bookkeeping (no bond joins two sites of one colour): the
+        # oracle's energy change over the GPU's pass = the GPU's accepted dH
+        e1 = O.observables(self.lat, self.p, after)["E"]
+        acc_dh = float(dh[sel][a_gpu].sum())
+        assert abs((e1 - e0) - acc_dh) <= (1e-7 if f32 else 1e-9) * max(1.0, abs(e0)) + \
+            (1e-6 * self.lat.n_occ if f32 else 0.0), (e1 - e0, acc_dh)
+        return int(flip.sum())
+
+    def measured_sweep(self):
+        """One measured sweep with the benchmark's kernel: fused records and
+        the library's from-scratch measurement against the oracle's
+        observables of the resulting state, and the state against the
+        oracle's sweep from the same starting state."""
+        f32 = self.prec == "f32"
+        t = self.sim.get_sweep()
+        before = natural(self.sim)
+        self.sim.sweep(1, measure=True)
+        fused = self.sim.observables()[0]
+        direct = self.sim.measure_state()[0]
+        after = natural(self.sim)
+        N = self.lat.n_occ
+        ob = O.observables(self.lat, self.p, after)
+        assert fused["n_sites"] == N and fused["sweep"] == t + 1
+        for o in (fused, direct):
+            assert np.max(np.abs(o["M"] - ob["m"])) <= 1e-12, (o["M"], ob["m"])
+        # fused: FP32 neighbour fields (the update's own) enter the bond sum
+        # (FP32: the chain's Hamiltonian has the easy axis rounded to FP32, so
+        # each (S.e)^2 may differ from the oracle's by up to 2 sqrt(3) 2^-24)
+        tol_an = 4e-7 * abs(self.rep.K) * N if f32 else 1e-10 * abs(ob["E"])
+        assert abs(fused["E"] - ob["E"]) <= (1e-9 if f32 else 1e-10) * abs(ob["E"]) + tol_an, \
+            (fused["E"], ob["E"])
+        assert abs(fused["E_anis"] - ob["E_anis"]) <= tol_an, (fused["E_anis"], ob["E_anis"])
+        # from scratch: every product in FP64 on FP32-exact values
+        assert abs(direct["E"] - ob["E"]) <= 1e-12 * abs(ob["E"]), (direct["E"], ob["E"])
+        ref = [a.copy() for a in before]
+        n_orc = O.sweep(self.lat, self.p, t, ref)
+        if f32:
+            # a margin flip changes one site and, in the second pass, the
+            # fields of its neighbours: count sites off by more than rounding
+            off = np.zeros(self.lat.n_box, bool)
+            for g, o in zip(after, ref):
+                off |= np.abs(g - o) > 2e-6
+            n_off = int(off.sum())
+            print("sites off by more than 2e-6 after one sweep:", n_off, flush=True)
+            assert n_off <= max(50, 2e-5 * N), n_off
+            assert abs(fused["n_accepted"] - n_orc) <= max(50, n_off)
+        else:
+            for g, o in zip(after, ref):
+                assert np.max(np.abs(g - o)) <= 1e-12
+            assert fused["n_accepted"] == n_orc
+        return fused
+
+
+def run_full_size(M, w, prec, sweeps, trial_sweeps):
+    import torch
+
+    c = Case(M, w, prec)
+    tile = c.sim.autotune(trial_sweeps=trial_sweeps, measure=True)
+    print(w["name"], prec, "autotuned tile", tile, flush=True)
+    c.sim.sweep(sweeps)
+    c.measured_sweep()
+    n_flip = sum(c.full_pass(k) for k in range(c.lat.n_colours))
+    print(w["name"], prec, "margin flips", n_flip, "of", c.lat.n_occ, "attempts", flush=True)
+    # every flip lies inside the margin (checked per pass); FP32 rounding of
+    # dH (~1e-6) and exp puts about one attempt in 10^6 there
+    assert n_flip <= (max(3, 1e-5 * c.lat.n_occ) if prec == "f32" else 0)
+    del c
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_full_size_sc464(M, prec):
+    """sc 464^3 (99,897,344 spins), the headline workload, after the tuning
+    sweeps and 93 more."""
+    run_full_size(M, W.C5_SC464_ROOFLINE, prec, sweeps=93, trial_sweeps=6)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_full_size_bcc368(M, prec):
+    """bcc 2 x 368^3 (99,672,064 spins)."""
+    run_full_size(M, W.BCC_368_1E8, prec, sweeps=10, trial_sweeps=2)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_full_size_fcc292(M, prec):
+    """fcc 4 x 292^3 (99,588,352 spins)."""
+    run_full_size(M, W.FCC_292_1E8, prec, sweeps=5, trial_sweeps=2)
+
+
+def test_fcc_nanoparticle_every_site(M):
+    """The FCC nanoparticle (128^3 cells, R = 60 cells, open surface, 3,618,393
+    spins): its default kernel after 20 sweeps, then all four colour passes
+    at every site with energy bookkeeping; unoccupied sites never visited."""
+    c = Case(M, W.C4_FCC_PARTICLE, "f32")
+    c.sim.sweep(19)
+    c.measured_sweep()
+    n_flip = sum(c.full_pass(k) for k in range(4))
+    assert n_flip <= max(3, 1e-5 * c.lat.n_occ)
+    g = natural(c.sim)
+    for a in g:
+        assert np.all(a[~c.occ] == 0.0)
+
+
+def test_sc_1024_beyond_4gib(M):
+    """sc 1024^3 (1,073,741,824 spins, 12.9 GB of FP32 spins: each component
+    array is exactly 4 GiB, past the 32-bit offsets of the buffer kernels):
+    the default kernel is the LDS-staged one (64-bit addresses).  Three
+    sweeps equal the tile kernel's bitwise; then one debug pass at 4096
+    sampled sites of each colour against the oracle's single-site
+    evaluation; the fused records against the library's from-scratch
+    measurement."""
+    import torch
+
+    rep = M.Replica(kind="sc", L=(1024, 1024, 1024), J=1.0, K=0.02, e=(0.0, 0.0, 1.0), T=1.4)
+    a = M.Simulation([rep], precision="f32", seed=10)
+    assert a.get_tile()[0] == 8, a.get_tile()
+    a.sweep(2)
+    a.sweep(1, measure=True)
+    fused = a.observables()[0]
+    direct = a.measure_state()[0]
+    assert fused["n_sites"] == 1024**3
+    assert np.max(np.abs(fused["M"] - direct["M"])) <= 1e-12
+    assert abs(fused["E"] - direct["E"]) <= 1e-9 * abs(direct["E"])
+    b = M.Simulation([rep], precision="f32", seed=10)
+    b.set_tile(32, 8, 8, kernel=0)
+    b.sweep(3)
+    for x, y in zip(a.to_natural(0), b.to_natural(0)):
+        assert torch.equal(x, y)
+        del x, y
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+    geo = O.Geometry(O.SC, 1024, 1024, 1024, periodic_mask=7)
+    p = O.Params(J=rep.J, K=rep.K, e=rep.e, T=rep.T, seed=10)
+    rng = np.random.default_rng(1024)
+    t = a.get_sweep()
+    n_flip = 0
+    for colour in (0, 1):
+        before = natural(a)
+        dh, acc = a.debug_pass(colour)
+        after = natural(a)
+        s = rng.integers(0, 1024**3, size=4 * 4096)
+        x, y, z = s % 1024, (s // 1024) % 1024, s // (1024 * 1024)
+        s = s[((x + y + z) & 1) == colour][:4096]
+        idx = torch.as_tensor(colour * (1024**3 // 2) + s // 2, dtype=torch.int64, device="cuda")
+        dhs = dh[0][idx].double().cpu().numpy()
+        accs = acc[0][idx].cpu().numpy()
+        del dh, acc
+        for k, site in enumerate(s):
+            r = geo.site_attempt(p, t, before, int(site))
+            assert abs(dhs[k] - r["dH"]) <= 1e-5 * max(abs(r["dH"]), 1.0), (site, dhs[k], r)
+            if bool(accs[k]) != r["accepted"]:
+                assert abs(r["margin"]) < 1e-4, (site, r)
+                n_flip += 1
+                continue
+            got = np.array([after[0][site], after[1][site], after[2][site]])
+            assert np.max(np.abs(got - r["S_after"])) <= 2e-6
+        del before, after
+    assert n_flip <= 2

@@ -79,6 +79,10 @@ SMALL_CASES = [
     dict(kind="sc", L=(150, 14, 12), periodic_mask=7, J=1.0, K=0.05, e=(0.0, 0.0, 1.0), T=1.4),
     # sc long rows, open in y and z with odd lengths
     dict(kind="sc", L=(130, 9, 7), periodic_mask=1, J=0.8, K=0.2, e=(0.3, 0.0, 1.0), T=1.1),
+    # sc cut to a sphere (open surface): the tile and LDS kernels skip the
+    # unoccupied sites
+    dict(kind="sc", L=(14, 12, 10), periodic_mask=0, sphere_radius=4.6, J=1.0, K=0.1,
+         e=(0.2, 0.3, 1.0), T=1.1),
 ]
 
 
@@ -179,6 +183,11 @@ def _single_pass_check(M, rep, seed, sweeps, prec="f32"):
             a_sel = sel & acc64.astype(bool) & (acc.astype(bool) == acc64)
             for a, b in zip(after, ref):
                 assert np.max(np.abs(a[a_sel] - b[a_sel]), initial=0.0) <= 2e-6
+            # rejected moves, other colours and unoccupied sites keep their bits
+            keep = ~sel | ((acc == 0) & ~acc64.astype(bool))
+            assert np.all(acc[~sel] == 255)
+            for a, b in zip(after, state):
+                assert np.array_equal(a[keep], b[keep])
             # continue both from the oracle's state rounded to the working precision
             sim.from_natural(0, [np.float32(a) if prec == "f32" else a for a in ref])
     return n_checked, n_margin
@@ -250,6 +259,9 @@ def test_measuring_does_not_change_the_chain(M, case, prec):
     import torch
 
     kind, L, tile = MEASURE_CASES[case]
+    if prec == "f64" and tile and tile[0] == 5 and tile[2] == 4:
+        pytest.skip("FP64 band-pair tiles take 2-row bands only (refusal tested with the pair "
+                    "kernel)")
     rep = M.Replica(kind=kind, L=L, K=0.1, T=1.3, e=(0.0, 0.6, 0.8))
     sims = []
     # the persistent kernel has no instantiation for strips of 1 or 8 rows or
@@ -305,6 +317,13 @@ def test_pair_kernel_is_bitwise(M, prec):
     for tile in PAIR_TILES:
         scratch = torch.empty(16 << 20, dtype=torch.uint8, device="cuda")
         one = M.Simulation(reps, precision=prec, seed=9, scratch=scratch)
+        if prec == "f64" and tile[0] == 5 and tile[2] == 4:
+            # FP64 band-pair tiles take 2-row bands only
+            with pytest.raises(M.MCError) as ei:
+                one.set_tile(tile[1], tile[2], tile[3], kernel=tile[0])
+            assert ei.value.status == -2
+            one.close()
+            continue
         one.set_tile(tile[1], tile[2], tile[3], kernel=tile[0])
         one.sweep(2)
         one.sweep(4, measure=True)
@@ -1056,3 +1075,128 @@ def test_schedule_measure_every(M, persistent):
     for r in range(2):
         for x, y in zip(natural(a, r), natural(b, r)):
             assert np.array_equal(x, y)
+
+
+def test_sc_sphere_kernels(M):
+    """A simple-cubic lattice cut to a sphere runs on the tile kernel (and the
+    LDS kernel for small lattices), which never updates an unoccupied site;
+    the other simple-cubic kernels are refused.  The tile kernel's FP64 chain
+    equals the oracle's, and the unoccupied sites stay zero."""
+    rep = M.Replica(kind="sc", L=(40, 38, 34), periodic_mask=0, sphere_radius=15.2, J=1.0,
+                    K=0.1, e=(0.0, 0.0, 1.0), T=1.3)
+    sim = M.Simulation([rep], precision="f64", seed=19)
+    assert sim.get_tile()[0] == 0
+    for kernel, tx, ty in ((1, 64, 2), (2, 256, 2), (4, 64, 2), (5, 256, 2)):
+        with pytest.raises(M.MCError) as ei:
+            sim.set_tile(tx, ty, 4, kernel=kernel)
+        assert ei.value.status == -2
+    sim.set_tile(16, 8, 5, kernel=0)
+    lat = oracle_lattice(rep)
+    p = oracle_params(rep, 19)
+    s = O.init(lat, p)
+    ref = O.run(lat, p, 0, 12, s)
+    for t in range(12):
+        sim.sweep(1, measure=True)
+        o = sim.observables()[0]
+        assert o["n_accepted"] == ref[t, 5]
+        assert np.max(np.abs(o["M"] - ref[t, 0:3] / lat.n_occ)) <= 1e-12
+    occ = lat.tables()[0]
+    for a, b in zip(natural(sim), s):
+        assert np.max(np.abs(a - b)) <= 1e-12
+        assert np.all(a[~occ] == 0.0)
+
+
+@pytest.mark.parametrize("case", range(len(SMALL_CASES)))
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_measure_buffers_matches_oracle(M, case, prec):
+    """mc_measure_buffers (no handle; caller workspace) on a simulation's own
+    spin buffers after a few sweeps: magnetisation sums and both energy terms
+    equal the oracle's from-scratch observables of the same state (every
+    product in FP64, so only the summation order differs), and equal
+    mc_measure_state's."""
+    rep = M.Replica(**SMALL_CASES[case], replica_id=4)
+    sim = M.Simulation([rep], precision=prec, seed=23)
+    sim.sweep(3)
+    sim.synchronize()
+    got = M.measure_buffers(rep, prec, *sim.spins[0])
+    lat = oracle_lattice(rep)
+    ob = O.observables(lat, oracle_params(rep, 23), natural(sim))
+    assert got["n_sites"] == lat.n_occ
+    assert np.max(np.abs(got["M"] - ob["M"])) <= 1e-12 * lat.n_occ
+    for k in ("E_exch", "E_anis"):
+        assert abs(got[k] - ob[k]) <= 1e-12 * max(1.0, abs(ob["E"])), (k, got[k], ob[k])
+    st = sim.measure_state()[0]
+    assert abs(st["E"] - got["E"]) <= 1e-12 * max(1.0, abs(ob["E"]))
+
+
+def test_measure_buffers_errors(M):
+    import torch
+
+    rep = M.Replica(kind="sc", L=(8, 8, 8))
+    t = [torch.zeros(512, dtype=torch.float32, device="cuda") for _ in range(3)]
+    with pytest.raises(M.MCError) as ei:
+        M.measure_buffers(rep, "f32", *t, workspace=torch.empty(1024, dtype=torch.uint8,
+                                                                device="cuda"))
+    assert ei.value.status == -3
+    short = [x[:100] for x in t]
+    with pytest.raises(M.MCError) as ei:
+        M.measure_buffers(rep, "f32", *short)
+    assert ei.value.status == -3
+    with pytest.raises(M.MCError) as ei:
+        M.measure_buffers(M.Replica(kind="sc", L=(8, 7, 8)), "f32", *t)
+    assert ei.value.status == -2
+
+
+LBAND_TILES = [(8, 256, 1, 3), (8, 256, 2, 5), (8, 256, 4, 2), (8, 256, 7, 34), (8, 256, 3, 1)]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_lds_band_kernel_is_bitwise(M, prec):
+    """Rows staged through LDS by asynchronous copies (kernel 8): spins and
+    accepted counts equal the tile kernel's bitwise, over periodic and open
+    faces, ragged row tiles and several plane chunks; rows that are not a
+    multiple of 16 bytes are refused."""
+    import torch
+
+    base = dict(kind="sc", J=1.0, K=0.1, e=(0.0, 0.6, 0.8))
+    reps = [M.Replica(L=(24, 24, 24), T=1.0, replica_id=0, periodic_mask=7, **base),
+            M.Replica(L=(40, 38, 34), T=1.5, replica_id=1, periodic_mask=7, **base),
+            M.Replica(L=(48, 14, 12), T=0.7, replica_id=2, periodic_mask=7, **base),
+            M.Replica(L=(32, 9, 7), T=1.2, replica_id=3, periodic_mask=1, **base),
+            M.Replica(L=(64, 4, 6), T=1.3, replica_id=4, periodic_mask=6, **base)]
+    ref = M.Simulation(reps, precision=prec, seed=13,
+                       scratch=torch.empty(16 << 20, dtype=torch.uint8, device="cuda"))
+    ref.set_tile(16, 16, 2, kernel=0)
+    ref.sweep(3)
+    ref.sweep(3, measure=True)
+    obs_r = ref.observables()
+    for tile in LBAND_TILES:
+        one = M.Simulation(reps, precision=prec, seed=13,
+                           scratch=torch.empty(16 << 20, dtype=torch.uint8, device="cuda"))
+        one.set_tile(tile[1], tile[2], tile[3], kernel=tile[0])
+        one.sweep(3)
+        one.sweep(3, measure=True)
+        o = one.observables()
+        for r in range(len(reps)):
+            for a, b in zip(natural(one, r), natural(ref, r)):
+                assert np.array_equal(a, b), (r, tile)
+            assert o[r]["n_accepted"] == obs_r[r]["n_accepted"], (r, tile)
+            assert abs(o[r]["E"] - obs_r[r]["E"]) <= 1e-9 * abs(o[r]["E"])
+        one.close()
+    # debug pass of the same kernel: per-site dH and decisions as the tile kernel's
+    a = M.Simulation(reps[:2], precision=prec, seed=14,
+                     scratch=torch.empty(16 << 20, dtype=torch.uint8, device="cuda"))
+    b = M.Simulation(reps[:2], precision=prec, seed=14,
+                     scratch=torch.empty(16 << 20, dtype=torch.uint8, device="cuda"))
+    a.set_tile(16, 16, 2, kernel=0)
+    b.set_tile(256, 2, 3, kernel=8)
+    for c in (0, 1):
+        da, aa = a.debug_pass(c)
+        db, ab = b.debug_pass(c)
+        for r in range(2):
+            assert torch.equal(aa[r], ab[r])
+            assert torch.equal(torch.nan_to_num(da[r], nan=7.0), torch.nan_to_num(db[r], nan=7.0))
+    odd = M.Simulation([M.Replica(kind="sc", L=(18, 8, 8))], precision=prec)
+    with pytest.raises(M.MCError) as ei:
+        odd.set_tile(256, 2, 3, kernel=8)
+    assert ei.value.status == -2
