@@ -237,7 +237,8 @@ def test_sc_1024_beyond_4gib(M):
     assert fused["n_sites"] == 1024**3
     assert np.max(np.abs(fused["M"] - direct["M"])) <= 1e-12
     assert abs(fused["E"] - direct["E"]) <= 1e-9 * abs(direct["E"])
-    b = M.Simulation([rep], precision="f32", seed=10)
+    b = M.Simulation([rep], precision="f32", seed=10,
+                     scratch=torch.empty(64 << 20, dtype=torch.uint8, device="cuda"))
     b.set_tile(32, 8, 8, kernel=0)
     b.sweep(3)
     for x, y in zip(a.to_natural(0), b.to_natural(0)):
