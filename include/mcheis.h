@@ -223,6 +223,19 @@ mc_status mc_measure_buffers(const mc_replica_desc *d, mc_precision prec,
                              const mc_spin_buffers *bufs, void *workspace,
                              uint64_t workspace_bytes, double *record_dev, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): mc_measure_buffers
+ * with its workspace replaced by a static device array of the library
+ * (64 KiB per GPU, held until the process ends); same arguments otherwise,
+ * same results bit for bit.  Calls no allocating routine.  Every call on one
+ * GPU shares that GPU's array: calls that overlap on one GPU (other streams,
+ * other host threads) race and must be ordered by the caller.  No state
+ * carries over between calls (each call writes every partial it reads).
+ * MC_E_DEVICE if the array's device address cannot be found. */
+mc_status mc_measure_buffers_static(const mc_replica_desc *d, mc_precision prec,
+                                    const mc_spin_buffers *bufs, double *record_dev,
+                                    void *hip_stream);
+
 /* Run a temperature schedule: at each temperature thermalise, then average
  * (the paper's Monte Carlo and simulation-setup paragraphs: equilibration
  * sweeps followed by measurement sweeps per temperature).  Sweeps are replayed

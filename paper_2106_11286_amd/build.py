@@ -20,7 +20,9 @@ KERNEL_SOURCES = ["kernels_pass.hip", "kernels_basis_pair.hip", "kernels_persist
                   "kernels_measure.hip"]
 # host runtime behind the C ABI
 HOST_SOURCES = ["abi.cpp", "abi_tune.cpp", "abi_stats.cpp", "abi_extensions.cpp"]
-SOURCES = KERNEL_SOURCES + HOST_SOURCES
+# host entry point that shares its translation unit with a static device array
+MIXED_SOURCES = ["abi_noalloc.hip"]
+SOURCES = KERNEL_SOURCES + HOST_SOURCES + MIXED_SOURCES
 ARCH = os.environ.get("MCHEIS_ARCH", "gfx950")
 
 

@@ -130,6 +130,9 @@ _SIGNATURES = {
     "mc_measure_buffers": (ctypes.c_int, [ctypes.POINTER(ReplicaDesc), ctypes.c_int,
                                           ctypes.POINTER(SpinBuffers), ctypes.c_void_p,
                                           ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p]),
+    "mc_measure_buffers_static": (ctypes.c_int, [ctypes.POINTER(ReplicaDesc), ctypes.c_int,
+                                                 ctypes.POINTER(SpinBuffers), ctypes.c_void_p,
+                                                 ctypes.c_void_p]),
     "mc_tune_device_key": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_int32, ctypes.c_int32,
                                           ctypes.c_char_p, ctypes.c_uint64]),
     "mc_synchronize": (ctypes.c_int, [ctypes.c_void_p]),
@@ -254,6 +257,20 @@ def measure_buffers(rep: Replica, precision: str, sx, sy, sz, workspace=None) ->
     _check("mc_measure_buffers", LIB.mc_measure_buffers(
         ctypes.byref(d), prec, ctypes.byref(b), workspace.data_ptr(), workspace.numel(),
         rec.data_ptr(), stream))
+    return _record_dict(rec.cpu().tolist())
+
+
+def measure_buffers_static(rep: Replica, precision: str, sx, sy, sz, record=None) -> dict:
+    """``mc_measure_buffers_static``: as ``measure_buffers`` with the library's
+    static scratch (no workspace).  ``record`` (8 doubles on the device) may
+    be passed in; synchronises and returns the same dict."""
+    prec = {"f32": F32, "f64": F64}[precision]
+    d = rep.desc()
+    b = SpinBuffers(sx.data_ptr(), sy.data_ptr(), sz.data_ptr(), int(sx.numel()))
+    rec = torch.zeros(8, dtype=torch.float64, device=sx.device) if record is None else record
+    stream = torch.cuda.current_stream(sx.device).cuda_stream
+    _check("mc_measure_buffers_static", LIB.mc_measure_buffers_static(
+        ctypes.byref(d), prec, ctypes.byref(b), rec.data_ptr(), stream))
     return _record_dict(rec.cpu().tolist())
 
 
