@@ -24,7 +24,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0           # MI355X HBM3E
-KERNEL_NAMES = ["tile", "strip", "band", "lds", "pair", "pband", "bstrip", "bpair", "lband"]  # mc_set_tile ids
+KERNEL_NAMES = ["tile", "strip", "band", "lds", "pair", "pband", "bstrip", "bpair", "lband",
+                "fused"]  # mc_set_tile ids
 BYTES_PER_UPDATE = {"f32": 36, "f64": 72}  # two-pass colour-packed: read own + other, write own
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sc_pass_f32_L464_traffic.json")
 
@@ -117,6 +118,49 @@ def time_precision(M, W, prec, steps, warmup, tile=None):
     del sim
     torch.cuda.empty_cache()
     log(f"[bench] {prec}: {res['value']:.2f} updates/ns, pass {pass_ms:.4f} ms")
+    return res
+
+
+FUSED_TILES = ((9, 256, 2, 16), (9, 256, 4, 8), (9, 256, 4, 16))
+
+
+def time_fused(M, W, steps, warmup):
+    """The fused sweep kernel (9) on the same lattice, FP32, measured sweeps:
+    the fastest of a few tile shapes (20 trial sweeps each), then `steps`
+    sweeps timed with HIP events around each launch (one per sweep).  Its
+    algorithmic bytes are 24 per update (each spin read and written once)."""
+    import torch
+
+    w = W.C5_SC464_ROOFLINE
+    rep = M.Replica(**W.replica_fields(w))
+    sim = M.Simulation([rep], precision="f32", seed=w["seed"],
+                       scratch=torch.empty(64 << 20, dtype=torch.uint8, device="cuda"))
+    sim.enable_fused()
+    n = sim.n_occ[0]
+    best = None
+    for t in FUSED_TILES:
+        sim.set_tile(t[1], t[2], t[3], kernel=t[0])
+        launch_ms, _ = sim.sweep_timed(20, measure=True)
+        if best is None or launch_ms < best[0]:
+            best = (launch_ms, t)
+    t = best[1]
+    sim.set_tile(t[1], t[2], t[3], kernel=t[0])
+    if warmup:
+        sim.sweep(warmup, measure=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    launch_ms, total_ms = sim.sweep_timed(steps, measure=True)
+    wall = time.perf_counter() - t0
+    res = {"tile": {"kernel": KERNEL_NAMES[t[0]], "tx": t[1], "ty": t[2], "zc": t[3]},
+           "value": n * steps / (wall * 1e9), "ms_per_step": wall * 1e3 / steps,
+           "launch_ms": launch_ms,
+           "algorithmic_bytes_per_launch": 24.0 * n,
+           "achieved_GBps": 24.0 * n / (launch_ms * 1e-3) / 1e9,
+           "frac": 24.0 * n / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS}
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    log(f"[bench] fused f32: {res['value']:.2f} updates/ns, launch {launch_ms:.4f} ms, tile {t}")
     return res
 
 
@@ -324,8 +368,9 @@ def run_c2(M, W, init="random"):
 def run_c3(M, W, sweeps):
     """64 sc replicas (L in {32, 48, 64, 96}, T 0.8 .. 2.0), FP32: the sweeps as
     graph-replayed per-pass launches, and as one persistent launch per call
-    with one work queue per XCD and with a single queue.  Each mode runs on
-    its own autotuned tile."""
+    with one work queue per XCD and with a single queue, each mode on its own
+    autotuned tile; then in the launch mode the autotuner picks together with
+    the tile."""
     import torch
 
     w = W.C3_BATCHED
@@ -346,6 +391,16 @@ def run_c3(M, W, sweeps):
         if queues:
             res[mode]["queues"] = sim.persistent_queues()
         log(f"[bench] c3 {mode}: {res[mode]['updates_per_ns']:.1f} updates/ns, tile {tile}")
+    # the autotuner choosing the launch mode with the tile (per-XCD queues for
+    # the persistent candidates), then sweeps in the chosen mode
+    sim.set_persistent_mode("auto")
+    tile = sim.autotune(trial_sweeps=3, measure=True, tune_launch=True)
+    sim.sweep(20, measure=True, tuned=True)
+    _, dt = _timed(lambda: sim.sweep(sweeps, measure=True, tuned=True))
+    res["tuned_launch"] = {"s": dt, "updates_per_ns": N * sweeps / dt / 1e9, "tile": list(tile),
+                           "launch": sim.tuned_launch()}
+    log(f"[bench] c3 tuned_launch: {res['tuned_launch']['updates_per_ns']:.1f} updates/ns, "
+        f"tile {tile}, {sim.tuned_launch()}")
     return res
 
 
@@ -370,7 +425,7 @@ def run_c4(M, W, sweeps):
 
 
 def run_big(M, L=1000, sweeps=20):
-    """One sc L^3 lattice of 10^9 spins (L = 1000, FP32, 12 GB): autotuned
+    """One sc L^3 lattice of ~10^9 spins (L = 1000, FP32, 12 GB; or L as given): autotuned
     throughput, and the fused FP64 observables of the last timed sweep against
     a recomputation of the same state over every bond."""
     import torch
@@ -388,7 +443,7 @@ def run_big(M, L=1000, sweeps=20):
     full = sim.measure_state()[0]
     dE = abs(fused["E"] - full["E"]) / abs(full["E"])
     dM = float(max(abs(a - b) for a, b in zip(fused["M"], full["M"])))
-    return {"workload": f"sc-L{L}-1e9-spins", "spins": N, "bytes_state": 12 * N,
+    return {"workload": f"sc-L{L}-{N / 1e9:.2g}e9-spins", "spins": N, "bytes_state": 12 * N,
             "default_tile": list(default), "tile": list(tile), "sweeps": sweeps,
             "updates_per_ns": N * sweeps / (total_ms * 1e6), "pass_ms": pass_ms,
             "algorithmic_GBps": 36 * N / 2 / (pass_ms * 1e-3) / 1e9,
@@ -628,6 +683,8 @@ def main():
     ap.add_argument("--cpu-sweeps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-fused", action="store_true",
+                    help="skip the fused sweep kernel's line beside the two-pass one")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--workload", default="c5",
                     choices=["c5", "c1", "c2", "c3", "c4", "f1", "big", "bcc", "fcc", "exchange",
@@ -638,6 +695,9 @@ def main():
     ap.add_argument("--f1-sweeps", type=int, default=10000,
                     help="thermalisation and averaging sweeps each")
     ap.add_argument("--f1-K", type=float, default=0.01, help="anisotropy of the f1 lattices")
+    ap.add_argument("--big-L", type=int, default=1000,
+                    help="edge of the big workload's lattice (1024: component arrays of 4 GiB, "
+                         "beyond the 32-bit buffer offsets of the pair kernels)")
     ap.add_argument("--init", default="random", choices=["random", "aligned"],
                     help="initial state of the c2 ladder")
     ap.add_argument("--tile", default=None,
@@ -668,7 +728,7 @@ def main():
         elif args.workload == "c2":
             out = run_c2(M, W, args.init)
         elif args.workload == "big":
-            out = run_big(M)
+            out = run_big(M, L=args.big_L)
         elif args.workload == "bcc":
             out = run_bcc(M, W, W.BCC_368_1E8["sweeps"])
         elif args.workload == "fcc":
@@ -691,6 +751,9 @@ def main():
     r32 = time_precision(M, W, "f32", args.steps, args.warmup, tile)
     r64 = None if args.no_fp64 else time_precision(M, W, "f64", min(args.steps, args.fp64_steps),
                                                   min(args.warmup, 5))
+    fused = None if args.no_fused else time_fused(M, W, min(args.steps, 200), min(args.warmup, 5))
+    if fused:
+        fused["vs_two_pass"] = fused["value"] / r32["value"]
     cpu = None
     if rank == 0 and not args.no_cpu_baseline:
         cpu = cpu_baseline(W, args.cpu_sweeps)
@@ -744,6 +807,8 @@ def main():
         "fp32": r32,
         "fp64": r64,
         "fp32_over_fp64": (r32["value"] / r64["value"]) if r64 else None,
+        # both colours in one launch per sweep (24 B per update), same lattice
+        "fused": fused,
     }
     if rank == 0:
         print(json.dumps(out), flush=True)

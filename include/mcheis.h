@@ -55,6 +55,11 @@ typedef enum { MC_INIT_RANDOM = 0, MC_INIT_ALIGNED = 1, MC_INIT_USER = 2 } mc_in
 
 /* mc_sweep / mc_schedule flags */
 #define MC_MEASURE 1u    /* reduce observables on every sweep of this call            */
+#define MC_TUNED_LAUNCH 4u /* launch as mc_autotune with this flag chose: per-pass   */
+                           /* launches replayed as HIP graphs, or one persistent     */
+                           /* launch (per-pass before any such tuning and after a    */
+                           /* later mc_set_tile); not with MC_PERSISTENT.  Results   */
+                           /* are bitwise the same in either mode.                   */
 #define MC_PERSISTENT 2u /* run the sweeps as one persistent launch: work units       */
                          /* (sweep, colour, tile) are claimed in order by the resident */
                          /* workgroups, each replica advancing as soon as its previous */
@@ -124,7 +129,7 @@ typedef struct {
     int32_t n_T;
     const double *T; /* host array [n_T][n_reps] */
     uint32_t n_equil, n_meas, measure_every;
-    uint32_t flags;  /* 0 or MC_PERSISTENT */
+    uint32_t flags;  /* 0, MC_PERSISTENT or MC_TUNED_LAUNCH */
 } mc_schedule;
 
 /* Summary statistics of one replica's series (equilibrium averages over the
@@ -183,8 +188,9 @@ mc_status mc_sweep(mc_sim *h, uint32_t n_sweeps, uint32_t flags);
 
 /* mc_sweep with HIP events recorded on the handle's stream around every
  * colour-pass launch; synchronises and returns the mean duration of one pass
- * launch and the total time of the call (milliseconds).  For measuring the
- * kernels in place; results are identical to mc_sweep. */
+ * launch (with the fused sweep kernel 9: of its one launch per sweep) and the
+ * total time of the call (milliseconds).  For measuring the kernels in place;
+ * results are identical to mc_sweep. */
 mc_status mc_sweep_timed(mc_sim *h, uint32_t n_sweeps, uint32_t flags, double *pass_ms_avg,
                          double *total_ms);
 
@@ -313,13 +319,39 @@ mc_status mc_set_sweep(mc_sim *h, uint64_t t);
  *    plane's rows (other colour y0-1 .. y0+ty, own colour y0 .. y0+ty-1) are
  *    copied into LDS by asynchronous global-to-LDS loads one plane ahead of
  *    the arithmetic (double buffered, at most 60 KiB per workgroup), and the
- *    neighbour field is read from LDS.  No persistent sweeps.
+ *    neighbour field is read from LDS.  No persistent sweeps;
+ *  kernel 9 (sc only, even packed rows, every replica given a second buffer
+ *    set by mc_set_second_buffers, component arrays below 4 GiB): the fused
+ *    sweep -- both colours in one launch per sweep, reading the current
+ *    state once and writing the next one into the other buffer set (24 bytes
+ *    per update in FP32).  Tiles of ty whole rows (1 .. 64) walked over zc
+ *    planes by tx = 256 threads; the new colour-0 spins of rows y0-1 .. y0+ty
+ *    are computed by the tile itself (also those outside it) and exchanged
+ *    through 9 (ty+2) Lx/2 spin values of LDS (above the device's limit:
+ *    MC_E_UNSUPPORTED).  After each sweep the two buffer sets trade places
+ *    (mc_get_state_buffers names the current one).  No persistent sweeps and
+ *    no mc_debug_pass (MC_E_UNSUPPORTED).
  * The spins do not depend on the choice (only the FP64 summation order of the
  * observables does).  A shape whose work list does not fit the handle's
  * scratch gives MC_E_BUFFER.  Choosing any kernel but 3 discards the record of the
  * last measured sweep.  Synchronises; a deferred error of an earlier
  * persistent launch (watchdog, undrained queue) is returned first. */
 mc_status mc_set_tile(mc_sim *h, int32_t kernel, int32_t tx, int32_t ty, int32_t zc);
+
+/* Second buffer set of every replica (bufs[n_reps], same layout and
+ * capacity as the state's, device memory, 16-byte aligned, not overlapping
+ * the current state), used by the fused sweep kernel (9): a fused sweep reads
+ * the current set and writes the other, after which the two trade places.
+ * The caller owns the buffers and keeps them alive while the handle may run
+ * kernel 9.  Sets the buffer set that does not hold the current state; the
+ * state stays where it is.  MC_E_BUFFER for missing, small, misaligned or
+ * overlapping buffers.  Synchronises. */
+mc_status mc_set_second_buffers(mc_sim *h, const mc_spin_buffers *bufs);
+
+/* The buffer set that holds a replica's current state: the one given to
+ * mc_init_lattice, or (after an odd number of fused sweeps) the second set.
+ * Host only; reflects every sweep enqueued so far. */
+mc_status mc_get_state_buffers(const mc_sim *h, int32_t replica, mc_spin_buffers *out);
 mc_status mc_get_tile(const mc_sim *h, int32_t *kernel, int32_t *tx, int32_t *ty, int32_t *zc,
                       uint64_t *n_items);
 
@@ -335,6 +367,13 @@ mc_status mc_get_tile(const mc_sim *h, int32_t *kernel, int32_t *tx, int32_t *ty
  * be NULL).  Synchronises. */
 mc_status mc_autotune(mc_sim *h, uint32_t trial_sweeps, uint32_t flags, const char *cache_path,
                       int32_t *kernel, int32_t *tx, int32_t *ty, int32_t *zc);
+
+/* The launch mode the autotuner chose with MC_TUNED_LAUNCH (there it times
+ * every candidate tile both as graph-replayed per-pass launches and, where the
+ * tile has a persistent kernel, as one persistent launch, and keeps the
+ * fastest pair): *persistent = 1 for the persistent launch, 0 otherwise
+ * (also before any such tuning). */
+mc_status mc_get_tuned_launch(const mc_sim *h, int32_t *persistent);
 
 /* The device part of the autotuner's cache key: architecture name (the
  * device's gcnArchName), compute units and XCDs (both change with the

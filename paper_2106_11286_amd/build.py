@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libmcheis.so")
 # device code: one translation unit per launch family (compiled in parallel)
 KERNEL_SOURCES = ["kernels_pass.hip", "kernels_basis_pair.hip", "kernels_persistent.hip",
                   "kernels_lds.hip", "kernels_util.hip", "kernels_block.hip",
-                  "kernels_measure.hip"]
+                  "kernels_measure.hip", "kernels_fused.hip"]
 # host runtime behind the C ABI
 HOST_SOURCES = ["abi.cpp", "abi_tune.cpp", "abi_stats.cpp", "abi_extensions.cpp"]
 # host entry point that shares its translation unit with a static device array

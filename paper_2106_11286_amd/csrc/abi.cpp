@@ -124,7 +124,8 @@ uint64_t xy_tiles(const mc_replica_desc &d, const Tile &t)
         const uint64_t F = (uint64_t)((d.Ly + t.ty - 1) / t.ty) * cols;
         return (F + t.tx - 1) / t.tx;
     }
-    if (t.kernel == KERNEL_LBAND) return (uint64_t)((d.Ly + t.ty - 1) / t.ty);
+    if (t.kernel == KERNEL_LBAND || t.kernel == KERNEL_FUSED)
+        return (uint64_t)((d.Ly + t.ty - 1) / t.ty);
     const int wx = t.kernel == KERNEL_PAIR ? 2 * t.tx : t.tx; // packed columns per tile
     return (uint64_t)((row_len(d) + wx - 1) / wx) * ((d.Ly + t.ty - 1) / t.ty);
 }
@@ -257,6 +258,13 @@ mc_status check_tile(const Tile &t, int kind, uint64_t max_component_bytes, bool
         if (t.ty < 1 || t.ty > 64)
             return fail(MC_E_ARG, "LDS-staged band tile: ty (rows per tile) must be in [1, 64]");
         (void)max_component_bytes;
+    } else if (t.kernel == KERNEL_FUSED) {
+        if (kind != MC_SC) return fail(MC_E_ARG, "the fused sweep kernel is for simple cubic lattices");
+        if (max_component_bytes > 0xFFFFFFFFull)
+            return fail(MC_E_UNSUPPORTED, "fused sweep kernel: a spin component array exceeds 4 GiB");
+        if (t.tx != 256) return fail(MC_E_ARG, "fused sweep tile: tx must be 256 (got %d)", t.tx);
+        if (t.ty < 1 || t.ty > 64)
+            return fail(MC_E_ARG, "fused sweep tile: ty (rows per tile) must be in [1, 64]");
     } else if (t.kernel == KERNEL_TILE) {
         if (t.tx < 1 || t.ty < 1 || t.tx * t.ty > 256)
             return fail(MC_E_ARG, "tile %d x %d invalid (need >= 1 and tx*ty <= 256)", t.tx, t.ty);
@@ -308,7 +316,7 @@ void make_work(const mc_replica_desc *reps, int n, const Tile &t, std::vector<Wo
             end[r] = (uint32_t)work.size();
             continue;
         }
-        if (t.kernel == KERNEL_LBAND) { // whole rows: tiles of ty rows
+        if (t.kernel == KERNEL_LBAND || t.kernel == KERNEL_FUSED) { // whole rows: tiles of ty rows
             for (int z0 = 0; z0 < d.Lz; z0 += t.zc)
                 for (int y0 = 0; y0 < d.Ly; y0 += t.ty) work.push_back(WorkItem{(uint32_t)r, 0, y0, z0});
             end[r] = (uint32_t)work.size();
@@ -430,6 +438,11 @@ PassLaunch pass_args(mc_sim *h, uint32_t item_base, uint32_t n_blocks, uint32_t 
         p.lds_bytes = lband_lds_bytes(p.tile.ty, w, esz);
         p.lds_positions = (p.tile.ty * (w / 2) + p.tile.tx - 1) / p.tile.tx;
     }
+    if (p.tile.kernel == KERNEL_FUSED) {
+        int w = 1;
+        for (const auto &d : h->desc) w = std::max(w, row_len(d));
+        p.lds_bytes = fused_lds_bytes(p.tile.ty, w, h->prec == MC_F64 ? 8 : 4);
+    }
     return p;
 }
 
@@ -486,9 +499,16 @@ mc_status enqueue_sweeps(mc_sim *h, uint32_t n, bool measure, uint32_t slot0)
     if (h->tile.kernel == KERNEL_LDS) return enqueue_lds(h, n, measure, slot0);
     const bool f64 = h->prec == MC_F64;
     const uint32_t n_items = (uint32_t)h->work.size();
+    const bool fused = h->tile.kernel == KERNEL_FUSED;
     for (uint32_t i = 0; i < n; ++i) {
         const PassLaunch p = pass_args(h, 0, n_items, i);
-        for (int c = 0; c < h->n_colours; ++c) HIP_TRY(launch_pass(h->kind, f64, c, measure, 0, p, h->stream));
+        if (fused) {
+            HIP_TRY(launch_fused(f64, measure, p, h->stream));
+            HIP_TRY(launch_swap_state(h->reps_dev, (uint32_t)h->n_reps, h->stream));
+        } else {
+            for (int c = 0; c < h->n_colours; ++c)
+                HIP_TRY(launch_pass(h->kind, f64, c, measure, 0, p, h->stream));
+        }
         if (measure) {
             const uint32_t slot = (slot0 + i) % kRing;
             HIP_TRY(launch_finalize(h->reps_dev, h->n_reps, h->n_colours, h->partials, n_items,
@@ -581,7 +601,7 @@ mc_status plan_queues(mc_sim *h)
 // Tile shapes the persistent kernel is instantiated for.
 bool persistent_supported(const Tile &t)
 {
-    if (t.kernel == KERNEL_LBAND) return false;
+    if (t.kernel == KERNEL_LBAND || t.kernel == KERNEL_FUSED) return false;
     if (t.kernel == KERNEL_PAIR) return t.ty == 1 || t.ty == 2;
     if (t.kernel == KERNEL_PBAND) return t.ty == 2;
     if (t.kernel == KERNEL_BPAIR) return t.ty == 1 || t.ty == 2;
@@ -735,12 +755,27 @@ mc_status upload_reps(mc_sim *h)
 }
 
 
+// The host copies of the replica descriptors follow the device ones: after an
+// odd number of fused sweeps the two buffer sets have traded places.
+void note_sweeps(mc_sim *h, uint64_t n)
+{
+    if (h->tile.kernel != KERNEL_FUSED || !(n & 1u)) return;
+    for (RepDev &R : h->reps) {
+        std::swap(R.sx, R.ax);
+        std::swap(R.sy, R.ay);
+        std::swap(R.sz, R.az);
+    }
+}
+
 mc_status run_chunk(mc_sim *h, uint32_t n, bool measure, uint32_t slot0, bool persistent)
 {
     if (n == 0) return MC_OK;
-    if (!h->stream)
-        return persistent ? enqueue_persistent(h, n, measure, slot0)
-                          : enqueue_sweeps(h, n, measure, slot0);
+    if (!h->stream) {
+        const mc_status s = persistent ? enqueue_persistent(h, n, measure, slot0)
+                                       : enqueue_sweeps(h, n, measure, slot0);
+        if (s == MC_OK) note_sweeps(h, n);
+        return s;
+    }
     // replay a captured graph of n sweeps; graphs bake the ring slots, so a
     // measured graph is keyed by its first slot too (callers use slot 0)
     const std::pair<uint32_t, uint32_t> key(n | (persistent ? 0x80000000u : 0u),
@@ -764,6 +799,7 @@ mc_status run_chunk(mc_sim *h, uint32_t n, bool measure, uint32_t slot0, bool pe
         it = h->graphs.emplace(key, ex).first;
     }
     HIP_TRY(hipGraphLaunch(it->second, h->stream));
+    note_sweeps(h, n);
     // the LDS kernel keeps no counters that a watchdog could trip
     if (persistent && h->tile.kernel != KERNEL_LDS) h->persist_used = true;
     return MC_OK;
@@ -1004,7 +1040,11 @@ mc_status mc_init_lattice(const mc_replica_desc *reps, int32_t n_reps, mc_precis
 mc_status mc_sweep(mc_sim *h, uint32_t n_sweeps, uint32_t flags)
 {
     if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
-    if (flags & ~(MC_MEASURE | MC_PERSISTENT)) return fail(MC_E_ARG, "unknown flags 0x%x", flags);
+    if (flags & ~(MC_MEASURE | MC_PERSISTENT | MC_TUNED_LAUNCH))
+        return fail(MC_E_ARG, "unknown flags 0x%x", flags);
+    if ((flags & MC_PERSISTENT) && (flags & MC_TUNED_LAUNCH))
+        return fail(MC_E_ARG, "MC_PERSISTENT and MC_TUNED_LAUNCH exclude each other");
+    if ((flags & MC_TUNED_LAUNCH) && h->tuned_persistent) flags |= MC_PERSISTENT;
     if (n_sweeps == 0) return MC_OK;
     if (h->t + n_sweeps > 0xFFFFFFFFull) return fail(MC_E_STATE, "sweep counter would exceed 2^32-1");
     const bool measure = flags & MC_MEASURE;
@@ -1012,6 +1052,7 @@ mc_status mc_sweep(mc_sim *h, uint32_t n_sweeps, uint32_t flags)
     mc_status s = (flags & MC_PERSISTENT) ? enqueue_persistent(h, n_sweeps, measure, slot0)
                                           : enqueue_sweeps(h, n_sweeps, measure, slot0);
     if (s != MC_OK) return s;
+    note_sweeps(h, n_sweeps);
     h->t += n_sweeps;
     if (measure) {
         h->n_measured += n_sweeps;
@@ -1057,7 +1098,9 @@ mc_status mc_sweep_timed(mc_sim *h, uint32_t n_sweeps, uint32_t flags, double *p
     }
     const bool f64 = h->prec == MC_F64;
     const uint32_t n_items = (uint32_t)h->work.size();
-    const uint32_t n_pass = n_sweeps * (uint32_t)h->n_colours;
+    const bool fused = h->tile.kernel == KERNEL_FUSED; // one launch per sweep
+    const uint32_t per_sweep = fused ? 1u : (uint32_t)h->n_colours;
+    const uint32_t n_pass = n_sweeps * per_sweep;
     std::vector<hipEvent_t> ev(2 * (size_t)n_pass + 2, nullptr);
     for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
     auto release = [&]() {
@@ -1068,11 +1111,15 @@ mc_status mc_sweep_timed(mc_sim *h, uint32_t n_sweeps, uint32_t flags, double *p
     hipError_t err = hipEventRecord(ev[2 * n_pass], h->stream);
     for (uint32_t i = 0; i < n_sweeps && err == hipSuccess; ++i) {
         const PassLaunch p = pass_args(h, 0, n_items, i);
-        for (int c = 0; c < h->n_colours && err == hipSuccess; ++c) {
-            const uint32_t k = i * h->n_colours + c;
+        for (uint32_t c = 0; c < per_sweep && err == hipSuccess; ++c) {
+            const uint32_t k = i * per_sweep + c;
             err = hipEventRecord(ev[2 * k], h->stream);
-            if (err == hipSuccess) err = launch_pass(h->kind, f64, c, measure, 0, p, h->stream);
+            if (err == hipSuccess)
+                err = fused ? launch_fused(f64, measure, p, h->stream)
+                            : launch_pass(h->kind, f64, (int)c, measure, 0, p, h->stream);
             if (err == hipSuccess) err = hipEventRecord(ev[2 * k + 1], h->stream);
+            if (err == hipSuccess && fused)
+                err = launch_swap_state(h->reps_dev, (uint32_t)h->n_reps, h->stream);
         }
         if (measure && err == hipSuccess)
             err = launch_finalize(h->reps_dev, h->n_reps, h->n_colours, h->partials, n_items,
@@ -1098,6 +1145,7 @@ mc_status mc_sweep_timed(mc_sim *h, uint32_t n_sweeps, uint32_t flags, double *p
     release();
     *pass_ms_avg = sum / n_pass;
     *total_ms = tot;
+    note_sweeps(h, n_sweeps);
     h->t += n_sweeps;
     if (measure) {
         h->n_measured += n_sweeps;
@@ -1201,8 +1249,12 @@ mc_status mc_run_schedule(mc_sim *h, const mc_schedule *s, mc_obs *series, uint6
     if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
     if (!s || !s->T) return fail(MC_E_ARG, "schedule or its T is NULL");
     if (s->n_T < 1 || s->measure_every < 1) return fail(MC_E_ARG, "n_T and measure_every must be >= 1");
-    if (s->flags & ~MC_PERSISTENT) return fail(MC_E_ARG, "unknown schedule flags 0x%x", s->flags);
-    const bool persistent = (s->flags & MC_PERSISTENT) != 0;
+    if (s->flags & ~(MC_PERSISTENT | MC_TUNED_LAUNCH))
+        return fail(MC_E_ARG, "unknown schedule flags 0x%x", s->flags);
+    if ((s->flags & MC_PERSISTENT) && (s->flags & MC_TUNED_LAUNCH))
+        return fail(MC_E_ARG, "MC_PERSISTENT and MC_TUNED_LAUNCH exclude each other");
+    const bool persistent = (s->flags & MC_PERSISTENT) != 0 ||
+                            ((s->flags & MC_TUNED_LAUNCH) && h->tuned_persistent);
     const uint64_t per_step = s->n_meas / s->measure_every;
     const uint64_t need = (uint64_t)s->n_T * per_step * h->n_reps;
     if (need > 0 && !series) return fail(MC_E_ARG, "series is NULL");
@@ -1299,6 +1351,9 @@ mc_status mc_debug_pass(mc_sim *h, int32_t colour, void *const *dh, void *const 
     if (colour < 0 || colour >= h->n_colours)
         return fail(MC_E_ARG, "colour %d out of range [0, %d)", colour, h->n_colours);
     if (!dh || !accepted) return fail(MC_E_ARG, "dh or accepted is NULL");
+    if (h->pass_tile.kernel == KERNEL_FUSED)
+        return fail(MC_E_UNSUPPORTED, "the fused sweep kernel has no single colour pass; set "
+                                      "another tile for debug passes");
     const size_t esz = h->prec == MC_F64 ? sizeof(double) : sizeof(float);
     for (int r = 0; r < h->n_reps; ++r) {
         mc_status s = check_device_buffer(dh[r], h->reps[r].n_box * esz, "dh", r);
@@ -1334,6 +1389,54 @@ mc_status mc_layout_copy(mc_sim *h, int32_t replica, int32_t to_natural, void *n
     return MC_OK;
 }
 
+mc_status mc_set_second_buffers(mc_sim *h, const mc_spin_buffers *bufs)
+{
+    if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
+    if (!bufs) return fail(MC_E_ARG, "bufs is NULL");
+    const size_t esz = h->prec == MC_F64 ? sizeof(double) : sizeof(float);
+    for (int r = 0; r < h->n_reps; ++r) {
+        const RepDev &R = h->reps[r];
+        if (bufs[r].capacity_sites < R.n_box)
+            return fail(MC_E_BUFFER, "replica %d: capacity %llu < %u sites", r,
+                        (unsigned long long)bufs[r].capacity_sites, R.n_box);
+        const void *pl[3] = {bufs[r].sx, bufs[r].sy, bufs[r].sz};
+        const char *nm[3] = {"sx", "sy", "sz"};
+        for (int a = 0; a < 3; ++a) {
+            mc_status st = check_device_buffer(pl[a], (uint64_t)R.n_box * esz, nm[a], r);
+            if (st != MC_OK) return st;
+            const char *p0 = (const char *)pl[a], *p1 = p0 + (uint64_t)R.n_box * esz;
+            const void *cur[3] = {R.sx, R.sy, R.sz};
+            for (int b = 0; b < 3; ++b) {
+                const char *q0 = (const char *)cur[b], *q1 = q0 + (uint64_t)R.n_box * esz;
+                if (p0 < q1 && q0 < p1)
+                    return fail(MC_E_BUFFER, "replica %d: second %s overlaps the current state",
+                                r, nm[a]);
+            }
+        }
+    }
+    if (h->tile.kernel == KERNEL_FUSED) HIP_TRY(hipStreamSynchronize(h->stream));
+    for (int r = 0; r < h->n_reps; ++r) {
+        h->reps[r].ax = bufs[r].sx;
+        h->reps[r].ay = bufs[r].sy;
+        h->reps[r].az = bufs[r].sz;
+    }
+    return upload_reps(h);
+}
+
+mc_status mc_get_state_buffers(const mc_sim *h, int32_t replica, mc_spin_buffers *out)
+{
+    if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
+    if (!out) return fail(MC_E_ARG, "out is NULL");
+    if (replica < 0 || replica >= h->n_reps)
+        return fail(MC_E_ARG, "replica %d out of range [0, %d)", replica, h->n_reps);
+    const RepDev &R = h->reps[replica];
+    out->sx = R.sx;
+    out->sy = R.sy;
+    out->sz = R.sz;
+    out->capacity_sites = R.n_box;
+    return MC_OK;
+}
+
 mc_status mc_set_tile(mc_sim *h, int32_t kernel, int32_t tx, int32_t ty, int32_t zc)
 {
     if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
@@ -1350,6 +1453,7 @@ mc_status mc_set_tile(mc_sim *h, int32_t kernel, int32_t tx, int32_t ty, int32_t
         for (auto &kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
         h->graphs.clear();
         h->tile = Tile{KERNEL_LDS, tx, 1, 1};
+        h->tuned_persistent = false; // a tile set by hand runs per pass under MC_TUNED_LAUNCH
         return MC_OK;
     }
     Tile t{kernel, tx, ty, zc};
@@ -1380,10 +1484,23 @@ mc_status mc_set_tile(mc_sim *h, int32_t kernel, int32_t tx, int32_t ty, int32_t
             return fail(MC_E_UNSUPPORTED, "LDS-staged band kernel: %d rows of %d columns need more "
                                           "than %d copies per lane", ty + 2, w, LBAND_SLOTS);
     }
+    if (kernel == KERNEL_FUSED) {
+        for (int r = 0; r < h->n_reps; ++r)
+            if (!h->reps[r].ax || !h->reps[r].ay || !h->reps[r].az)
+                return fail(MC_E_STATE, "fused sweep kernel: replica %d has no second buffer set "
+                                        "(mc_set_second_buffers)", r);
+        int w = 1;
+        for (int r = 0; r < h->n_reps; ++r) w = std::max(w, row_len(h->desc[r]));
+        const uint32_t lds = fused_lds_bytes(ty, w, h->prec == MC_F64 ? 8 : 4);
+        if (lds > h->lds_max)
+            return fail(MC_E_UNSUPPORTED, "fused sweep kernel: %d rows of %d columns need %u bytes "
+                                          "of LDS, a workgroup may use %u", ty, w, lds, h->lds_max);
+    }
     if (kernel != KERNEL_TILE && sc_sphere(h))
         return fail(MC_E_UNSUPPORTED, "a simple-cubic lattice cut to a sphere runs on the tile "
                                       "kernel (0) or the LDS kernel (3) only");
-    if (kernel == KERNEL_PAIR || kernel == KERNEL_PBAND || kernel == KERNEL_BPAIR)
+    if (kernel == KERNEL_PAIR || kernel == KERNEL_PBAND || kernel == KERNEL_BPAIR ||
+        kernel == KERNEL_FUSED)
         for (int r = 0; r < h->n_reps; ++r)
             if (row_len(h->desc[r]) % 2)
                 return fail(MC_E_UNSUPPORTED, "pair kernels: replica %d has an odd number (%d) of "
@@ -1399,10 +1516,16 @@ mc_status mc_set_tile(mc_sim *h, int32_t kernel, int32_t tx, int32_t ty, int32_t
     HIP_TRY(hipStreamSynchronize(h->stream));
     // a deferred persistent-launch error lives in the state words that move
     if ((st = check_persistent(h)) != MC_OK) return st;
+    if (kernel == KERNEL_FUSED) {
+        int w = 1;
+        for (int r = 0; r < h->n_reps; ++r) w = std::max(w, row_len(h->desc[r]));
+        HIP_TRY(fused_allow(h->prec == MC_F64, fused_lds_bytes(ty, w, h->prec == MC_F64 ? 8 : 4)));
+    }
     for (auto &kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
     h->graphs.clear();
     h->tile = t;
     h->pass_tile = t;
+    h->tuned_persistent = false;
     h->work.swap(work);
     h->lay = lay;
     h->reps_dev = (RepDev *)(h->scratch + lay.off_reps);

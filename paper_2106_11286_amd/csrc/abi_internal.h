@@ -88,6 +88,7 @@ struct mc_sim {
     std::vector<uint32_t> xchg_rep_host;   // upload staging
     uint32_t spin_limit = 1u << 24;
     bool persist_used = false;
+    bool tuned_persistent = false;  // launch mode chosen by mc_autotune(MC_TUNED_LAUNCH)
     int persist_mode = MC_PERSIST_AUTO;
     bool xcd_ok = false;            // workgroups are dealt to 8 XCDs in turn
     uint32_t n_queues = 1, max_queue_items = 0;

@@ -106,7 +106,7 @@ std::string tune_key(const mc_sim *h, uint32_t flags)
     std::ostringstream k;
     k << h->device_key << "/kind" << h->kind << "/prec" << (int)h->prec << "/flags" << flags
       << "/reps" << h->n_reps;
-    if (flags & MC_PERSISTENT) k << "/queues" << h->persist_mode;
+    if (flags & (MC_PERSISTENT | MC_TUNED_LAUNCH)) k << "/queues" << h->persist_mode;
     k << "/" << std::hex << hash;
     return k.str();
 }
@@ -114,6 +114,14 @@ std::string tune_key(const mc_sim *h, uint32_t flags)
 } // namespace
 
 extern "C" {
+
+mc_status mc_get_tuned_launch(const mc_sim *h, int32_t *persistent)
+{
+    if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
+    if (!persistent) return fail(MC_E_ARG, "persistent is NULL");
+    *persistent = h->tuned_persistent ? 1 : 0;
+    return MC_OK;
+}
 
 mc_status mc_tune_device_key(const char *arch, int32_t n_cu, int32_t n_xcd, char *out,
                              uint64_t capacity)
@@ -137,10 +145,15 @@ mc_status mc_autotune(mc_sim *h, uint32_t trial_sweeps, uint32_t flags, const ch
                       int32_t *kernel, int32_t *tx, int32_t *ty, int32_t *zc)
 {
     if (!alive(h)) return fail(MC_E_STATE, "invalid or destroyed handle");
-    if (flags & ~(MC_MEASURE | MC_PERSISTENT)) return fail(MC_E_ARG, "unknown flags 0x%x", flags);
+    if (flags & ~(MC_MEASURE | MC_PERSISTENT | MC_TUNED_LAUNCH))
+        return fail(MC_E_ARG, "unknown flags 0x%x", flags);
+    if ((flags & MC_PERSISTENT) && (flags & MC_TUNED_LAUNCH))
+        return fail(MC_E_ARG, "MC_PERSISTENT and MC_TUNED_LAUNCH exclude each other");
+    const bool tune_launch = (flags & MC_TUNED_LAUNCH) != 0;
     if (trial_sweeps < 1) return fail(MC_E_ARG, "trial_sweeps must be >= 1");
     const std::string key = tune_key(h, flags);
     Tile best = h->tile;
+    bool best_pers = false;
     bool found = false;
     if (cache_path) {
         std::ifstream in(cache_path);
@@ -150,8 +163,11 @@ mc_status mc_autotune(mc_sim *h, uint32_t trial_sweeps, uint32_t flags, const ch
             std::string k;
             Tile t;
             double ms;
+            int pers = 0;
             if (ls >> k >> t.kernel >> t.tx >> t.ty >> t.zc >> ms && k == key) {
+                if (!(ls >> pers)) pers = 0;
                 best = t;
+                best_pers = tune_launch && pers == 1;
                 found = true;
             }
         }
@@ -168,27 +184,36 @@ mc_status mc_autotune(mc_sim *h, uint32_t trial_sweeps, uint32_t flags, const ch
         for (const Tile &t : tile_candidates(h)) {
             if ((flags & MC_PERSISTENT) && !persistent_supported(t)) continue;
             if (mc_set_tile(h, t.kernel, t.tx, t.ty, t.zc) != MC_OK) continue; // e.g. too big
-            mc_status st = mc_sweep(h, 1, flags);
-            if (st == MC_OK) st = mc_synchronize(h);
-            if (st != MC_OK) {
-                (void)hipEventDestroy(e0);
-                (void)hipEventDestroy(e1);
-                return st;
-            }
-            (void)hipEventRecord(e0, h->stream);
-            st = mc_sweep(h, trial_sweeps, flags);
-            (void)hipEventRecord(e1, h->stream);
-            if (st == MC_OK) st = mc_synchronize(h);
-            if (st != MC_OK) {
-                (void)hipEventDestroy(e0);
-                (void)hipEventDestroy(e1);
-                return st;
-            }
-            float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            if (ms < best_ms) {
-                best_ms = ms;
-                best = t;
+            // launch modes to time: as asked, or (MC_TUNED_LAUNCH) both
+            for (int mode = 0; mode < 2; ++mode) {
+                uint32_t f = flags & ~MC_TUNED_LAUNCH;
+                if (mode == 1) {
+                    if (!tune_launch || !persistent_supported(t) || t.kernel == KERNEL_LDS) break;
+                    f |= MC_PERSISTENT;
+                }
+                mc_status st = mc_sweep(h, 1, f);
+                if (st == MC_OK) st = mc_synchronize(h);
+                if (st != MC_OK) {
+                    (void)hipEventDestroy(e0);
+                    (void)hipEventDestroy(e1);
+                    return st;
+                }
+                (void)hipEventRecord(e0, h->stream);
+                st = mc_sweep(h, trial_sweeps, f);
+                (void)hipEventRecord(e1, h->stream);
+                if (st == MC_OK) st = mc_synchronize(h);
+                if (st != MC_OK) {
+                    (void)hipEventDestroy(e0);
+                    (void)hipEventDestroy(e1);
+                    return st;
+                }
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = t;
+                    best_pers = mode == 1;
+                }
             }
         }
         (void)hipEventDestroy(e0);
@@ -197,11 +222,15 @@ mc_status mc_autotune(mc_sim *h, uint32_t trial_sweeps, uint32_t flags, const ch
         if (st != MC_OK) return st;
         if (cache_path) {
             std::ofstream out(cache_path, std::ios::app);
-            if (out)
+            if (out) {
                 out << key << " " << best.kernel << " " << best.tx << " " << best.ty << " "
-                    << best.zc << " " << best_ms / trial_sweeps << "\n";
+                    << best.zc << " " << best_ms / trial_sweeps;
+                if (tune_launch) out << " " << (best_pers ? 1 : 0);
+                out << "\n";
+            }
         }
     }
+    if (tune_launch) h->tuned_persistent = best_pers;
     if (kernel) *kernel = h->tile.kernel;
     if (tx) *tx = h->tile.tx;
     if (ty) *ty = h->tile.ty;

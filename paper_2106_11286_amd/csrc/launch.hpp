@@ -95,6 +95,16 @@ hipError_t launch_lds(int kind, bool f64, bool measure, const LdsLaunch &L, int 
 // Allow the LDS kernels of one lattice kind and precision `bytes` of dynamic LDS.
 hipError_t lds_allow(int kind, bool f64, uint32_t bytes);
 
+// The fused simple-cubic sweep (kernel 9): both colours of one sweep in one
+// launch, from each replica's current buffer set (sx, sy, sz) into its second
+// set (ax, ay, az), measured or not; p.lds_bytes of dynamic LDS.
+hipError_t launch_fused(bool f64, bool measure, const PassLaunch &p, hipStream_t st);
+// Swap every replica's two buffer sets in the device descriptors (after a
+// fused sweep: the second set holds the current state).
+hipError_t launch_swap_state(RepDev *reps_dev, uint32_t n_reps, hipStream_t st);
+// Allow the fused kernel `bytes` of dynamic LDS.
+hipError_t fused_allow(bool f64, uint32_t bytes);
+
 // The HBM streams of a colour pass without its arithmetic (see mc_stream_probe).
 hipError_t launch_stream_probe(bool f64, void *x, void *y, void *z, uint64_t P, uint32_t grid,
                                hipStream_t st);

@@ -11,7 +11,8 @@ enum Kind : int32_t { SC = 0, BCC = 1, FCC = 2 };
 
 // Per-replica descriptor as the kernels see it (lives in device scratch).
 struct alignas(16) RepDev {
-    void *sx, *sy, *sz;       // colour-major planes (library layout)
+    void *sx, *sy, *sz;       // colour-major planes (library layout): the current state
+    void *ax, *ay, *az;       // second buffer set the fused sweep writes (null if none)
     int32_t Lx, Ly, Lz;       // cells
     int32_t Lxh;              // sc: Lx/2 (packed row length); basis kinds: Lx
     uint32_t pmask;           // periodic axes
@@ -55,6 +56,8 @@ enum : int32_t {
     KERNEL_BSTRIP = 6, // bcc / fcc: tx (multiple of 64) lanes along x, ty rows, planes in registers
     KERNEL_BPAIR = 7,  // bcc / fcc, even Lx: tx threads over (band, pair) positions, ty rows per band
     KERNEL_LBAND = 8,  // sc only, 16-byte rows: tiles of ty whole rows, rows staged through LDS
+    KERNEL_FUSED = 9,  // sc only, even packed rows: both colours in one launch, tiles of ty
+                       // whole rows (tx = 256 threads), next state into the second buffer set
 };
 
 // LDS elements of one stage of the LDS-staged band kernel for tiles of br rows
@@ -70,6 +73,12 @@ constexpr uint32_t lband_comp_chunks(int rows, int lxh, int esz)
 constexpr uint32_t lband_lds_bytes(int br, int lxh, int esz)
 {
     return 2u * 3u * 16u * (lband_comp_chunks(br + 2, lxh, esz) + lband_comp_chunks(br, lxh, esz));
+}
+// Dynamic LDS of the fused sweep kernel: three planes of new colour-0 spins,
+// rows y0-1 .. y0+br of lxh packed columns, three components.
+constexpr uint32_t fused_lds_bytes(int br, int lxh, int esz)
+{
+    return 9u * (uint32_t)(br + 2) * (uint32_t)lxh * (uint32_t)esz;
 }
 // Copy slots per lane and buffer (chunk groups of 64 over 4 waves).
 constexpr int LBAND_SLOTS = 6;

@@ -27,6 +27,7 @@ F32, F64 = 0, 1
 INIT_RANDOM, INIT_ALIGNED, INIT_USER = 0, 1, 2
 MEASURE = 1
 PERSISTENT = 2
+TUNED_LAUNCH = 4
 BLOCK_CONFLICTS = 4
 BLOCK_RESET = 8
 STATUS = {0: "MC_OK", -1: "MC_E_ARG", -2: "MC_E_UNSUPPORTED", -3: "MC_E_BUFFER",
@@ -98,6 +99,9 @@ _SIGNATURES = {
                                       ctypes.c_void_p, ctypes.c_void_p]),
     "mc_set_tile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                    ctypes.c_int32]),
+    "mc_set_second_buffers": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SpinBuffers)]),
+    "mc_get_state_buffers": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32,
+                                            ctypes.POINTER(SpinBuffers)]),
     "mc_get_tile": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
                                    ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                    ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_uint64)]),
@@ -133,6 +137,7 @@ _SIGNATURES = {
     "mc_measure_buffers_static": (ctypes.c_int, [ctypes.POINTER(ReplicaDesc), ctypes.c_int,
                                                  ctypes.POINTER(SpinBuffers), ctypes.c_void_p,
                                                  ctypes.c_void_p]),
+    "mc_get_tuned_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
     "mc_tune_device_key": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_int32, ctypes.c_int32,
                                           ctypes.c_char_p, ctypes.c_uint64]),
     "mc_synchronize": (ctypes.c_int, [ctypes.c_void_p]),
@@ -369,11 +374,20 @@ class Simulation:
         return self._h
 
     # -- the four entry points --------------------------------------------
-    def sweep(self, n: int = 1, measure: bool = False, persistent: bool = False):
+    def sweep(self, n: int = 1, measure: bool = False, persistent: bool = False,
+              tuned: bool = False):
         """``mc_sweep``: enqueue n sweeps (asynchronous); ``persistent`` runs them
-        as one persistent launch."""
-        flags = (MEASURE if measure else 0) | (PERSISTENT if persistent else 0)
+        as one persistent launch, ``tuned`` in the launch mode the autotuner
+        chose with ``tune_launch``."""
+        flags = ((MEASURE if measure else 0) | (PERSISTENT if persistent else 0) |
+                 (TUNED_LAUNCH if tuned else 0))
         _check("mc_sweep", LIB.mc_sweep(self.handle, int(n), flags))
+
+    def tuned_launch(self) -> str:
+        """``mc_get_tuned_launch``: "persistent" or "per-pass"."""
+        v = ctypes.c_int32()
+        _check("mc_get_tuned_launch", LIB.mc_get_tuned_launch(self.handle, ctypes.byref(v)))
+        return "persistent" if v.value else "per-pass"
 
     def synchronize_checked(self):
         """``mc_synchronize``: wait and report deferred errors."""
@@ -465,7 +479,7 @@ class Simulation:
         return [obs_to_dict(o) for o in out]
 
     def run_schedule(self, T, n_equil: int, n_meas: int, measure_every: int = 1,
-                     persistent: bool = False) -> np.ndarray:
+                     persistent: bool = False, tuned: bool = False) -> np.ndarray:
         """``mc_run_schedule``: T is (n_T,) or (n_T, n_reps).  Returns an array
         (n_T, n_rec, n_reps, 10) of records (see ``obs_array_to_numpy``)."""
         T = np.asarray(T, dtype=np.float64)
@@ -480,7 +494,7 @@ class Simulation:
         s.n_T = n_T
         s.T = T.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         s.n_equil, s.n_meas, s.measure_every = int(n_equil), int(n_meas), int(measure_every)
-        s.flags = PERSISTENT if persistent else 0
+        s.flags = PERSISTENT if persistent else (TUNED_LAUNCH if tuned else 0)
         nw = ctypes.c_uint64()
         _check("mc_run_schedule", LIB.mc_run_schedule(self.handle, ctypes.byref(s), series, cap,
                                                       ctypes.byref(nw)))
@@ -510,15 +524,43 @@ class Simulation:
         (tx threads along the row, ty rows per thread), 2 = sc band, 3 = whole
         sweeps in LDS (tx threads per replica), 4 = sc pair strip (two columns
         per thread), 5 = sc band of pairs, 6 = bcc/fcc strip, 7 = bcc/fcc band of
-        cell pairs, 8 = sc tiles of ty whole rows staged through LDS (tx = 256);
-        zc planes per tile."""
+        cell pairs, 8 = sc tiles of ty whole rows staged through LDS (tx = 256),
+        9 = sc fused sweep over tiles of ty whole rows (tx = 256; needs
+        ``enable_fused``); zc planes per tile."""
         _check("mc_set_tile", LIB.mc_set_tile(self.handle, int(kernel), int(tx), int(ty), int(zc)))
 
+    def enable_fused(self):
+        """Allocate every replica's second spin buffer set and hand it to the
+        library (``mc_set_second_buffers``), so the fused sweep kernel (9) can
+        be chosen; it writes each sweep's new state into the other set."""
+        if getattr(self, "alt_spins", None) is None:
+            self.alt_spins = [[torch.zeros(n, dtype=self.dtype, device=self.device)
+                               for _ in range(3)] for n in self.sites]
+        bufs = (SpinBuffers * self.n_reps)()
+        for i, (pl, n) in enumerate(zip(self.alt_spins, self.sites)):
+            bufs[i].sx, bufs[i].sy, bufs[i].sz = pl[0].data_ptr(), pl[1].data_ptr(), pl[2].data_ptr()
+            bufs[i].capacity_sites = n
+        _check("mc_set_second_buffers", LIB.mc_set_second_buffers(self.handle, bufs))
+
+    def state_spins(self, r: int = 0):
+        """The three component tensors that hold replica r's current state
+        (``mc_get_state_buffers``: the initial set, or the second one after an
+        odd number of fused sweeps)."""
+        b = SpinBuffers()
+        _check("mc_get_state_buffers", LIB.mc_get_state_buffers(self.handle, int(r), ctypes.byref(b)))
+        for pl in [self.spins[r]] + ([self.alt_spins[r]] if getattr(self, "alt_spins", None) else []):
+            if pl[0].data_ptr() == b.sx:
+                return pl
+        raise MCError("mc_get_state_buffers", -5, "state buffers unknown to this binding")
+
     def autotune(self, trial_sweeps: int = 5, measure: bool = True, persistent: bool = False,
-                 cache_path: Optional[str] = None):
+                 cache_path: Optional[str] = None, tune_launch: bool = False):
         """``mc_autotune``: pick the fastest kernel / tile shape (the trial
-        sweeps advance the chain).  Returns (kernel, tx, ty, zc)."""
-        flags = (MEASURE if measure else 0) | (PERSISTENT if persistent else 0)
+        sweeps advance the chain); with ``tune_launch`` also the launch mode
+        (per-pass graphs or persistent) used by ``sweep(tuned=True)``.
+        Returns (kernel, tx, ty, zc)."""
+        flags = ((MEASURE if measure else 0) | (PERSISTENT if persistent else 0) |
+                 (TUNED_LAUNCH if tune_launch else 0))
         k, a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         path = cache_path.encode() if cache_path else None
         _check("mc_autotune", LIB.mc_autotune(self.handle, int(trial_sweeps), flags, path,

@@ -274,3 +274,31 @@ def test_sc_1024_beyond_4gib(M):
             assert np.max(np.abs(got - r["S_after"])) <= 2e-6
         del before, after
     assert n_flip <= 2
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_full_size_sc464_fused(M, prec):
+    """The fused sweep kernel (kernel 9) on the headline lattice, sc 464^3:
+    two measured sweeps (one from each buffer set) against the oracle's
+    sweep and observables from the same state, then the state after four
+    sweeps bitwise against the two-pass band-pair kernel's."""
+    import torch
+
+    c = Case(M, W.C5_SC464_ROOFLINE, prec)
+    c.sim.enable_fused()
+    c.sim.set_tile(256, 4, 16, kernel=9)
+    c.sim.sweep(2)
+    c.measured_sweep()
+    assert c.sim.state_spins(0)[0].data_ptr() == c.sim.alt_spins[0][0].data_ptr()
+    c.measured_sweep()
+    assert c.sim.state_spins(0)[0].data_ptr() == c.sim.spins[0][0].data_ptr()
+    got = natural(c.sim)
+    del c
+    torch.cuda.empty_cache()
+    w = W.C5_SC464_ROOFLINE
+    ref = M.Simulation([M.Replica(**W.replica_fields(w))], precision=prec, seed=w["seed"],
+                       scratch=torch.empty(64 << 20, dtype=torch.uint8, device="cuda"))
+    ref.set_tile(256, 2, 7, kernel=5)
+    ref.sweep(4)
+    for a, b in zip(got, natural(ref)):
+        assert np.array_equal(a, b)

@@ -1200,3 +1200,129 @@ def test_lds_band_kernel_is_bitwise(M, prec):
     with pytest.raises(M.MCError) as ei:
         odd.set_tile(256, 2, 3, kernel=8)
     assert ei.value.status == -2
+
+
+def test_tuned_launch_keeps_the_chain(M, tmp_path):
+    """The autotuner choosing the launch mode with the tile (MC_TUNED_LAUNCH):
+    sweeps in the chosen mode, and a schedule with the flag, give bitwise the
+    spins of plain per-pass sweeps; the choice is cached with the tile."""
+    import torch
+
+    reps = [M.Replica(kind="sc", L=(L, L, L), K=0.1, T=0.9 + 0.2 * r, replica_id=r)
+            for r, L in enumerate((16, 24, 32, 24, 16, 32, 24, 16, 20))]
+    cache = str(tmp_path / "tune.txt")
+    a = M.Simulation(reps, precision="f32", seed=31,
+                     scratch=torch.empty(32 << 20, dtype=torch.uint8, device="cuda"))
+    tile = a.autotune(trial_sweeps=2, measure=True, tune_launch=True, cache_path=cache)
+    mode = a.tuned_launch()
+    assert mode in ("persistent", "per-pass")
+    t = a.get_sweep()
+    a.sweep(5, measure=True, tuned=True)
+    a.run_schedule([[rep.T for rep in reps]], n_equil=0, n_meas=3, tuned=True)
+    b = M.Simulation(reps, precision="f32", seed=31,
+                     scratch=torch.empty(32 << 20, dtype=torch.uint8, device="cuda"))
+    b.set_tile(tile[1], tile[2], tile[3], kernel=tile[0])
+    b.sweep(t + 8)
+    for r in range(len(reps)):
+        for x, y in zip(natural(a, r), natural(b, r)):
+            assert np.array_equal(x, y), r
+    c = M.Simulation(reps, precision="f32", seed=31,
+                     scratch=torch.empty(32 << 20, dtype=torch.uint8, device="cuda"))
+    assert c.autotune(trial_sweeps=2, measure=True, tune_launch=True, cache_path=cache) == tile
+    assert c.tuned_launch() == mode
+    c.set_tile(tile[1], tile[2], tile[3], kernel=tile[0])
+    assert c.tuned_launch() == "per-pass"
+    with pytest.raises(M.MCError) as ei:
+        M._check("mc_sweep", M.LIB.mc_sweep(a.handle, 1, M.PERSISTENT | M.TUNED_LAUNCH))
+    assert ei.value.status == -1
+
+
+FUSED_TILES = [(9, 256, 1, 1), (9, 256, 2, 3), (9, 256, 3, 5), (9, 256, 4, 64)]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_fused_sweep_is_bitwise(M, prec):
+    """The fused sweep (kernel 9: both colours in one launch, next state into
+    the second buffer set, halo colour-0 spins recomputed per tile) gives
+    bitwise the spins of the two-pass chain and the same accepted counts, on
+    periodic, open and mixed faces, ragged row tiles and z chunks, odd and
+    even sweep counts; the state moves between the two buffer sets and every
+    other entry point follows it."""
+    import torch
+
+    base = dict(kind="sc", J=1.0, K=0.1, e=(0.0, 0.6, 0.8))
+    reps = [M.Replica(L=(24, 24, 24), T=1.0, replica_id=0, periodic_mask=7, **base),
+            M.Replica(L=(40, 38, 34), T=1.5, replica_id=1, periodic_mask=7, **base),
+            M.Replica(L=(48, 14, 12), T=0.7, replica_id=2, periodic_mask=7, **base),
+            M.Replica(L=(32, 9, 7), T=1.2, replica_id=3, periodic_mask=1, **base),
+            M.Replica(L=(64, 4, 6), T=1.3, replica_id=4, periodic_mask=6, **base),
+            M.Replica(L=(12, 2, 2), T=0.9, replica_id=5, periodic_mask=7, **base)]
+    ref = M.Simulation(reps, precision=prec, seed=13,
+                       scratch=torch.empty(16 << 20, dtype=torch.uint8, device="cuda"))
+    ref.set_tile(16, 16, 2, kernel=0)
+    ref.sweep(3)
+    ref.sweep(3, measure=True)
+    obs_r = ref.observables()
+    for tile in FUSED_TILES:
+        one = M.Simulation(reps, precision=prec, seed=13,
+                           scratch=torch.empty(16 << 20, dtype=torch.uint8, device="cuda"))
+        with pytest.raises(M.MCError) as ei:  # no second buffer set yet
+            one.set_tile(tile[1], tile[2], tile[3], kernel=tile[0])
+        assert ei.value.status == -5
+        one.enable_fused()
+        one.set_tile(tile[1], tile[2], tile[3], kernel=tile[0])
+        first = [p[0].data_ptr() for p in one.spins]
+        one.sweep(3)
+        # odd count: the state is in the second set now
+        assert [one.state_spins(r)[0].data_ptr() for r in range(len(reps))] == \
+            [p[0].data_ptr() for p in one.alt_spins]
+        one.sweep(3, measure=True)
+        assert [one.state_spins(r)[0].data_ptr() for r in range(len(reps))] == first
+        o = one.observables()
+        for r in range(len(reps)):
+            for a, b in zip(natural(one, r), natural(ref, r)):
+                assert np.array_equal(a, b), (r, tile)
+            assert o[r]["n_accepted"] == obs_r[r]["n_accepted"], (r, tile)
+            assert abs(o[r]["E"] - obs_r[r]["E"]) <= 1e-9 * abs(o[r]["E"]), (r, tile)
+            n_sites = int(np.prod(reps[r].L))  # FP64 sums in another order
+            assert np.max(np.abs(np.array(o[r]["M"]) - np.array(obs_r[r]["M"]))) <= 1e-9 * n_sites
+        one.close()
+    # leave the fused kernel with the state in the second set, continue on
+    # another kernel, then come back: still the same chain
+    a = M.Simulation(reps, precision=prec, seed=21,
+                     scratch=torch.empty(16 << 20, dtype=torch.uint8, device="cuda"))
+    b = M.Simulation(reps, precision=prec, seed=21,
+                     scratch=torch.empty(16 << 20, dtype=torch.uint8, device="cuda"))
+    b.set_tile(16, 16, 2, kernel=0)
+    a.enable_fused()
+    a.set_tile(256, 2, 4, kernel=9)
+    a.sweep(1)
+    a.set_tile(16, 16, 2, kernel=0)
+    a.sweep(2)
+    a.set_tile(256, 3, 2, kernel=9)
+    a.sweep(2, measure=True)
+    b.sweep(5, measure=True)
+    oa, ob = a.observables(), b.observables()
+    for r in range(len(reps)):
+        for x, y in zip(natural(a, r), natural(b, r)):
+            assert np.array_equal(x, y), r
+        assert oa[r]["n_accepted"] == ob[r]["n_accepted"]
+    # a schedule on the fused kernel (graph-replayed chunks) equals one on kernel 0
+    ra = a.run_schedule([[rep.T for rep in reps]], n_equil=3, n_meas=4)
+    rb = b.run_schedule([[rep.T for rep in reps]], n_equil=3, n_meas=4)
+    assert np.allclose(ra, rb, rtol=1e-9, atol=1e-6)
+    for r in range(len(reps)):
+        for x, y in zip(natural(a, r), natural(b, r)):
+            assert np.array_equal(x, y), r
+    # no single-pass debug on the fused kernel; persistent sweeps refused
+    with pytest.raises(M.MCError) as ei:
+        a.debug_pass(0)
+    assert ei.value.status == -2
+    with pytest.raises(M.MCError):
+        a.sweep(1, persistent=True)
+    # odd packed rows are refused
+    odd = M.Simulation([M.Replica(kind="sc", L=(18, 8, 8))], precision=prec)
+    odd.enable_fused()
+    with pytest.raises(M.MCError) as ei:
+        odd.set_tile(256, 2, 3, kernel=9)
+    assert ei.value.status == -2
