@@ -121,7 +121,7 @@ def time_precision(M, W, prec, steps, warmup, tile=None):
     return res
 
 
-FUSED_TILES = ((9, 256, 2, 16), (9, 256, 4, 8), (9, 256, 4, 16))
+FUSED_TILES = ((9, 1024, 6, 16), (9, 1024, 6, 32), (9, 512, 8, 16))
 
 
 def time_fused(M, W, steps, warmup):

@@ -325,10 +325,12 @@ mc_status mc_set_sweep(mc_sim *h, uint64_t t);
  *    sweep -- both colours in one launch per sweep, reading the current
  *    state once and writing the next one into the other buffer set (24 bytes
  *    per update in FP32).  Tiles of ty whole rows (1 .. 64) walked over zc
- *    planes by tx = 256 threads; the new colour-0 spins of rows y0-1 .. y0+ty
- *    are computed by the tile itself (also those outside it) and exchanged
- *    through 9 (ty+2) Lx/2 spin values of LDS (above the device's limit:
- *    MC_E_UNSUPPORTED).  After each sweep the two buffer sets trade places
+ *    planes by tx = 256, 512 or 1024 threads, each lane holding up to four
+ *    (row, pair) positions of rows y0-1 .. y0+ty (1024 threads: one; FP64:
+ *    one, and tx <= 512); the new colour-0 spins of those rows are computed by
+ *    the tile itself (also those outside it) and exchanged through
+ *    6 (ty+2) Lx/2 spin values of LDS.  Shapes beyond these limits or the
+ *    device's LDS give MC_E_UNSUPPORTED.  After each sweep the two buffer sets trade places
  *    (mc_get_state_buffers names the current one).  No persistent sweeps and
  *    no mc_debug_pass (MC_E_UNSUPPORTED).
  * The spins do not depend on the choice (only the FP64 summation order of the

@@ -262,7 +262,8 @@ mc_status check_tile(const Tile &t, int kind, uint64_t max_component_bytes, bool
         if (kind != MC_SC) return fail(MC_E_ARG, "the fused sweep kernel is for simple cubic lattices");
         if (max_component_bytes > 0xFFFFFFFFull)
             return fail(MC_E_UNSUPPORTED, "fused sweep kernel: a spin component array exceeds 4 GiB");
-        if (t.tx != 256) return fail(MC_E_ARG, "fused sweep tile: tx must be 256 (got %d)", t.tx);
+        if (t.tx != 256 && t.tx != 512 && t.tx != 1024)
+            return fail(MC_E_ARG, "fused sweep tile: tx must be 256, 512 or 1024 (got %d)", t.tx);
         if (t.ty < 1 || t.ty > 64)
             return fail(MC_E_ARG, "fused sweep tile: ty (rows per tile) must be in [1, 64]");
     } else if (t.kernel == KERNEL_TILE) {
@@ -442,6 +443,7 @@ PassLaunch pass_args(mc_sim *h, uint32_t item_base, uint32_t n_blocks, uint32_t 
         int w = 1;
         for (const auto &d : h->desc) w = std::max(w, row_len(d));
         p.lds_bytes = fused_lds_bytes(p.tile.ty, w, h->prec == MC_F64 ? 8 : 4);
+        p.lds_positions = fused_positions(p.tile.ty, w, p.tile.tx);
     }
     return p;
 }
@@ -1491,6 +1493,15 @@ mc_status mc_set_tile(mc_sim *h, int32_t kernel, int32_t tx, int32_t ty, int32_t
                                         "(mc_set_second_buffers)", r);
         int w = 1;
         for (int r = 0; r < h->n_reps; ++r) w = std::max(w, row_len(h->desc[r]));
+        const bool f64 = h->prec == MC_F64;
+        if (f64 && tx == 1024)
+            return fail(MC_E_UNSUPPORTED, "fused sweep kernel: FP64 tiles take 256 or 512 threads");
+        // FP64 keeps one position per lane (two would need more than 256 registers)
+        const int max_pos = (tx == 1024 || f64) ? 1 : 4;
+        if (fused_positions(ty, w, tx) > max_pos)
+            return fail(MC_E_UNSUPPORTED, "fused sweep kernel: %d rows of %d columns exceed %d "
+                                          "(row, pair) position%s per thread of %d", ty + 2, w,
+                        max_pos, max_pos > 1 ? "s" : "", tx);
         const uint32_t lds = fused_lds_bytes(ty, w, h->prec == MC_F64 ? 8 : 4);
         if (lds > h->lds_max)
             return fail(MC_E_UNSUPPORTED, "fused sweep kernel: %d rows of %d columns need %u bytes "

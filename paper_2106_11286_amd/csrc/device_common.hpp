@@ -174,7 +174,7 @@ __device__ __forceinline__ uint32_t xcd_id()
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void block_store_partials(double (&a)[Q_N], double *dst)
 {
-    __shared__ double red[4][Q_N];
+    __shared__ double red[16][Q_N]; // up to 1024 threads
 #pragma unroll
     for (int q = 0; q < Q_N; ++q) {
         double v = a[q];

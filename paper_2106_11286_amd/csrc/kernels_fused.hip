@@ -5,12 +5,13 @@
 
 namespace mc {
 
-template <typename T, bool MEASURE>
-__global__ void __launch_bounds__(256) k_sc_fused(PassLaunch P)
+// 1024 threads only for one FP32 position per lane (128 registers)
+template <typename T, bool MEASURE, int PP>
+__global__ void __launch_bounds__((PP == 1 && sizeof(T) == 4) ? 1024 : 512) k_sc_fused(PassLaunch P)
 {
     uint32_t item;
     if (!logical_item(P, item)) return;
-    sc_fused_body<T, MEASURE>(P, item, *P.tctr_dev + P.t_off);
+    sc_fused_body<T, MEASURE, PP>(P, item, *P.tctr_dev + P.t_off);
 }
 
 // After a fused sweep the second buffer set holds the current state.
@@ -28,23 +29,29 @@ __global__ void __launch_bounds__(64) k_swap_state(RepDev *reps, uint32_t n)
     R.az = c;
 }
 
+template <typename T, bool MEASURE>
+static hipError_t fused_dispatch(const PassLaunch &p, hipStream_t st)
+{
+    const dim3 g(((p.n_blocks + 7u) >> 3) << 3), b((unsigned)p.tile.tx);
+    switch (p.lds_positions) {
+    case 1: hipLaunchKernelGGL((k_sc_fused<T, MEASURE, 1>), g, b, p.lds_bytes, st, p); break;
+    case 2: hipLaunchKernelGGL((k_sc_fused<T, MEASURE, 2>), g, b, p.lds_bytes, st, p); break;
+    case 3: hipLaunchKernelGGL((k_sc_fused<T, MEASURE, 3>), g, b, p.lds_bytes, st, p); break;
+    case 4: hipLaunchKernelGGL((k_sc_fused<T, MEASURE, 4>), g, b, p.lds_bytes, st, p); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_fused(bool f64, bool measure, const PassLaunch &p, hipStream_t st)
 {
     if (p.n_blocks == 0) return hipSuccess;
-    if (p.tile.tx != 256 || p.tile.ty < 1) return hipErrorInvalidValue;
-    const dim3 g(((p.n_blocks + 7u) >> 3) << 3), b(256);
-    if (f64) {
-        if (measure)
-            hipLaunchKernelGGL((k_sc_fused<double, true>), g, b, p.lds_bytes, st, p);
-        else
-            hipLaunchKernelGGL((k_sc_fused<double, false>), g, b, p.lds_bytes, st, p);
-    } else {
-        if (measure)
-            hipLaunchKernelGGL((k_sc_fused<float, true>), g, b, p.lds_bytes, st, p);
-        else
-            hipLaunchKernelGGL((k_sc_fused<float, false>), g, b, p.lds_bytes, st, p);
-    }
-    return hipGetLastError();
+    if ((p.tile.tx != 256 && p.tile.tx != 512 && p.tile.tx != 1024) || p.tile.ty < 1 ||
+        (p.tile.tx == 1024 && (p.lds_positions != 1 || f64)) || (f64 && p.lds_positions != 1))
+        return hipErrorInvalidValue;
+    if (f64)
+        return measure ? fused_dispatch<double, true>(p, st) : fused_dispatch<double, false>(p, st);
+    return measure ? fused_dispatch<float, true>(p, st) : fused_dispatch<float, false>(p, st);
 }
 
 hipError_t launch_swap_state(RepDev *reps_dev, uint32_t n_reps, hipStream_t st)
@@ -53,22 +60,24 @@ hipError_t launch_swap_state(RepDev *reps_dev, uint32_t n_reps, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t fused_allow(bool f64, uint32_t bytes)
+template <typename T, bool MEASURE>
+static hipError_t fused_allow_one(uint32_t bytes)
 {
-    const void *f[2];
-    if (f64) {
-        f[0] = (const void *)&k_sc_fused<double, false>;
-        f[1] = (const void *)&k_sc_fused<double, true>;
-    } else {
-        f[0] = (const void *)&k_sc_fused<float, false>;
-        f[1] = (const void *)&k_sc_fused<float, true>;
-    }
+    const void *f[4] = {(const void *)&k_sc_fused<T, MEASURE, 1>, (const void *)&k_sc_fused<T, MEASURE, 2>,
+                        (const void *)&k_sc_fused<T, MEASURE, 3>, (const void *)&k_sc_fused<T, MEASURE, 4>};
     for (const void *fn : f) {
         const hipError_t e =
             hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+hipError_t fused_allow(bool f64, uint32_t bytes)
+{
+    hipError_t e = f64 ? fused_allow_one<double, false>(bytes) : fused_allow_one<float, false>(bytes);
+    if (e != hipSuccess) return e;
+    return f64 ? fused_allow_one<double, true>(bytes) : fused_allow_one<float, true>(bytes);
 }
 
 } // namespace mc

@@ -74,11 +74,16 @@ constexpr uint32_t lband_lds_bytes(int br, int lxh, int esz)
 {
     return 2u * 3u * 16u * (lband_comp_chunks(br + 2, lxh, esz) + lband_comp_chunks(br, lxh, esz));
 }
-// Dynamic LDS of the fused sweep kernel: three planes of new colour-0 spins,
+// Dynamic LDS of the fused sweep kernel: two planes of new colour-0 spins,
 // rows y0-1 .. y0+br of lxh packed columns, three components.
 constexpr uint32_t fused_lds_bytes(int br, int lxh, int esz)
 {
-    return 9u * (uint32_t)(br + 2) * (uint32_t)lxh * (uint32_t)esz;
+    return 6u * (uint32_t)(br + 2) * (uint32_t)lxh * (uint32_t)esz;
+}
+// (row, pair) positions per lane of the fused sweep kernel (tx threads).
+constexpr int fused_positions(int br, int lxh, int tx)
+{
+    return ((br + 2) * (lxh / 2) + tx - 1) / tx;
 }
 // Copy slots per lane and buffer (chunk groups of 64 over 4 waves).
 constexpr int LBAND_SLOTS = 6;

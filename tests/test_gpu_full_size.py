@@ -286,7 +286,10 @@ def test_full_size_sc464_fused(M, prec):
 
     c = Case(M, W.C5_SC464_ROOFLINE, prec)
     c.sim.enable_fused()
-    c.sim.set_tile(256, 4, 16, kernel=9)
+    if prec == "f32":
+        c.sim.set_tile(1024, 6, 16, kernel=9)  # the benchmark's fused tile
+    else:
+        c.sim.set_tile(512, 2, 16, kernel=9)   # FP64: one position per lane
     c.sim.sweep(2)
     c.measured_sweep()
     assert c.sim.state_spins(0)[0].data_ptr() == c.sim.alt_spins[0][0].data_ptr()

@@ -1237,7 +1237,11 @@ def test_tuned_launch_keeps_the_chain(M, tmp_path):
     assert ei.value.status == -1
 
 
-FUSED_TILES = [(9, 256, 1, 1), (9, 256, 2, 3), (9, 256, 3, 5), (9, 256, 4, 64)]
+# (kernel, threads, rows, planes): one to four (row, pair) positions per lane
+FUSED_TILES = {"f32": [(9, 256, 1, 1), (9, 256, 2, 3), (9, 256, 3, 5), (9, 256, 4, 64),
+                       (9, 512, 6, 4), (9, 1024, 5, 7), (9, 256, 20, 3), (9, 256, 40, 2),
+                       (9, 256, 60, 2)],
+               "f64": [(9, 256, 1, 1), (9, 256, 2, 3), (9, 512, 3, 5), (9, 256, 4, 64)]}
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
@@ -1263,7 +1267,7 @@ def test_fused_sweep_is_bitwise(M, prec):
     ref.sweep(3)
     ref.sweep(3, measure=True)
     obs_r = ref.observables()
-    for tile in FUSED_TILES:
+    for tile in FUSED_TILES[prec]:
         one = M.Simulation(reps, precision=prec, seed=13,
                            scratch=torch.empty(16 << 20, dtype=torch.uint8, device="cuda"))
         with pytest.raises(M.MCError) as ei:  # no second buffer set yet
@@ -1326,3 +1330,11 @@ def test_fused_sweep_is_bitwise(M, prec):
     with pytest.raises(M.MCError) as ei:
         odd.set_tile(256, 2, 3, kernel=9)
     assert ei.value.status == -2
+    # shapes beyond the positions a lane can hold are refused
+    with pytest.raises(M.MCError) as ei:
+        a.set_tile(1024, 64, 2, kernel=9)
+    assert ei.value.status == -2
+    if prec == "f64":
+        with pytest.raises(M.MCError) as ei:
+            a.set_tile(256, 20, 3, kernel=9)
+        assert ei.value.status == -2
