@@ -325,7 +325,7 @@ mc_status mc_set_sweep(mc_sim *h, uint64_t t);
  *    sweep -- both colours in one launch per sweep, reading the current
  *    state once and writing the next one into the other buffer set (24 bytes
  *    per update in FP32).  Tiles of ty whole rows (1 .. 64) walked over zc
- *    planes by tx = 256, 512 or 1024 threads, each lane holding up to four
+ *    planes by tx = 256, 512 or 1024 threads, each lane holding up to three
  *    (row, pair) positions of rows y0-1 .. y0+ty (1024 threads: one; FP64:
  *    one, and tx <= 512); the new colour-0 spins of those rows are computed by
  *    the tile itself (also those outside it) and exchanged through

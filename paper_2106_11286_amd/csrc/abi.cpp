@@ -1496,8 +1496,9 @@ mc_status mc_set_tile(mc_sim *h, int32_t kernel, int32_t tx, int32_t ty, int32_t
         const bool f64 = h->prec == MC_F64;
         if (f64 && tx == 1024)
             return fail(MC_E_UNSUPPORTED, "fused sweep kernel: FP64 tiles take 256 or 512 threads");
-        // FP64 keeps one position per lane (two would need more than 256 registers)
-        const int max_pos = (tx == 1024 || f64) ? 1 : 4;
+        // FP64 keeps one position per lane, FP32 at most three (more would need
+        // more than the 256 registers of a lane); 1024 threads: one
+        const int max_pos = (tx == 1024 || f64) ? 1 : 3;
         if (fused_positions(ty, w, tx) > max_pos)
             return fail(MC_E_UNSUPPORTED, "fused sweep kernel: %d rows of %d columns exceed %d "
                                           "(row, pair) position%s per thread of %d", ty + 2, w,

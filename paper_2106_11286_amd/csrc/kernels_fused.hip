@@ -29,15 +29,28 @@ __global__ void __launch_bounds__(64) k_swap_state(RepDev *reps, uint32_t n)
     R.az = c;
 }
 
+// FP32: one to three positions per lane; FP64: one (more would not fit 256
+// registers, checked on the host)
 template <typename T, bool MEASURE>
 static hipError_t fused_dispatch(const PassLaunch &p, hipStream_t st)
 {
     const dim3 g(((p.n_blocks + 7u) >> 3) << 3), b((unsigned)p.tile.tx);
     switch (p.lds_positions) {
     case 1: hipLaunchKernelGGL((k_sc_fused<T, MEASURE, 1>), g, b, p.lds_bytes, st, p); break;
-    case 2: hipLaunchKernelGGL((k_sc_fused<T, MEASURE, 2>), g, b, p.lds_bytes, st, p); break;
-    case 3: hipLaunchKernelGGL((k_sc_fused<T, MEASURE, 3>), g, b, p.lds_bytes, st, p); break;
-    case 4: hipLaunchKernelGGL((k_sc_fused<T, MEASURE, 4>), g, b, p.lds_bytes, st, p); break;
+    case 2:
+        if constexpr (sizeof(T) == 4) {
+            hipLaunchKernelGGL((k_sc_fused<T, MEASURE, 2>), g, b, p.lds_bytes, st, p);
+            break;
+        } else {
+            return hipErrorInvalidValue;
+        }
+    case 3:
+        if constexpr (sizeof(T) == 4) {
+            hipLaunchKernelGGL((k_sc_fused<T, MEASURE, 3>), g, b, p.lds_bytes, st, p);
+            break;
+        } else {
+            return hipErrorInvalidValue;
+        }
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -63,9 +76,13 @@ hipError_t launch_swap_state(RepDev *reps_dev, uint32_t n_reps, hipStream_t st)
 template <typename T, bool MEASURE>
 static hipError_t fused_allow_one(uint32_t bytes)
 {
-    const void *f[4] = {(const void *)&k_sc_fused<T, MEASURE, 1>, (const void *)&k_sc_fused<T, MEASURE, 2>,
-                        (const void *)&k_sc_fused<T, MEASURE, 3>, (const void *)&k_sc_fused<T, MEASURE, 4>};
+    const void *f[3] = {(const void *)&k_sc_fused<T, MEASURE, 1>, nullptr, nullptr};
+    if constexpr (sizeof(T) == 4) {
+        f[1] = (const void *)&k_sc_fused<T, MEASURE, 2>;
+        f[2] = (const void *)&k_sc_fused<T, MEASURE, 3>;
+    }
     for (const void *fn : f) {
+        if (!fn) continue;
         const hipError_t e =
             hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         if (e != hipSuccess) return e;

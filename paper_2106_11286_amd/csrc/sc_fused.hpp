@@ -19,7 +19,7 @@
 // are the same arithmetic in the same order (-z, -y, -x, +x, +y, +z) as in
 // every other simple-cubic kernel, so the chain is bitwise the two-pass chain.
 //
-// Work of a lane: PP fixed (row, pair) positions of the tile's rows y0-1 ..
+// Work of a lane: PP (1 .. 3) fixed (row, pair) positions of the tile's rows y0-1 ..
 // y0+BR, the same on every plane.  Across planes a lane keeps in registers
 // the old colour-1 pair of its own row on planes n-1 and n (the -z and
 // in-row terms of plane n's colour 0, the +z term of plane n-1's), and the
