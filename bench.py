@@ -583,6 +583,39 @@ def run_block(M, W):
     return res
 
 
+SHAPES = ((464, 464, 464), (448, 464, 480), (512, 464, 420), (480, 464, 448), (464, 512, 420),
+          (464, 448, 480), (512, 512, 512))
+
+
+def run_shapes(M, sweeps=200):
+    """Rate of measured FP32 sweeps (K = 0.02, T = 1.4, random start) on
+    simple-cubic lattices of about 10^8 spins whose packed rows differ in
+    length (Lx/2 floats: 928 bytes at Lx = 464, 896 at 448, 1024 at 512, 960
+    at 480), each on its autotuned tile: the cost of rows that are not a
+    multiple of the 128-byte line."""
+    import torch
+
+    res = {"workload": "sc-row-length-scan", "sweeps": sweeps, "shapes": []}
+    for L in SHAPES:
+        rep = M.Replica(kind="sc", L=L, J=1.0, K=0.02, e=(0.0, 0.0, 1.0), T=1.4)
+        sim = M.Simulation([rep], precision="f32", seed=4,
+                           scratch=torch.empty(64 << 20, dtype=torch.uint8, device="cuda"))
+        tile = sim.autotune(trial_sweeps=3, measure=True)
+        sim.sweep(10, measure=True)
+        pass_ms, total_ms = sim.sweep_timed(sweeps, measure=True)
+        n = sim.n_occ[0]
+        row = {"L": list(L), "spins": n, "row_bytes": L[0] // 2 * 4, "tile": list(tile),
+               "updates_per_ns": n * sweeps / (total_ms * 1e6), "pass_ms": pass_ms,
+               "algorithmic_GBps": 36.0 * n / 2 / (pass_ms * 1e-3) / 1e9}
+        res["shapes"].append(row)
+        log(f"[bench] shapes {L}: {row['updates_per_ns']:.1f} updates/ns, pass {pass_ms * 1e3:.1f} us, "
+            f"tile {tile}")
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+    return res
+
+
 F1_TEMPERATURES = (1.30, 1.32, 1.34, 1.36, 1.38, 1.40, 1.41, 1.42, 1.43, 1.44, 1.45, 1.46,
                    1.48, 1.50)
 
@@ -688,7 +721,7 @@ def main():
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--workload", default="c5",
                     choices=["c5", "c1", "c2", "c3", "c4", "f1", "big", "bcc", "fcc", "exchange",
-                             "block"],
+                             "block", "shapes"],
                     help="c5 (default): the 10^8-spin headline; others print their own line "
                          "(f1: the paper's M(T) accuracy experiment)")
     ap.add_argument("--f1-sizes", default="128,256,512")
@@ -742,6 +775,8 @@ def main():
                          args.f1_sweeps, K=args.f1_K)
         elif args.workload == "c3":
             out = run_c3(M, W, W.C3_BATCHED["sweeps"])
+        elif args.workload == "shapes":
+            out = run_shapes(M)
         else:
             out = run_c4(M, W, 1000)
         print(json.dumps(out), flush=True)
