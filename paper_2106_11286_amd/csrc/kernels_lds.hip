@@ -15,6 +15,22 @@ namespace mc {
 // ---------------------------------------------------------------------------
 template <typename T> using lptr = __attribute__((address_space(3))) T *;
 
+// Division by a divisor fixed for the launch (a lattice edge d >= 1):
+// floor(n / d) = mulhi(n, ceil(2^32 / d)), exact while n d < 2^32, which the
+// site indices of a lattice held in LDS (n below its few thousand box sites)
+// always satisfy.  Replaces the integer division sequence in the site loop.
+struct FastDiv {
+    uint32_t d, m;
+};
+__device__ __forceinline__ FastDiv fast_div(uint32_t d)
+{
+    return FastDiv{d, d <= 1u ? 0u : (uint32_t)((0x100000000ull + d - 1u) / d)};
+}
+__device__ __forceinline__ uint32_t div_of(uint32_t n, FastDiv f)
+{
+    return f.d <= 1u ? n : __umulhi(n, f.m);
+}
+
 // Block reduction for up to 1024 threads into out[0..Q_N) (LDS); fixed order.
 __device__ __forceinline__ void block_reduce_1024(double (&a)[Q_N], double *out)
 {
@@ -58,6 +74,7 @@ __global__ void __launch_bounds__(1024) k_lds_sweeps(LdsLaunch L)
     const bool px = R.pmask & 1u, py = R.pmask & 2u, pz = R.pmask & 4u;
     const double Kd = R.K, Jd = R.J;
     const uint32_t t0 = *L.tctr_dev;
+    const FastDiv f_row = fast_div((uint32_t)(KIND == SC ? Lxh : Lx)), f_y = fast_div((uint32_t)Ly);
     const lptr<T> lx = (lptr<T>)(lptr<unsigned char>)lds_raw;
     const lptr<T> ly = lx + n_box, lz = ly + n_box;
     for (uint32_t i = threadIdx.x; i < n_box; i += blockDim.x) {
@@ -75,9 +92,10 @@ __global__ void __launch_bounds__(1024) k_lds_sweeps(LdsLaunch L)
                 T hx, hy, hz, sh_x, sh_y, sh_z;
                 uint32_t i, s;
                 if constexpr (KIND == SC) {
-                    const int xh = (int)(k % (uint32_t)Lxh);
-                    const uint32_t row = k / (uint32_t)Lxh;
-                    const int y = (int)(row % (uint32_t)Ly), z = (int)(row / (uint32_t)Ly);
+                    const uint32_t row = div_of(k, f_row);
+                    const int xh = (int)(k - row * (uint32_t)Lxh);
+                    const uint32_t zz = div_of(row, f_y);
+                    const int y = (int)(row - zz * (uint32_t)Ly), z = (int)zz;
                     const int p = (c + y + z) & 1;
                     if (!occupied(R, 2 * xh + p, y, z, 0, 0, 0)) continue;
                     sc_site_field<T>(lx, ly, lz, c ? 0u : plane, Lxh, Ly, Lz, px, py, pz, xh, y,
@@ -85,9 +103,10 @@ __global__ void __launch_bounds__(1024) k_lds_sweeps(LdsLaunch L)
                     i = (c ? plane : 0u) + k;
                     s = row * (uint32_t)Lx + 2u * (uint32_t)xh + (uint32_t)p;
                 } else {
-                    const int x = (int)(k % (uint32_t)Lx);
-                    const uint32_t r2 = k / (uint32_t)Lx;
-                    const int y = (int)(r2 % (uint32_t)Ly), z = (int)(r2 / (uint32_t)Ly);
+                    const uint32_t r2 = div_of(k, f_row);
+                    const int x = (int)(k - r2 * (uint32_t)Lx);
+                    const uint32_t zz = div_of(r2, f_y);
+                    const int y = (int)(r2 - zz * (uint32_t)Ly), z = (int)zz;
                     if (!occupied(R, x, y, z, basis2(KIND, c, 0), basis2(KIND, c, 1),
                                   basis2(KIND, c, 2)))
                         continue;
