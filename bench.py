@@ -124,7 +124,7 @@ def time_precision(M, W, prec, steps, warmup, tile=None):
 FUSED_TILES = ((9, 1024, 6, 16), (9, 1024, 6, 32), (9, 512, 8, 16))
 
 
-def time_fused(M, W, steps, warmup):
+def time_fused(M, W, steps, warmup, tile=None):
     """The fused sweep kernel (9) on the same lattice, FP32, measured sweeps:
     the fastest of a few tile shapes (20 trial sweeps each), then `steps`
     sweeps timed with HIP events around each launch (one per sweep).  Its
@@ -138,7 +138,7 @@ def time_fused(M, W, steps, warmup):
     sim.enable_fused()
     n = sim.n_occ[0]
     best = None
-    for t in FUSED_TILES:
+    for t in (FUSED_TILES if tile is None else (tuple(tile),)):
         sim.set_tile(t[1], t[2], t[3], kernel=t[0])
         launch_ms, _ = sim.sweep_timed(20, measure=True)
         if best is None or launch_ms < best[0]:
@@ -718,6 +718,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-fused", action="store_true",
                     help="skip the fused sweep kernel's line beside the two-pass one")
+    ap.add_argument("--fused-only", action="store_true",
+                    help="time only the fused sweep kernel (on --tile if given) and print its line")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--workload", default="c5",
                     choices=["c5", "c1", "c2", "c3", "c4", "f1", "big", "bcc", "fcc", "exchange",
@@ -783,6 +785,10 @@ def main():
         return
 
     w = W.C5_SC464_ROOFLINE
+    if args.fused_only:
+        print(json.dumps({"workload": w["name"], "fused": time_fused(M, W, args.steps, args.warmup,
+                                                                      tile)}), flush=True)
+        return
     r32 = time_precision(M, W, "f32", args.steps, args.warmup, tile)
     r64 = None if args.no_fp64 else time_precision(M, W, "f64", min(args.steps, args.fp64_steps),
                                                   min(args.warmup, 5))

@@ -360,7 +360,8 @@ mc_status mc_get_tile(const mc_sim *h, int32_t *kernel, int32_t *tx, int32_t *ty
 /* Autotuner (a property of this implementation, not of the method): time
  * candidate kernels and tile shapes on the handle's own lattices
  * (trial_sweeps sweeps each, with `flags` as for mc_sweep) and keep the
- * fastest.  The trial sweeps are ordinary sweeps of the chain: they advance
+ * fastest (the fused sweep kernel 9 is a candidate once every replica has a
+ * second buffer set).  The trial sweeps are ordinary sweeps of the chain: they advance
  * the state and the sweep counter (results stay bitwise independent of the
  * shape).  cache_path (may be NULL) names a text file of earlier choices
  * keyed by device (mc_tune_device_key of the handle's device), lattices,

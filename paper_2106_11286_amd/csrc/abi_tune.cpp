@@ -44,6 +44,15 @@ std::vector<Tile> tile_candidates(const mc_sim *h)
             for (int rows : {256 / np, 512 / np})
                 if (rows >= 1) base.push_back(Tile{KERNEL_LBAND, 256, std::min(rows, 64), 1});
             base.push_back(Tile{KERNEL_PBAND, 128, 2, 1});
+            // the fused sweep, when every replica has its second buffer set
+            bool second = true;
+            for (const RepDev &R : h->reps) second &= R.ax && R.ay && R.az;
+            if (second) {
+                base.push_back(Tile{KERNEL_FUSED, 1024, 6, 1});
+                base.push_back(Tile{KERNEL_FUSED, 512, 8, 1});
+                base.push_back(Tile{KERNEL_FUSED, 256, 4, 1});
+                base.push_back(Tile{KERNEL_FUSED, 256, 2, 1});
+            }
         }
     }
     for (int tx : {64, 32, 16, 8}) {

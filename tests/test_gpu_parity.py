@@ -1341,3 +1341,26 @@ def test_fused_sweep_is_bitwise(M, prec):
         with pytest.raises(M.MCError) as ei:
             a.set_tile(256, 20, 3, kernel=9)
         assert ei.value.status == -2
+
+
+def test_autotune_with_fused_candidates(M):
+    """With second buffer sets the autotuner times the fused sweep's tiles
+    too; whatever it keeps, the chain (odd trial counts leave the state in
+    either set) equals plain sweeps on kernel 0."""
+    import torch
+
+    reps = [M.Replica(kind="sc", L=(L, L, L), K=0.1, T=1.1 + 0.1 * r, replica_id=r)
+            for r, L in enumerate((16, 24, 32))]
+    a = M.Simulation(reps, precision="f32", seed=5,
+                     scratch=torch.empty(32 << 20, dtype=torch.uint8, device="cuda"))
+    a.enable_fused()
+    tile = a.autotune(trial_sweeps=1, measure=True)
+    a.sweep(3, measure=True)
+    t = a.get_sweep()
+    b = M.Simulation(reps, precision="f32", seed=5,
+                     scratch=torch.empty(32 << 20, dtype=torch.uint8, device="cuda"))
+    b.set_tile(16, 16, 2, kernel=0)
+    b.sweep(t)
+    for r in range(len(reps)):
+        for x, y in zip(natural(a, r), natural(b, r)):
+            assert np.array_equal(x, y), (r, tile)
