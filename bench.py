@@ -304,13 +304,20 @@ def run_c1(M, W, cpu):
     rep = M.Replica(**W.replica_fields(w))
     n = w["sweeps"]
     res = {"workload": w["name"], "spins": 4096, "sweeps": n, "dtype": "f64"}
-    for mode in ("graph", "persistent"):
+    for mode in ("graph", "persistent", "autotuned"):
         sim = M.Simulation([rep], precision="f64", seed=w["seed"])
+        tuned = mode == "autotuned"
+        if tuned:  # kernel, tile and launch mode chosen by the autotuner
+            tile = sim.autotune(trial_sweeps=3, measure=True, tune_launch=True)
         # the first call captures the graphs; the second (continuing the
         # chain) is timed
-        sim.run_schedule([rep.T], 0, n, persistent=mode == "persistent")
-        _, dt = _timed(lambda: sim.run_schedule([rep.T], 0, n, persistent=mode == "persistent"))
-        res[mode] = {"s": dt, "updates_per_ns": 4096 * n / dt / 1e9, "us_per_sweep": dt / n * 1e6}
+        sim.run_schedule([rep.T], 0, n, persistent=mode == "persistent", tuned=tuned)
+        _, dt = _timed(lambda: sim.run_schedule([rep.T], 0, n, persistent=mode == "persistent",
+                                                tuned=tuned))
+        res[mode] = {"s": dt, "updates_per_ns": 4096 * n / dt / 1e9, "us_per_sweep": dt / n * 1e6,
+                     "tile": list(sim.get_tile()[:4])}
+        if tuned:
+            res[mode]["launch"] = sim.tuned_launch()
     if cpu:
         from oracle import oracle as O
 

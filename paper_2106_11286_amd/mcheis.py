@@ -332,7 +332,9 @@ class Simulation:
         self.n_occ = [occupied_sites(r) for r in self.replicas]
         self.spins = [[torch.zeros(n, dtype=self.dtype, device=self.device) for _ in range(3)]
                       for n in self.sites]
-        nbytes = required_scratch(self.replicas)
+        # the default tile's work list, or 4 MiB, whichever is larger: room
+        # for the autotuner's smaller tiles on small lattices
+        nbytes = max(required_scratch(self.replicas), 4 << 20)
         if scratch is None:
             scratch = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.scratch = scratch

@@ -595,7 +595,9 @@ def test_abi_errors(M):
     with pytest.raises(M.MCError) as ei:
         M.Simulation([M.Replica(L=(8, 8, 8))], scratch=small)
     assert ei.value.status == -3
-    sim = M.Simulation([M.Replica(L=(8, 8, 8))])
+    exact = M.required_scratch([M.Replica(L=(8, 8, 8))])
+    sim = M.Simulation([M.Replica(L=(8, 8, 8))],
+                       scratch=torch.empty(exact, dtype=torch.uint8, device="cuda"))
     with pytest.raises(M.MCError) as ei:
         sim.observables()
     assert ei.value.status == -5
