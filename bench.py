@@ -590,6 +590,40 @@ def run_block(M, W):
     return res
 
 
+SCAN_TILES = tuple([(4, 128, 2, z) for z in (1, 2, 3, 5, 7, 13)] +
+                   [(5, 256, 2, z) for z in (1, 2, 3, 5, 7, 13)] +
+                   [(4, 128, 1, 7), (4, 128, 4, 7), (5, 256, 4, 7), (2, 256, 2, 7), (1, 256, 2, 7),
+                    (8, 256, 2, 14), (0, 32, 8, 4)] +
+                   [(9, 1024, 6, 16), (9, 1024, 6, 32), (9, 512, 8, 16), (9, 256, 4, 16),
+                    (9, 256, 2, 16)])
+
+
+def run_tiles(M, W, sweeps=60):
+    """Every kernel on the headline lattice (sc 464^3, FP32, measured sweeps):
+    pass time (per launch: a colour pass, or the fused kernel's whole sweep)
+    and updates/ns per tile shape, the z-chunk depth scanned for the two
+    register kernels."""
+    import torch
+
+    w = W.C5_SC464_ROOFLINE
+    rep = M.Replica(**W.replica_fields(w))
+    sim = M.Simulation([rep], precision="f32", seed=w["seed"],
+                       scratch=torch.empty(256 << 20, dtype=torch.uint8, device="cuda"))
+    sim.enable_fused()
+    n = sim.n_occ[0]
+    res = {"workload": w["name"] + "-tile-scan", "sweeps": sweeps, "tiles": []}
+    for t in SCAN_TILES:
+        sim.set_tile(t[1], t[2], t[3], kernel=t[0])
+        sim.sweep(3, measure=True)
+        launch_ms, total_ms = sim.sweep_timed(sweeps, measure=True)
+        row = {"tile": list(t), "kernel": KERNEL_NAMES[t[0]], "launch_ms": launch_ms,
+               "updates_per_ns": n * sweeps / (total_ms * 1e6), "items": sim.get_tile()[4]}
+        res["tiles"].append(row)
+        log(f"[bench] tiles {t}: launch {launch_ms * 1e3:.1f} us, {row['updates_per_ns']:.1f} updates/ns")
+    sim.close()
+    return res
+
+
 SHAPES = ((464, 464, 464), (448, 464, 480), (512, 464, 420), (480, 464, 448), (464, 512, 420),
           (464, 448, 480), (512, 512, 512))
 
@@ -730,7 +764,7 @@ def main():
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--workload", default="c5",
                     choices=["c5", "c1", "c2", "c3", "c4", "f1", "big", "bcc", "fcc", "exchange",
-                             "block", "shapes"],
+                             "block", "shapes", "tiles"],
                     help="c5 (default): the 10^8-spin headline; others print their own line "
                          "(f1: the paper's M(T) accuracy experiment)")
     ap.add_argument("--f1-sizes", default="128,256,512")
@@ -786,6 +820,8 @@ def main():
             out = run_c3(M, W, W.C3_BATCHED["sweeps"])
         elif args.workload == "shapes":
             out = run_shapes(M)
+        elif args.workload == "tiles":
+            out = run_tiles(M, W)
         else:
             out = run_c4(M, W, 1000)
         print(json.dumps(out), flush=True)
