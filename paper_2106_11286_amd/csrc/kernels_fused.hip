@@ -1,5 +1,7 @@
 // kernels_fused.hip -- the fused simple-cubic sweep (kernel 9) and the swap of
 // the two state buffer sets that follows each of its launches.
+#include <mutex>
+
 #include "launch.hpp"
 #include "sc_fused.hpp"
 
@@ -90,11 +92,25 @@ static hipError_t fused_allow_one(uint32_t bytes)
     return hipSuccess;
 }
 
+// The allowance is per kernel (and device), shared by every handle: it is
+// only ever raised, so a handle with a smaller tile never takes away what
+// another one's launches need.
 hipError_t fused_allow(bool f64, uint32_t bytes)
 {
-    hipError_t e = f64 ? fused_allow_one<double, false>(bytes) : fused_allow_one<float, false>(bytes);
+    static std::mutex mu;
+    static uint32_t allowed[64][2]; // per device and precision
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
-    return f64 ? fused_allow_one<double, true>(bytes) : fused_allow_one<float, true>(bytes);
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    uint32_t &a = allowed[dev][f64 ? 1 : 0];
+    if (bytes <= a) return hipSuccess;
+    e = f64 ? fused_allow_one<double, false>(bytes) : fused_allow_one<float, false>(bytes);
+    if (e == hipSuccess)
+        e = f64 ? fused_allow_one<double, true>(bytes) : fused_allow_one<float, true>(bytes);
+    if (e == hipSuccess) a = bytes;
+    return e;
 }
 
 } // namespace mc

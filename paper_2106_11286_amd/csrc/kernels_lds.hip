@@ -1,5 +1,7 @@
 // kernels_lds.hip -- whole sweeps of small lattices held in one workgroup's
 // LDS.
+#include <mutex>
+
 #include "device_common.hpp"
 
 namespace mc {
@@ -224,9 +226,24 @@ template <typename T> static hipError_t lds_allow_kind(int kind, uint32_t bytes)
     return hipSuccess;
 }
 
+// The allowance is per kernel (and device), shared by every handle: it is
+// only ever raised, so a handle with a smaller lattice never takes away what
+// another one's launches need.
 hipError_t lds_allow(int kind, bool f64, uint32_t bytes)
 {
-    return f64 ? lds_allow_kind<double>(kind, bytes) : lds_allow_kind<float>(kind, bytes);
+    static std::mutex mu;
+    static uint32_t allowed[64][3][2]; // per device, lattice kind and precision
+    if (kind < 0 || kind > 2) return hipErrorInvalidValue;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    uint32_t &a = allowed[dev][kind][f64 ? 1 : 0];
+    if (bytes <= a) return hipSuccess;
+    e = f64 ? lds_allow_kind<double>(kind, bytes) : lds_allow_kind<float>(kind, bytes);
+    if (e == hipSuccess) a = bytes;
+    return e;
 }
 
 } // namespace mc

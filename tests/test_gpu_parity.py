@@ -1366,3 +1366,39 @@ def test_autotune_with_fused_candidates(M):
     for r in range(len(reps)):
         for x, y in zip(natural(a, r), natural(b, r)):
             assert np.array_equal(x, y), (r, tile)
+
+
+def test_lds_allowance_shared_by_handles(M):
+    """The dynamic-LDS allowance of a kernel is shared by every handle: a
+    second handle with a smaller need must not take away what the first
+    handle's launches use (fused sweep kernel and whole-sweep LDS kernel)."""
+    import torch
+
+    big = [M.Replica(kind="sc", L=(64, 24, 16), K=0.1, T=1.2)]
+    small = [M.Replica(kind="sc", L=(16, 8, 8), K=0.1, T=1.2)]
+    a = M.Simulation(big, precision="f64", seed=3,
+                     scratch=torch.empty(8 << 20, dtype=torch.uint8, device="cuda"))
+    a.enable_fused()
+    a.set_tile(512, 10, 4, kernel=9)      # 6 * 12 * 32 * 8 = 18 KiB of LDS
+    b = M.Simulation(small, precision="f64", seed=3)
+    b.enable_fused()
+    b.set_tile(256, 1, 4, kernel=9)       # less
+    a.sweep(2)
+    b.sweep(2)
+    ref = M.Simulation(big, precision="f64", seed=3)
+    ref.set_tile(16, 16, 2, kernel=0)
+    ref.sweep(2)
+    for x, y in zip(natural(a), natural(ref)):
+        assert np.array_equal(x, y)
+    # whole-sweep LDS kernel: a larger lattice first, then a smaller one
+    c = M.Simulation([M.Replica(kind="sc", L=(16, 16, 16), K=0.1, T=1.2)], precision="f64", seed=4)
+    d = M.Simulation([M.Replica(kind="sc", L=(8, 8, 8), K=0.1, T=1.2)], precision="f64", seed=4)
+    assert c.get_tile()[0] == 3 and d.get_tile()[0] == 3
+    c.sweep(3)
+    d.sweep(3)
+    c.sweep(1)
+    e = M.Simulation([M.Replica(kind="sc", L=(16, 16, 16), K=0.1, T=1.2)], precision="f64", seed=4)
+    e.set_tile(16, 16, 2, kernel=0)
+    e.sweep(4)
+    for x, y in zip(natural(c), natural(e)):
+        assert np.array_equal(x, y)
