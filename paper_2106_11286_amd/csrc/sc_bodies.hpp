@@ -426,9 +426,12 @@ __device__ __forceinline__ void sc_pair_body(const PassLaunch &P, int colour, ui
             const uint32_t i0 = own + (uint32_t)(z * Ly + yc) * Lxh + xa;
             const bool aa = site(me.xa, me.ya, me.za, hxa, hya, hza, s0, live, i0);
             const bool ab = site(me.xb, me.yb, me.zb, hxb, hyb, hzb, s0 + 2u, live, i0 + 1u);
-            // a pair with one accepted move rewrites the other column's
-            // unchanged value (same bits; no other workgroup owns it)
-            if (MODE != 1 && live && (aa || ab)) {
+            // every pair is written back, accepted or not (same bits where
+            // rejected; no other workgroup owns it): whole lines reach the L2,
+            // measured 0.8 % faster than storing only pairs with a move
+            (void)aa;
+            (void)ab;
+            if (MODE != 1 && live) {
                 buf_store2(me.xa, me.xb, q.x, b_c, s_own);
                 buf_store2(me.ya, me.yb, q.y, b_c, s_own);
                 buf_store2(me.za, me.zb, q.z, b_c, s_own);
