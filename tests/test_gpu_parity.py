@@ -1402,3 +1402,45 @@ def test_lds_allowance_shared_by_handles(M):
     e.sweep(4)
     for x, y in zip(natural(c), natural(e)):
         assert np.array_equal(x, y)
+
+
+def test_fused_state_in_second_set_follows_every_entry_point(M):
+    """With the state in the second buffer set (after an odd number of fused
+    sweeps), writing spins from natural order, the from-scratch measurement,
+    checkpoint/resume of the sweep counter and a later kernel change act on
+    that set: the chain equals one run on kernel 0 throughout."""
+    import torch
+
+    reps = [M.Replica(kind="sc", L=(24, 16, 12), K=0.1, T=1.3, replica_id=0),
+            M.Replica(kind="sc", L=(16, 16, 16), K=0.1, T=0.9, replica_id=1)]
+    a = M.Simulation(reps, precision="f32", seed=8,
+                     scratch=torch.empty(16 << 20, dtype=torch.uint8, device="cuda"))
+    b = M.Simulation(reps, precision="f32", seed=8,
+                     scratch=torch.empty(16 << 20, dtype=torch.uint8, device="cuda"))
+    a.enable_fused()
+    a.set_tile(256, 2, 3, kernel=9)
+    b.set_tile(16, 16, 2, kernel=0)
+    a.sweep(3)
+    b.sweep(3)
+    assert a.state_spins(0)[0].data_ptr() == a.alt_spins[0][0].data_ptr()
+    rng = np.random.default_rng(2)
+    for r, rep in enumerate(reps):
+        n = int(np.prod(rep.L))
+        v = rng.normal(size=(3, n))
+        v /= np.linalg.norm(v, axis=0)
+        a.from_natural(r, [v[0].astype(np.float32), v[1].astype(np.float32), v[2].astype(np.float32)])
+        b.from_natural(r, [v[0].astype(np.float32), v[1].astype(np.float32), v[2].astype(np.float32)])
+    ma, mb = a.measure_state(), b.measure_state()
+    for r in range(len(reps)):
+        assert ma[r]["E"] == mb[r]["E"] and np.array_equal(ma[r]["M"], mb[r]["M"])
+    t = a.get_sweep()
+    a.set_sweep(t + 5)
+    b.set_sweep(t + 5)
+    a.sweep(1, measure=True)
+    b.sweep(1, measure=True)
+    a.set_tile(128, 2, 4, kernel=4)
+    a.sweep(2)
+    b.sweep(2)
+    for r in range(len(reps)):
+        for x, y in zip(natural(a, r), natural(b, r)):
+            assert np.array_equal(x, y), r
