@@ -534,15 +534,18 @@ class Simulation:
     def enable_fused(self):
         """Allocate every replica's second spin buffer set and hand it to the
         library (``mc_set_second_buffers``), so the fused sweep kernel (9) can
-        be chosen; it writes each sweep's new state into the other set."""
-        if getattr(self, "alt_spins", None) is None:
-            self.alt_spins = [[torch.zeros(n, dtype=self.dtype, device=self.device)
-                               for _ in range(3)] for n in self.sites]
+        be chosen; it writes each sweep's new state into the other set.
+        Calling it again does nothing."""
+        if getattr(self, "alt_spins", None) is not None:
+            return
+        alt = [[torch.zeros(n, dtype=self.dtype, device=self.device) for _ in range(3)]
+               for n in self.sites]
         bufs = (SpinBuffers * self.n_reps)()
-        for i, (pl, n) in enumerate(zip(self.alt_spins, self.sites)):
+        for i, (pl, n) in enumerate(zip(alt, self.sites)):
             bufs[i].sx, bufs[i].sy, bufs[i].sz = pl[0].data_ptr(), pl[1].data_ptr(), pl[2].data_ptr()
             bufs[i].capacity_sites = n
         _check("mc_set_second_buffers", LIB.mc_set_second_buffers(self.handle, bufs))
+        self.alt_spins = alt
 
     def state_spins(self, r: int = 0):
         """The three component tensors that hold replica r's current state
