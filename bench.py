@@ -408,6 +408,17 @@ def run_c3(M, W, sweeps):
                            "launch": sim.tuned_launch()}
     log(f"[bench] c3 tuned_launch: {res['tuned_launch']['updates_per_ns']:.1f} updates/ns, "
         f"tile {tile}, {sim.tuned_launch()}")
+    # persistent launches (per-XCD queues) on larger work units: the
+    # per-unit claim, poll and count weigh less, the phases balance worse
+    sim.set_persistent_mode("xcd")
+    res["persistent_unit_scan"] = []
+    for t in ((5, 256, 2, 7), (5, 256, 2, 14), (5, 256, 2, 28), (5, 256, 2, 48), (2, 256, 2, 14)):
+        sim.set_tile(t[1], t[2], t[3], kernel=t[0])
+        sim.sweep(20, measure=True, persistent=True)
+        n_sw = min(sweeps, 1000)
+        _, dt = _timed(lambda: sim.sweep(n_sw, measure=True, persistent=True))
+        res["persistent_unit_scan"].append({"tile": list(t), "updates_per_ns": N * n_sw / dt / 1e9})
+        log(f"[bench] c3 persistent {t}: {N * n_sw / dt / 1e9:.1f} updates/ns")
     return res
 
 
