@@ -37,8 +37,17 @@ template <typename T> __device__ __forceinline__ gptr<T> as_global(void *p)
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds, each with two
 // 32x32 -> 64-bit products (one v_mad_u64_u32 each); the high halves are mixed
 // with the other counter words and the key, which is bumped by the Weyl
-// increments between rounds.
+// increments between rounds.  A three-way XOR of varying words is one CDNA4
+// v_bitop3_b32 (truth table 0x96), which the compiler does not form from two
+// XORs itself.  Plain XORs stay where the words can be uniform (the replica
+// and sweep words of a colour pass's counter, and what the first round makes
+// of them), so that their part runs in scalar instructions.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 struct Words {
     uint32_t w0, w1, w2, w3;
 };
@@ -56,8 +65,8 @@ __device__ __forceinline__ Words philox10(uint32_t c0, uint32_t c1, uint32_t c2,
     for (int r = 0; r < 10; ++r) {
         const uint64_t pa = (uint64_t)kMulA * c0;
         const uint64_t pb = (uint64_t)kMulB * c2;
-        const uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = r <= 1 ? (uint32_t)(pb >> 32) ^ c1 ^ k0 : xor3((uint32_t)(pb >> 32), c1, k0);
+        const uint32_t n2 = r <= 2 ? (uint32_t)(pa >> 32) ^ c3 ^ k1 : xor3((uint32_t)(pa >> 32), c3, k1);
         c0 = n0;
         c1 = (uint32_t)pb;
         c2 = n2;
@@ -213,7 +222,9 @@ __device__ __forceinline__ bool metropolis_words(const Words &w, T &sx, T &sy, T
     const T po = sx * ex + sy * ey + sz * ez;
     // Eq. (1): dH = -h.(S'-S) - K[(S'.e)^2 - (S.e)^2]
     dH = -(hx * dx + hy * dy + hz * dz) - K * ((pn - po) * (pn + po));
-    const bool acc = (dH <= T(0)) || (!greedy && P <= fast_exp(-beta * dH));
+    // Non-short-circuit: both comparisons stay lane masks, combined with the
+    // uniform greedy flag by scalar mask operations.
+    const bool acc = (dH <= T(0)) | ((P <= fast_exp(-beta * dH)) & !greedy);
     if (acc) {
         const T inv = inv_norm(nx * nx + ny * ny + nz * nz);
         sx = nx * inv;
