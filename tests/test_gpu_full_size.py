@@ -303,5 +303,8 @@ def test_full_size_sc464_fused(M, prec):
                        scratch=torch.empty(64 << 20, dtype=torch.uint8, device="cuda"))
     ref.set_tile(256, 2, 7, kernel=5)
     ref.sweep(4)
-    for a, b in zip(got, natural(ref)):
-        assert np.array_equal(a, b)
+    for comp, (a, b) in enumerate(zip(got, natural(ref))):
+        bad = np.nonzero(a != b)[0]
+        # on a mismatch, name the sites (x, y, z of the natural index) for diagnosis
+        assert bad.size == 0, (comp, bad.size, [(int(i % 464), int(i // 464 % 464), int(i // 464**2))
+                                                for i in bad[:8]])
