@@ -15,7 +15,7 @@ using namespace mcabi;
 namespace {
 
 // Candidate shapes for the autotuner: each kernel family with a few tile
-// widths, rows per thread and plane chunks aimed at 2k .. 16k workgroups.
+// widths, rows per thread and plane chunks aimed at 2k .. 24k workgroups.
 std::vector<Tile> tile_candidates(const mc_sim *h)
 {
     int W = 1, Ly = 1;
@@ -85,7 +85,7 @@ std::vector<Tile> tile_candidates(const mc_sim *h)
             planes = std::max(planes, d.Lz);
         }
         int last = -1;
-        for (uint64_t target : {2048ull, 4096ull, 8192ull, 16384ull}) {
+        for (uint64_t target : {2048ull, 4096ull, 8192ull, 16384ull, 24576ull}) {
             const int zc = (int)std::max<uint64_t>(1, std::min<uint64_t>((cols + target - 1) / target, planes));
             if (zc == last) continue;
             last = zc;
