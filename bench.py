@@ -601,9 +601,10 @@ def run_block(M, W):
     return res
 
 
-SCAN_TILES = tuple([(4, 128, 2, z) for z in (1, 2, 3, 5, 7, 13)] +
+SCAN_TILES = tuple([(4, 128, 2, z) for z in (1, 2, 3, 4, 5, 6, 7, 9, 13)] +
                    [(5, 256, 2, z) for z in (1, 2, 3, 5, 7, 13)] +
-                   [(4, 128, 1, 7), (4, 128, 4, 7), (5, 256, 4, 7), (2, 256, 2, 7), (1, 256, 2, 7),
+                   [(4, 64, 2, 5), (4, 128, 1, 7), (4, 128, 4, 7), (5, 256, 4, 7), (2, 256, 2, 7),
+                    (1, 256, 2, 7),
                     (8, 256, 2, 14), (0, 32, 8, 4)] +
                    [(9, 1024, 6, 16), (9, 1024, 6, 32), (9, 512, 8, 16), (9, 256, 4, 16),
                     (9, 256, 2, 16)])
@@ -622,6 +623,7 @@ def run_tiles(M, W, sweeps=60):
                        scratch=torch.empty(256 << 20, dtype=torch.uint8, device="cuda"))
     sim.enable_fused()
     n = sim.n_occ[0]
+    sim.sweep(20, measure=True)  # the device's first sweeps run slower
     res = {"workload": w["name"] + "-tile-scan", "sweeps": sweeps, "tiles": []}
     for t in SCAN_TILES:
         sim.set_tile(t[1], t[2], t[3], kernel=t[0])
