@@ -73,7 +73,10 @@ def time_precision(M, W, prec, steps, warmup, tile=None):
     n = sim.n_occ[0]
     if tile is None:
         # kernel / tile shape chosen by the library's autotuner (its trial
-        # sweeps are ordinary sweeps of the chain and count as warm-up)
+        # sweeps are ordinary sweeps of the chain and count as warm-up); the
+        # device's first ~60 sweeps run up to 5 % slower, so they go first,
+        # lest the candidates timed early look slower than they are
+        sim.sweep(60, measure=True)
         tile = sim.autotune(trial_sweeps=6, measure=True)
         how = "autotuned"
     else:
